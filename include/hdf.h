@@ -1,0 +1,182 @@
+/*
+ * hdf.h -- C ABI of the MI355X (gfx950) Harmonic Decomposition Factorization.
+ *
+ * The library builds, for an isotropic kernel k(||x_i - x_j||; l) on N points
+ * in R^d (d >= 3), a low-rank factor K ~ U D U^T whose rank is chosen from an
+ * error tolerance, not given by the caller (Ryan & Damle, "Linear Time Kernel
+ * Matrix Approximation via Hyperspherical Harmonics", ICML 2022: abstract,
+ * Sec. 3.2, Algorithm 1, and Remark 1 for the symmetric X = Y case with the
+ * diagonal eigenvalue matrix D).  It then applies the factor (Sec. 3.6,
+ * O(N r) matvec) and differentiates w^T K v with respect to the lengthscale
+ * and the points (not in the paper).
+ *
+ * Conventions shared by every entry point:
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  Ownership stays with the caller
+ *     unless stated.
+ *   - Dense arrays are row-major with an explicit leading dimension (in
+ *     elements): element (i, j) of an n x m array A with leading dimension
+ *     lda is A[i * lda + j], lda >= m.
+ *   - dtype 0 = float32, 1 = float64.  Precision HDF_MIXED requires float32
+ *     points / vectors, HDF_FP64 requires float64.
+ *   - All device work is enqueued on the caller's HIP stream (NULL = the
+ *     default stream).  A handle must not be used concurrently from two
+ *     streams or threads.
+ *   - On error an entry point returns a negative hdf_status, writes no
+ *     output, and leaves a human-readable reason in hdf_last_error()
+ *     (thread-local).  Argument errors are detected on the host before any
+ *     device work.
+ */
+#ifndef HDF_H
+#define HDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdf_factor* hdf_handle;      /* opaque, owned by the library */
+
+/* Kernels of Sec. 4.1 (Fig. 3 paragraph).  The Gaussian uses the lengthscale
+ * convention exp(-r^2 / (2 l^2)) (the paper writes exp(-(r/sigma)^2)). */
+typedef enum {
+  HDF_GAUSSIAN = 0,   /* exp(-r^2/(2 l^2))                       */
+  HDF_CAUCHY   = 1,   /* 1 / (1 + r^2/l^2)                       */
+  HDF_MATERN32 = 2,   /* (1 + z) e^-z,         z = sqrt(3) r / l */
+  HDF_MATERN52 = 3    /* (1 + z + z^2/3) e^-z, z = sqrt(5) r / l */
+} hdf_kernel;
+
+typedef enum {
+  HDF_FP64  = 0,      /* every device step in binary64                        */
+  HDF_MIXED = 1       /* binary32 factor, harmonics and MFMA contractions;
+                         binary64 geometry, reductions and compression        */
+} hdf_precision;
+
+typedef enum {
+  HDF_OK           =  0,
+  HDF_E_ARG        = -1,  /* invalid argument (NULL, size, dtype/precision)  */
+  HDF_E_DIM        = -2,  /* d < 3 or d > HDF_MAX_DIM                         */
+  HDF_E_NONFINITE  = -3,  /* a point coordinate is NaN or infinite           */
+  HDF_E_INFEASIBLE = -4,  /* degree above HDF_MAX_DEGREE, or the factor would
+                             exceed the memory budget (see hdf_build)        */
+  HDF_E_OOM        = -5,  /* device allocation failed                        */
+  HDF_E_HIP        = -6   /* a HIP runtime call failed                       */
+} hdf_status;
+
+#define HDF_MAX_DIM     8
+#define HDF_MAX_DEGREE  60   /* largest Chebyshev degree p accepted */
+#define HDF_MAX_RHS     256  /* largest number of right-hand sides per call */
+
+/* Summary of a built factor (hdf_info).  Sizes follow Sec. 3.6: H harmonics
+ * of the kept degrees, S = sum_k s_k radial functions, rank r = sum_k
+ * |H_k| s_k. */
+typedef struct {
+  int32_t  n_dim;          /* d                                            */
+  int32_t  precision;      /* hdf_precision                                */
+  int64_t  n_points;       /* N                                            */
+  int32_t  degree_p;       /* Chebyshev degree p (even)                    */
+  int32_t  n_degrees;      /* p/2 + 1 harmonic degrees k = 0..p/2          */
+  int64_t  n_harmonics;    /* H, harmonics of kept degrees (s_k > 0)       */
+  int64_t  n_radial;       /* S = sum_k s_k                                */
+  int64_t  rank;           /* r = sum_k |H_k| s_k                          */
+  double   tau;            /* eigenvalue threshold (Sec. 3.5)              */
+  double   nu;             /* estimate of ||K||_F / N                      */
+  double   cheb_tail;      /* sum_{i>p} |a_i|                              */
+  double   center_radius;  /* R = max_i ||x_i - c||                        */
+  double   rho2_min, rho2_max;  /* interval of the radial basis           */
+  int64_t  factor_bytes;   /* device bytes of the stored factor            */
+  double   t_prep_ms, t_plan_ms, t_gram_ms, t_compress_ms, t_build_ms;
+  int32_t  s_k[HDF_MAX_DEGREE / 2 + 1];   /* kept radial rank per degree   */
+} hdf_info_t;
+
+/* Build the factor (Algorithm 1, symmetric case, Remark 1).
+ *   points  device, n x d, leading dimension ld (>= d), dtype 0/1.
+ *   kernel, lengthscale (> 0), tol in (0, 1): target relative Frobenius
+ *           error ||K - U D U^T||_F <= tol ||K||_F (Sec. 3.5 bound, restated
+ *           in Frobenius form).
+ *   prec    HDF_MIXED (dtype must be 0) or HDF_FP64 (dtype must be 1).
+ *   out     receives the handle; untouched on error.
+ * The handle keeps its own copy of the points.  Two blocking device-to-host
+ * synchronisations happen on `hip_stream` (after the geometry pass and after
+ * the radial Gram pass) because the degree and the ranks depend on the data.
+ * HDF_E_INFEASIBLE when p > HDF_MAX_DEGREE or the factor would need more than
+ * max(1 GiB, 60% of the free device memory). */
+hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld,
+                     hdf_kernel kernel, double lengthscale, double tol,
+                     hdf_precision prec, void* hip_stream, hdf_handle* out);
+
+/* KV = U D U^T V (Sec. 3.6, two passes over the factor, no host sync).
+ *   V   device, n x m (ldv >= m), KV device, n x m (ldkv >= m); same dtype as
+ *       the points; 1 <= m <= HDF_MAX_RHS.  V and KV must not overlap. */
+hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv,
+                      void* KV, int64_t ldkv, void* hip_stream);
+
+/* Adjoint of F = sum_c w_c^T (U D U^T) v_c with the structure frozen at the
+ * build (centre, radius, degree, radial basis and coefficients, ranks).
+ *   Wm, Vm   device, n x m each with leading dimension ld (>= m).
+ *   dlength  host, receives dF/dl (NULL: not computed).
+ *   dX       device, n x d with leading dimension lddx (>= d), receives dF/dX
+ *            (NULL: not computed); same dtype as the points.
+ * One blocking synchronisation when dlength != NULL. */
+hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
+                        double* dlength, void* dX, int64_t lddx, void* hip_stream);
+
+/* Fill `info` (host) from the handle. */
+hdf_status hdf_info(hdf_handle h, hdf_info_t* info);
+
+/* Copy host-side parts of the factor.  Any pointer may be NULL.
+ *   index_table  int32, H x (d-1): (k, mu_1, ..., mu_{d-2}) per kept harmonic
+ *                in the enumeration order (k ascending, then lexicographic).
+ *   lambda       float64, S: eigenvalues, degree-major (k ascending, l).
+ *   radial_coef  float64, sum_k L_k s_k: E_k column-major per degree
+ *                (coefficient a of radial function l at [offset + l*L_k + a]).
+ *   a_cheb       float64, p+1 Chebyshev coefficients used. */
+hdf_status hdf_get_plan(hdf_handle h, int32_t* index_table, double* lambda,
+                        double* radial_coef, double* a_cheb);
+
+/* Copy the stored factor into caller buffers (device to device, enqueued on
+ * hip_stream).  phi_out: H x n (harmonic-major, leading dimension ld_phi >= n),
+ * q_out: S x n (radial functions, leading dimension ld_q >= n); element type
+ * = float32 for HDF_MIXED, float64 for HDF_FP64.  Either may be NULL.
+ * Column (k,h,l) of U is phi[row of h] * q[row of (k,l)] elementwise
+ * (Algorithm 1: Xbar^(k)[:, l] times the harmonic). */
+hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_out, int64_t ld_q,
+                           void* hip_stream);
+
+void        hdf_free(hdf_handle h);
+const char* hdf_status_string(hdf_status s);
+const char* hdf_last_error(void);
+
+/* ---- Host-only planner entry points (no device work; usable without a GPU).
+ * They expose the data-free steps of the build so they can be checked on the
+ * host. ---- */
+
+/* Chebyshev coefficients of f(s) = k(D |s|; l) on [-1, 1] (Sec. 3.3,
+ * Eq. chebtrunc) from the DCT at n_nodes first-kind nodes (n_nodes a power of
+ * two, >= 16); odd coefficients are exactly zero.  derivative != 0 gives the
+ * coefficients of d f / d l instead.  a: host, n_nodes doubles. */
+hdf_status hdf_plan_chebyshev(hdf_kernel kernel, double D, double lengthscale,
+                              int n_nodes, int derivative, double* a);
+
+/* Smallest even p <= p_max with sum_{i>p} |a_i| <= eps * nu / 2 (the degree
+ * rule standing in for ChebDegreeNeeded, Algorithm 1 / Remark 3).  Writes
+ * p and the tail; HDF_E_INFEASIBLE if none. */
+hdf_status hdf_plan_degree(const double* a, int n, double eps, double nu, int p_max,
+                           int* p, double* tail);
+
+/* Radial cores M_k, k = 0..p/2, of the degree-p expansion (Eq. preharm,
+ * Eq. preeigen, with Z_k folded in) in the basis T_a(t),
+ * t = (2 rho^2 - u0 - u1) / (u1 - u0): kernel(x, y) ~ sum_k sum_h
+ * S_k^h(xt) S_k^h(yt) sum_{a,b} M_k[a,b] T_a(t_x) T_b(t_y).  cores: host,
+ * sum_k L_k^2 doubles, L_k = p/2 - k + 1, each core row-major, k ascending. */
+hdf_status hdf_plan_cores(const double* a, int p, int d, double u0, double u1, double* cores);
+
+/* Index set H_k (Sec. 3.3) in the enumeration order: count = |H_k|
+ * (App. B); table (may be NULL) receives count x (d-2) int32. */
+hdf_status hdf_plan_index_set(int d, int k, int32_t* table, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDF_H */

@@ -1,0 +1,579 @@
+// C ABI of the HDF library: argument checks, the build pipeline (device
+// geometry -> host planner -> device radial Gram -> host compression ->
+// device factor evaluation) and the matvec / adjoint drivers.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hdf.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+hdf_status fail(hdf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+    if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
+    else p = nullptr;
+    return e;
+  }
+};
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+struct hdf_factor {
+  int d = 0, prec = 0, dtype = 0, kernel = 0;
+  int64_t N = 0, ldN = 0;
+  double l = 0, tol = 0;
+  hdf::GeoDev geo{};
+  double u0 = 0, u1 = 1, nu = 0, tail = 0, tau = 0;
+  int p = 0, K = 0;
+  std::vector<double> a;                          // p+1 coefficients
+  std::vector<std::vector<double>> cores;
+  std::vector<hdf::DegreeFactor> deg;             // k = 0..K
+  std::vector<hdf::DegDev> degs;                  // kept degrees
+  std::vector<int> kept_k;
+  std::vector<int32_t> index_table;               // H x (d-1)
+  int64_t H = 0, S = 0, r = 0;
+  int max_s = 0;
+  double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_build = -1;
+  hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
+  // device storage
+  DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
+      lam_row, moments;
+  int n_tiles = 0;
+  // matvec workspace
+  DevBuf ws_part, ws_W, ws_Wd;
+  ~hdf_factor() {
+    if (ev_b0) hipEventDestroy(ev_b0);
+    if (ev_b1) hipEventDestroy(ev_b1);
+  }
+  size_t elem() const { return prec == HDF_MIXED ? 4 : 8; }
+};
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? HDF_E_OOM : HDF_E_HIP,                   \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+namespace {
+
+// Loop order of the factor-evaluation kernel: azimuthal index outermost (|m|
+// ascending, +m then -m), then the chain levels from d-2 down to 1; each
+// innermost iteration is one harmonic.  Returns its canonical row or -1 for a
+// dropped degree.
+void loop_order_columns(int d, int K, const std::map<std::vector<int>, int>& canon,
+                        std::vector<int32_t>& col_of) {
+  col_of.clear();
+  std::vector<int> path;   // upper indices from level d-2 down to level 1
+  std::function<void(int, int, int)> rec = [&](int level, int b, int msigned) {
+    for (int nn = 0; nn <= K - b; ++nn) {
+      const int a = b + nn;
+      path.push_back(a);
+      if (level == 1) {
+        // path = [mu_{d-3}, ..., mu_1, k] (for d = 3: [k])
+        std::vector<int> key;
+        key.push_back(path.back());                       // k
+        for (int j = (int)path.size() - 2; j >= 0; --j) key.push_back(path[j]);   // mu_1..mu_{d-3}
+        key.push_back(msigned);
+        auto it = canon.find(key);
+        col_of.push_back(it == canon.end() ? -1 : it->second);
+      } else {
+        rec(level - 1, a, msigned);
+      }
+      path.pop_back();
+    }
+  };
+  for (int mm = 0; mm <= K; ++mm) {
+    rec(d - 2, mm, mm);
+    if (mm > 0) rec(d - 2, mm, -mm);
+  }
+}
+
+
+}  // namespace
+
+extern "C" {
+
+const char* hdf_status_string(hdf_status s) {
+  switch (s) {
+    case HDF_OK: return "ok";
+    case HDF_E_ARG: return "invalid argument";
+    case HDF_E_DIM: return "dimension not supported (need 3 <= d <= 8)";
+    case HDF_E_NONFINITE: return "non-finite point coordinate";
+    case HDF_E_INFEASIBLE: return "infeasible: degree or factor size above the limits";
+    case HDF_E_OOM: return "device out of memory";
+    case HDF_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* hdf_last_error(void) { return g_err.c_str(); }
+
+void hdf_free(hdf_handle h) { delete h; }
+
+// ------------------------------------------------------------------ build
+hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld,
+                     hdf_kernel kernel, double lengthscale, double tol, hdf_precision prec,
+                     void* hip_stream, hdf_handle* out) {
+  g_err.clear();
+  if (!out) return fail(HDF_E_ARG, "out is NULL");
+  if (!points) return fail(HDF_E_ARG, "points is NULL");
+  if (d < 3 || d > HDF_MAX_DIM) return fail(HDF_E_DIM, "d must be in [3, 8]");
+  if (n < 1) return fail(HDF_E_ARG, "n must be >= 1");
+  if (ld < d) return fail(HDF_E_ARG, "ld must be >= d");
+  if (dtype != 0 && dtype != 1) return fail(HDF_E_ARG, "dtype must be 0 (f32) or 1 (f64)");
+  if (prec != HDF_FP64 && prec != HDF_MIXED) return fail(HDF_E_ARG, "unknown precision");
+  if ((prec == HDF_MIXED) != (dtype == 0))
+    return fail(HDF_E_ARG, "HDF_MIXED needs float32 points, HDF_FP64 needs float64 points");
+  if ((int)kernel < 0 || (int)kernel > 3) return fail(HDF_E_ARG, "unknown kernel");
+  if (!(lengthscale > 0) || !std::isfinite(lengthscale)) return fail(HDF_E_ARG, "lengthscale must be > 0");
+  if (!(tol > 0 && tol < 1)) return fail(HDF_E_ARG, "tol must be in (0, 1)");
+  hipStream_t s = (hipStream_t)hip_stream;
+
+  std::unique_ptr<hdf_factor> f(new hdf_factor());
+  f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
+  f->N = n; f->l = lengthscale; f->tol = tol;
+  f->ldN = (n + 63) / 64 * 64;
+  const size_t in_elem = dtype == 0 ? 4 : 8;
+
+  // 1. geometry on the device, one sync
+  double t0 = now_ms();
+  HIPCHK(f->x_soa.ensure((size_t)d * f->ldN * in_elem));
+  HIPCHK(f->geo_dev.ensure(sizeof(hdf::GeoDev)));
+  HIPCHK(f->part.ensure((size_t)hdf::kPrepBlocks * 32 * sizeof(double)));
+  HIPCHK(hdf::launch_prep(points, dtype, n, d, ld, f->x_soa.p, f->ldN, kernel, lengthscale,
+                          (double*)f->part.p, (hdf::GeoDev*)f->geo_dev.p, s));
+  HIPCHK(hipMemcpyAsync(&f->geo, f->geo_dev.p, sizeof(hdf::GeoDev), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  f->t_prep = now_ms() - t0;
+  if (f->geo.nonfinite > 0) return fail(HDF_E_NONFINITE, "points contain NaN or Inf");
+
+  // 2. host planner
+  t0 = now_ms();
+  f->nu = std::sqrt(f->geo.nu2_sum / (double)hdf::kNuPairs);
+  const double D = 2.0 * f->geo.R;
+  std::vector<double> afull(hdf::kChebNodes);
+  hdf::chebyshev_coeffs(kernel, D, lengthscale, hdf::kChebNodes, false, afull.data());
+  f->p = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, HDF_MAX_DEGREE, &f->tail);
+  if (f->p < 0) {
+    int pp = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, hdf::kChebNodes - 2, nullptr);
+    char buf[160];
+    snprintf(buf, sizeof buf, "Chebyshev degree %d needed (> %d): diameter/lengthscale too large for tol",
+             pp, HDF_MAX_DEGREE);
+    return fail(HDF_E_INFEASIBLE, buf);
+  }
+  f->K = f->p / 2;
+  f->a.assign(afull.begin(), afull.begin() + f->p + 1);
+  hdf::radial_interval(f->geo.rho2_min, f->geo.rho2_max, &f->u0, &f->u1);
+  hdf::radial_cores(f->a.data(), f->p, d, f->u0, f->u1, f->cores);
+  f->tau = hdf::tau_threshold(tol, f->nu, n, d, f->p);
+  f->t_plan = now_ms() - t0;
+
+  // 3. radial Gram moments on the device, second sync
+  t0 = now_ms();
+  const int K = f->K;
+  const int nrt = (K + 1 + 15) / 16, nct = (2 * K + 1 + 15) / 16;
+  // Mixed precision uses the split (hi/lo) product on every tolerance: the
+  // radial Gram can be ill-conditioned (cond ~1e6 measured on uniform-cube
+  // data), and a plain binary32 Gram then forces a null-space cut that drops
+  // directions the tolerance needs.  Its cost is negligible.
+  const int gram_mode = (prec == HDF_FP64) ? 0 : 2;
+  const int gb = hdf::gram_blocks(n);
+  HIPCHK(f->part.ensure((size_t)gb * nrt * 16 * nct * 16 * sizeof(double) + 4096));
+  HIPCHK(f->moments.ensure((size_t)nrt * 16 * nct * 16 * sizeof(double)));
+  HIPCHK(hdf::launch_gram(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p,
+                          f->u0, f->u1, K, gram_mode, (double*)f->part.p, (double*)f->moments.p, s));
+  const int mcols = nct * 16;
+  std::vector<double> mom((size_t)nrt * 16 * mcols);
+  HIPCHK(hipMemcpyAsync(mom.data(), f->moments.p, mom.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  f->t_gram = now_ms() - t0;
+
+  // 4. compression per degree, two passes (CholeskyQR2-style): precondition
+  // with the first Gram, recompute the Gram of the preconditioned radial
+  // columns on the device in binary64 (third sync), compress on the host.
+  t0 = now_ms();
+  const double floor_rel = (gram_mode == 0) ? 1e-15 : 1e-10;
+  std::vector<hdf::Precond> pcs(K + 1);
+  std::vector<double> t1_all;
+  std::vector<int32_t> t1_off(K + 1);
+  for (int k = 0; k <= K; ++k) {
+    const int L = K - k + 1;
+    std::vector<double> G((size_t)L * L);
+    for (int aa = 0; aa < L; ++aa)
+      for (int bb = 0; bb < L; ++bb)
+        G[(size_t)aa * L + bb] = 0.5 * (mom[(size_t)k * mcols + aa + bb] + mom[(size_t)k * mcols + std::abs(aa - bb)]);
+    hdf::gram_precondition(L, G.data(), floor_rel, pcs[k]);
+    t1_off[k] = (int32_t)t1_all.size();
+    t1_all.insert(t1_all.end(), pcs[k].T1.begin(), pcs[k].T1.end());
+  }
+  {
+    DevBuf t1d, t1o, g2, g2part;
+    const int gb2 = hdf::gram2_blocks(n);
+    HIPCHK(t1d.ensure(t1_all.size() * 8));
+    HIPCHK(t1o.ensure(t1_off.size() * 4));
+    HIPCHK(g2.ensure((size_t)(K + 1) * 1024 * 8));
+    HIPCHK(g2part.ensure((size_t)gb2 * (K + 1) * 1024 * 8));
+    HIPCHK(hipMemcpyAsync(t1d.p, t1_all.data(), t1_all.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(t1o.p, t1_off.data(), t1_off.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hdf::launch_gram2(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p, f->u0,
+                             f->u1, K, (const double*)t1d.p, (const int32_t*)t1o.p,
+                             (double*)g2part.p, (double*)g2.p, s));
+    std::vector<double> g2h((size_t)(K + 1) * 1024);
+    HIPCHK(hipMemcpyAsync(g2h.data(), g2.p, g2h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    f->deg.resize(K + 1);
+    for (int k = 0; k <= K; ++k) {
+      const int L = K - k + 1;
+      std::vector<double> G2((size_t)L * L);
+      for (int aa = 0; aa < L; ++aa)
+        for (int bb = 0; bb < L; ++bb) G2[(size_t)aa * L + bb] = g2h[(size_t)k * 1024 + aa * 32 + bb];
+      hdf::compress_degree_refined(k, L, G2.data(), pcs[k], f->cores[k].data(), f->tau, 1e-14, f->deg[k]);
+    }
+  }
+  // kept degrees, offsets, tables
+  int64_t hoff = 0, qoff = 0, roff = 0;
+  std::map<std::vector<int>, int> canon;
+  for (int k = 0; k <= K; ++k) {
+    const hdf::DegreeFactor& df = f->deg[k];
+    if (df.s == 0) continue;
+    const int64_t nh = hdf::index_count(d, k);
+    hdf::DegDev dd{};
+    dd.hoff = (int32_t)hoff; dd.nh = (int32_t)nh; dd.qoff = (int32_t)qoff; dd.s = df.s; dd.roff = (int32_t)roff;
+    f->degs.push_back(dd);
+    f->kept_k.push_back(k);
+    std::vector<int32_t> tab;
+    hdf::index_set(d, k, tab);
+    for (int64_t h = 0; h < nh; ++h) {
+      std::vector<int> key(1, k);
+      f->index_table.push_back(k);
+      for (int j = 0; j < d - 2; ++j) {
+        key.push_back(tab[(size_t)h * (d - 2) + j]);
+        f->index_table.push_back(tab[(size_t)h * (d - 2) + j]);
+      }
+      canon[key] = (int)(hoff + h);
+    }
+    hoff += nh;
+    qoff += df.s;
+    roff += nh * df.s;
+    f->max_s = std::max(f->max_s, df.s);
+  }
+  f->H = hoff; f->S = qoff; f->r = roff;
+  f->t_compress = now_ms() - t0;
+
+  // 5. memory budget, then the factor evaluation
+  const size_t fbytes = (size_t)(f->H + f->S) * f->ldN * f->elem();
+  size_t freeb = 0, totb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totb));
+  const size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)(0.6 * (double)freeb));
+  if (fbytes > budget) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "factor needs %.3g GB (H=%lld, S=%lld), budget %.3g GB",
+             fbytes / 1e9, (long long)f->H, (long long)f->S, budget / 1e9);
+    return fail(HDF_E_INFEASIBLE, buf);
+  }
+  if (f->H > 0) {
+    HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
+    HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
+    // loop-order column table
+    std::vector<int32_t> col_of;
+    loop_order_columns(d, K, canon, col_of);
+    HIPCHK(f->col_of.ensure(col_of.size() * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(f->col_of.p, col_of.data(), col_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // recurrence coefficients as (A, B) pairs in the storage type
+    hdf::ChainCoeffs cc;
+    hdf::chain_coeffs(d, K, cc);
+    const size_t npair = cc.A.size();
+    std::vector<double> pd(2 * npair);
+    for (size_t i = 0; i < npair; ++i) { pd[2 * i] = cc.A[i]; pd[2 * i + 1] = cc.B[i]; }
+    std::vector<int32_t> ql, qo;
+    std::vector<double> qc;
+    for (size_t di = 0; di < f->kept_k.size(); ++di) {
+      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
+      for (int l = 0; l < df.s; ++l) {
+        ql.push_back(df.L);
+        qo.push_back((int32_t)qc.size());
+        qc.insert(qc.end(), df.E.begin() + (size_t)l * df.L, df.E.begin() + (size_t)(l + 1) * df.L);
+      }
+    }
+    auto upload_typed = [&](DevBuf& b, const std::vector<double>& v) -> hipError_t {
+      if (f->prec == HDF_MIXED) {
+        std::vector<float> tmp(v.begin(), v.end());
+        hipError_t e = b.ensure(tmp.size() * 4);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(b.p, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);      // tmp goes out of scope
+      }
+      hipError_t e = b.ensure(v.size() * 8);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return e;
+      return hipStreamSynchronize(s);
+    };
+    HIPCHK(upload_typed(f->chain, pd));
+    HIPCHK(upload_typed(f->q_coef, qc));
+    HIPCHK(f->q_len.ensure(ql.size() * 4));
+    HIPCHK(f->q_off.ensure(qo.size() * 4));
+    HIPCHK(hipMemcpyAsync(f->q_len.p, ql.data(), ql.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(f->q_off.p, qo.data(), qo.size() * 4, hipMemcpyHostToDevice, s));
+    // contraction tables
+    std::vector<hdf::TileDev> tiles;
+    for (size_t di = 0; di < f->degs.size(); ++di)
+      for (int h0 = 0; h0 < f->degs[di].nh; h0 += 16) tiles.push_back(hdf::TileDev{(int32_t)di, h0});
+    f->n_tiles = (int)tiles.size();
+    HIPCHK(f->degs_dev.ensure(f->degs.size() * sizeof(hdf::DegDev)));
+    HIPCHK(f->tiles_dev.ensure(tiles.size() * sizeof(hdf::TileDev)));
+    HIPCHK(hipMemcpyAsync(f->degs_dev.p, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(f->tiles_dev.p, tiles.data(), tiles.size() * sizeof(hdf::TileDev), hipMemcpyHostToDevice, s));
+    std::vector<double> lr;
+    lr.reserve(f->r);
+    for (size_t di = 0; di < f->degs.size(); ++di) {
+      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
+      for (int h = 0; h < f->degs[di].nh; ++h)
+        for (int l = 0; l < df.s; ++l) lr.push_back(df.lam[l]);
+    }
+    HIPCHK(f->lam_row.ensure(lr.size() * 8));
+    HIPCHK(hipMemcpyAsync(f->lam_row.p, lr.data(), lr.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
+
+    hdf::BuildTables tb{};
+    tb.col_of = (const int32_t*)f->col_of.p;
+    tb.chain = f->chain.p;
+    tb.q_len = (const int32_t*)f->q_len.p;
+    tb.q_off = (const int32_t*)f->q_off.p;
+    tb.q_coef = f->q_coef.p;
+    tb.K = K;
+    tb.S = (int)f->S;
+    HIPCHK(hipEventCreate(&f->ev_b0));
+    HIPCHK(hipEventCreate(&f->ev_b1));
+    HIPCHK(hipEventRecord(f->ev_b0, s));
+    HIPCHK(hdf::launch_build(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p,
+                             f->u0, f->u1, tb, prec, f->phi.p, f->ldN, f->q.p, f->ldN, s));
+    HIPCHK(hipEventRecord(f->ev_b1, s));
+  }
+  *out = f.release();
+  return HDF_OK;
+}
+
+// ------------------------------------------------------------------ matvec
+static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV,
+                              int64_t ldkv, hipStream_t s, double** W_out) {
+  const int64_t n = h->N;
+  const size_t el = h->elem();
+  if (h->r == 0) {
+    HIPCHK(hipMemset2DAsync(KV, ldkv * el, 0, m * el, n, s));
+    return HDF_OK;
+  }
+  const int m16 = (int)((m + 15) / 16 * 16);
+  int max_nct = h->max_s * (m16 / 16);
+  // splits of the point range for pass 1 (partials <= ~96 MB)
+  const size_t per_split = (size_t)h->r * m16 * sizeof(double);
+  int n_splits = (int)std::min<int64_t>(256, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
+  n_splits = (int)std::min<int64_t>(n_splits, (n + 1023) / 1024);
+  n_splits = std::max(n_splits, 1);
+  int64_t split_len = (n + n_splits - 1) / n_splits;
+  split_len = (split_len + 15) / 16 * 16;
+  n_splits = (int)((n + split_len - 1) / split_len);
+  HIPCHK(h->ws_part.ensure(per_split * n_splits));
+  HIPCHK(h->ws_W.ensure((size_t)h->r * m16 * sizeof(double)));
+  HIPCHK(h->ws_Wd.ensure((size_t)h->r * m16 * el));
+  HIPCHK(hdf::launch_matvec_t(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+                              (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, max_nct, V, ldv, n,
+                              (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
+                              h->prec, s));
+  HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
+                                   (const double*)h->lam_row.p, (double*)h->ws_W.p, h->ws_Wd.p,
+                                   h->prec, s));
+  HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+                              (int)h->degs.size(), h->max_s, h->ws_Wd.p, m16, KV, ldkv, n, (int)m,
+                              h->prec, s));
+  if (W_out) *W_out = (double*)h->ws_W.p;
+  return HDF_OK;
+}
+
+hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV, int64_t ldkv,
+                      void* hip_stream) {
+  g_err.clear();
+  if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  if (!V || !KV) return fail(HDF_E_ARG, "V or KV is NULL");
+  if (m < 1 || m > HDF_MAX_RHS) return fail(HDF_E_ARG, "m must be in [1, 256]");
+  if (ldv < m || ldkv < m) return fail(HDF_E_ARG, "leading dimensions must be >= m");
+  const size_t el = h->elem();
+  const char* v0 = (const char*)V;
+  const char* v1 = v0 + ((h->N - 1) * ldv + m) * el;
+  const char* k0 = (const char*)KV;
+  const char* k1 = k0 + ((h->N - 1) * ldkv + m) * el;
+  if (v0 < k1 && k0 < v1) return fail(HDF_E_ARG, "V and KV overlap");
+  return matvec_impl(h, V, m, ldv, KV, ldkv, (hipStream_t)hip_stream, nullptr);
+}
+
+hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
+                        double* dlength, void* dX, int64_t lddx, void* hip_stream) {
+  (void)Wm; (void)Vm; (void)m; (void)ld; (void)dlength; (void)dX; (void)lddx; (void)hip_stream;
+  if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  return fail(HDF_E_ARG, "hdf_backward: not available in this build");
+}
+
+// ------------------------------------------------------------------ info
+hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
+  g_err.clear();
+  if (!h || !info) return fail(HDF_E_ARG, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_dim = h->d;
+  info->precision = h->prec;
+  info->n_points = h->N;
+  info->degree_p = h->p;
+  info->n_degrees = h->K + 1;
+  info->n_harmonics = h->H;
+  info->n_radial = h->S;
+  info->rank = h->r;
+  info->tau = h->tau;
+  info->nu = h->nu;
+  info->cheb_tail = h->tail;
+  info->center_radius = h->geo.R;
+  info->rho2_min = h->u0;
+  info->rho2_max = h->u1;
+  info->factor_bytes = (int64_t)((h->H + h->S) * h->ldN * h->elem());
+  info->t_prep_ms = h->t_prep;
+  info->t_plan_ms = h->t_plan;
+  info->t_gram_ms = h->t_gram;
+  info->t_compress_ms = h->t_compress;
+  if (h->ev_b0 && h->ev_b1 && h->t_build < 0) {
+    float ms = 0.f;
+    if (hipEventSynchronize(h->ev_b1) == hipSuccess && hipEventElapsedTime(&ms, h->ev_b0, h->ev_b1) == hipSuccess)
+      h->t_build = ms;
+  }
+  info->t_build_ms = h->t_build;
+  for (int k = 0; k <= h->K && k <= HDF_MAX_DEGREE / 2; ++k) info->s_k[k] = h->deg[k].s;
+  return HDF_OK;
+}
+
+hdf_status hdf_get_plan(hdf_handle h, int32_t* index_table, double* lambda, double* radial_coef,
+                        double* a_cheb) {
+  g_err.clear();
+  if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  if (index_table) std::copy(h->index_table.begin(), h->index_table.end(), index_table);
+  if (lambda || radial_coef) {
+    size_t li = 0, ci = 0;
+    for (int k = 0; k <= h->K; ++k) {
+      const hdf::DegreeFactor& df = h->deg[k];
+      for (int l = 0; l < df.s; ++l) {
+        if (lambda) lambda[li] = df.lam[l];
+        ++li;
+      }
+      if (radial_coef) std::copy(df.E.begin(), df.E.end(), radial_coef + ci);
+      ci += df.E.size();
+    }
+  }
+  if (a_cheb) std::copy(h->a.begin(), h->a.end(), a_cheb);
+  return HDF_OK;
+}
+
+hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_out, int64_t ld_q,
+                           void* hip_stream) {
+  g_err.clear();
+  if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  if ((phi_out && ld_phi < h->N) || (q_out && ld_q < h->N)) return fail(HDF_E_ARG, "leading dimension < n");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t el = h->elem();
+  if (phi_out && h->H > 0)
+    HIPCHK(hipMemcpy2DAsync(phi_out, ld_phi * el, h->phi.p, h->ldN * el, h->N * el, h->H,
+                            hipMemcpyDeviceToDevice, s));
+  if (q_out && h->S > 0)
+    HIPCHK(hipMemcpy2DAsync(q_out, ld_q * el, h->q.p, h->ldN * el, h->N * el, h->S,
+                            hipMemcpyDeviceToDevice, s));
+  return HDF_OK;
+}
+
+// ------------------------------------------------------------------ host planner
+hdf_status hdf_plan_chebyshev(hdf_kernel kernel, double D, double lengthscale, int n_nodes,
+                              int derivative, double* a) {
+  g_err.clear();
+  if (!a) return fail(HDF_E_ARG, "a is NULL");
+  if (n_nodes < 16 || (n_nodes & (n_nodes - 1))) return fail(HDF_E_ARG, "n_nodes must be a power of two >= 16");
+  if ((int)kernel < 0 || (int)kernel > 3) return fail(HDF_E_ARG, "unknown kernel");
+  if (!(lengthscale > 0) || !(D >= 0)) return fail(HDF_E_ARG, "need D >= 0 and lengthscale > 0");
+  hdf::chebyshev_coeffs(kernel, D, lengthscale, n_nodes, derivative != 0, a);
+  return HDF_OK;
+}
+
+hdf_status hdf_plan_degree(const double* a, int n, double eps, double nu, int p_max, int* p,
+                           double* tail) {
+  g_err.clear();
+  if (!a || !p) return fail(HDF_E_ARG, "NULL argument");
+  if (n < 2) return fail(HDF_E_ARG, "n must be >= 2");
+  double t = 0;
+  const int pp = hdf::choose_degree(a, n, eps * nu / 2.0, p_max, &t);
+  if (pp < 0) return fail(HDF_E_INFEASIBLE, "no even degree <= p_max meets the tail bound");
+  *p = pp;
+  if (tail) *tail = t;
+  return HDF_OK;
+}
+
+hdf_status hdf_plan_cores(const double* a, int p, int d, double u0, double u1, double* cores) {
+  g_err.clear();
+  if (!a || !cores) return fail(HDF_E_ARG, "NULL argument");
+  if (p < 0 || (p % 2) || p > HDF_MAX_DEGREE) return fail(HDF_E_ARG, "p must be even in [0, HDF_MAX_DEGREE]");
+  if (d < 3 || d > HDF_MAX_DIM) return fail(HDF_E_DIM, "d must be in [3, 8]");
+  if (!(u1 > u0) || u0 < 0) return fail(HDF_E_ARG, "need 0 <= u0 < u1");
+  std::vector<std::vector<double>> c;
+  hdf::radial_cores(a, p, d, u0, u1, c);
+  size_t o = 0;
+  for (auto& M : c) {
+    std::copy(M.begin(), M.end(), cores + o);
+    o += M.size();
+  }
+  return HDF_OK;
+}
+
+hdf_status hdf_plan_index_set(int d, int k, int32_t* table, int64_t* count) {
+  g_err.clear();
+  if (!count) return fail(HDF_E_ARG, "count is NULL");
+  if (d < 3 || d > HDF_MAX_DIM) return fail(HDF_E_DIM, "d must be in [3, 8]");
+  if (k < 0) return fail(HDF_E_ARG, "k must be >= 0");
+  std::vector<int32_t> t;
+  hdf::index_set(d, k, t);
+  *count = (int64_t)(t.size() / (d - 2));
+  if (table) std::copy(t.begin(), t.end(), table);
+  return HDF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,853 @@
+// gfx950 kernels of the HDF hot path: geometry, radial Gram moments, factor
+// evaluation and the two contraction passes of the matvec.
+//
+// Layout in HBM (N points, padded leading dimension ldN):
+//   x_soa : d rows of ldN coordinates (input type), one row per coordinate;
+//   phi   : H rows of ldN values, row h = solid harmonic h at every point;
+//   q     : S rows of ldN values, row (k,l) = radial function l of degree k.
+// Every per-point kernel maps consecutive lanes to consecutive points, so a
+// wavefront reads/writes one contiguous 256 B (fp32) or 512 B (fp64) segment
+// per row.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace hdf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// 16x16x4 MFMA.  Operands: lane r + 16 q supplies A[r][q] and B[q][r].
+// Accumulator element e of lane j + 16 g holds D[row(g, e)][j]; the row map
+// differs between the two instructions (measured on gfx950):
+//   f32: row = 4 g + e        f64: row = g + 4 e
+template <> struct Mfma<float> {
+  typedef floatx4 V;
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
+};
+template <> struct Mfma<double> {
+  typedef doublex4 V;
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int e) { return g + 4 * e; }
+};
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { typedef float2 type; };
+template <> struct Vec2<double> { typedef double2 type; };
+
+__device__ __forceinline__ double kernel_value_dev(int kind, double r, double l) {
+  switch (kind) {
+    case 0: return exp(-(r * r) / (2.0 * l * l));
+    case 1: return 1.0 / (1.0 + (r * r) / (l * l));
+    case 2: { double z = 1.7320508075688772 * r / l; return (1.0 + z) * exp(-z); }
+    default: { double z = 2.23606797749979 * r / l; return (1.0 + z + z * z / 3.0) * exp(-z); }
+  }
+}
+
+// SplitMix64 output number q (1-based) of the stream started at `seed`:
+// the generator is counter based, state_q = seed + q * gamma.
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t q) {
+  uint64_t z = seed + q * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Fixed-order tree reduction over a 256-thread block (deterministic).
+template <typename Op>
+__device__ __forceinline__ double block_reduce(double v, double* sh, Op op) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] = op(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpAdd { __device__ double operator()(double a, double b) const { return a + b; } };
+
+// ------------------------------------------------------------------ prep
+// Partial record per block: [0..7] min, [8..15] max, [16] nu2, [17] nonfinite.
+constexpr int kPrepRec = 18;
+
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_prep_minmax(const Tin* __restrict__ pts, int64_t n, int d,
+                                                      int64_t ld, Tin* __restrict__ x_soa,
+                                                      int64_t ldx, int kind, double l,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[256];
+  double mn[8], mx[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) { mn[j] = INFINITY; mx[j] = -INFINITY; }
+  double nf = 0.0;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gsz) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < d) {
+        const Tin raw = pts[i * ld + j];
+        x_soa[(int64_t)j * ldx + i] = raw;
+        const double v = (double)raw;
+        if (!isfinite(v)) nf += 1.0;
+        mn[j] = fmin(mn[j], v);
+        mx[j] = fmax(mx[j], v);
+      }
+    }
+  }
+  // ||K||_F sample: pair t uses generator outputs 2t+1 and 2t+2
+  double nu = 0.0;
+  {
+#pragma clang fp contract(off)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < kNuPairs; t += gsz) {
+      const uint64_t ia = (splitmix_at(kNuSeed, 2 * (uint64_t)t + 1) >> 11) % (uint64_t)n;
+      const uint64_t ib = (splitmix_at(kNuSeed, 2 * (uint64_t)t + 2) >> 11) % (uint64_t)n;
+      double s = 0.0;
+      for (int j = 0; j < d; ++j) {
+        const double df = (double)pts[(int64_t)ia * ld + j] - (double)pts[(int64_t)ib * ld + j];
+        s = s + df * df;
+      }
+      const double kv = kernel_value_dev(kind, sqrt(s), l);
+      nu = nu + kv * kv;
+    }
+  }
+  double* rec = part + (int64_t)blockIdx.x * kPrepRec;
+  for (int j = 0; j < 8; ++j) {
+    const double a = block_reduce(mn[j], sh, OpMin());
+    const double b = block_reduce(mx[j], sh, OpMax());
+    if (threadIdx.x == 0) { rec[j] = a; rec[8 + j] = b; }
+  }
+  const double s1 = block_reduce(nu, sh, OpAdd());
+  const double s2 = block_reduce(nf, sh, OpAdd());
+  if (threadIdx.x == 0) { rec[16] = s1; rec[17] = s2; }
+}
+
+__global__ void __launch_bounds__(256) k_prep_fin1(const double* __restrict__ part, int nblk,
+                                                    GeoDev* geo) {
+  __shared__ double sh[256];
+  for (int q = 0; q < kPrepRec; ++q) {
+    double v = (q < 8) ? INFINITY : (q < 16 ? -INFINITY : 0.0);
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+      const double x = part[(int64_t)b * kPrepRec + q];
+      v = (q < 8) ? fmin(v, x) : (q < 16 ? fmax(v, x) : v + x);
+    }
+    double r;
+    if (q < 8) r = block_reduce(v, sh, OpMin());
+    else if (q < 16) r = block_reduce(v, sh, OpMax());
+    else r = block_reduce(v, sh, OpAdd());
+    if (threadIdx.x == 0) {
+      if (q < 8) geo->c[q] = r;                   // min, combined below
+      else if (q < 16) geo->c[q - 8] = (geo->c[q - 8] + r) * 0.5;
+      else if (q == 16) geo->nu2_sum = r;
+      else geo->nonfinite = r;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_prep_radius(const Tin* __restrict__ x_soa, int64_t ldx,
+                                                      int64_t n, int d, const GeoDev* geo,
+                                                      double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double sh[256];
+  double mx = 0.0;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gsz) {
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) {
+      const double t = (double)x_soa[(int64_t)j * ldx + i] - geo->c[j];
+      s = s + t * t;
+    }
+    mx = fmax(mx, s);
+  }
+  const double r = block_reduce(mx, sh, OpMax());
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) k_prep_fin2(const double* __restrict__ part, int nblk,
+                                                    GeoDev* geo) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) v = fmax(v, part[b]);
+  const double r = block_reduce(v, sh, OpMax());
+  if (threadIdx.x == 0) {
+    geo->R2 = r;
+    geo->R = sqrt(r);
+    geo->Reff = geo->R > 0.0 ? geo->R : 1.0;
+  }
+}
+
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_prep_rho(const Tin* __restrict__ x_soa, int64_t ldx,
+                                                   int64_t n, int d, const GeoDev* geo,
+                                                   double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double sh[256];
+  double mn = INFINITY, mx = -INFINITY;
+  const double Reff = geo->Reff;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gsz) {
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) {
+      const double t = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+      s = s + t * t;
+    }
+    mn = fmin(mn, s);
+    mx = fmax(mx, s);
+  }
+  const double a = block_reduce(mn, sh, OpMin());
+  const double b = block_reduce(mx, sh, OpMax());
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = a; part[2 * blockIdx.x + 1] = b; }
+}
+
+__global__ void __launch_bounds__(256) k_prep_fin3(const double* __restrict__ part, int nblk,
+                                                    GeoDev* geo) {
+  __shared__ double sh[256];
+  double mn = INFINITY, mx = -INFINITY;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    mn = fmin(mn, part[2 * b]);
+    mx = fmax(mx, part[2 * b + 1]);
+  }
+  const double a = block_reduce(mn, sh, OpMin());
+  const double c = block_reduce(mx, sh, OpMax());
+  if (threadIdx.x == 0) { geo->rho2_min = a; geo->rho2_max = c; }
+}
+
+hipError_t launch_prep(const void* pts, int dtype, int64_t n, int d, int64_t ld, void* x_soa,
+                       int64_t ldx, int kernel, double l, double* partials, GeoDev* geo,
+                       hipStream_t s) {
+  const int nb = kPrepBlocks;
+  if (dtype == 0) {
+    k_prep_minmax<float><<<nb, 256, 0, s>>>((const float*)pts, n, d, ld, (float*)x_soa, ldx, kernel, l, partials);
+  } else {
+    k_prep_minmax<double><<<nb, 256, 0, s>>>((const double*)pts, n, d, ld, (double*)x_soa, ldx, kernel, l, partials);
+  }
+  k_prep_fin1<<<1, 256, 0, s>>>(partials, nb, geo);
+  if (dtype == 0) k_prep_radius<float><<<nb, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, partials);
+  else k_prep_radius<double><<<nb, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, partials);
+  k_prep_fin2<<<1, 256, 0, s>>>(partials, nb, geo);
+  if (dtype == 0) k_prep_rho<float><<<nb, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, partials);
+  else k_prep_rho<double><<<nb, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, partials);
+  k_prep_fin3<<<1, 256, 0, s>>>(partials, nb, geo);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Gram
+// Moments mu[k][c] = sum_i rho_i^{2k} T_c(t_i) as a tall-skinny product
+// A^T B on MFMA (A[i][k] = rho_i^{2k}, B[i][c] = T_c(t_i)).  The per-degree
+// Gram blocks follow on the host from T_a T_b = (T_{a+b} + T_{|a-b|}) / 2.
+constexpr int kGramRowTiles = 2;   // k <= 31
+constexpr int kGramColTiles = 4;   // c <= 63
+constexpr int kGramBlocks = 480;
+
+template <typename Tin, int MODE>
+__global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
+                                               int d, const GeoDev* __restrict__ geo, double u0,
+                                               double u1, int K, int nrt, int nct,
+                                               double* __restrict__ part) {
+  typedef typename std::conditional<MODE == 0, double, float>::type T;
+  typedef typename Mfma<T>::V V;
+  __shared__ double sh[4][4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const double Reff = geo->Reff;
+  double dacc[kGramRowTiles][kGramColTiles][4];
+#pragma unroll
+  for (int a = 0; a < kGramRowTiles; ++a)
+#pragma unroll
+    for (int b = 0; b < kGramColTiles; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dacc[a][b][e] = 0.0;
+  const int64_t nchunks = (n + 63) / 64;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
+    V acc[kGramRowTiles][kGramColTiles];
+#pragma unroll
+    for (int a = 0; a < kGramRowTiles; ++a)
+#pragma unroll
+      for (int b = 0; b < kGramColTiles; ++b) acc[a][b] = V{0, 0, 0, 0};
+    // lane group g handles 16 consecutive points of the 64-point chunk
+    for (int s = 0; s < 16; ++s) {
+      const int64_t i = ch * 64 + g * 16 + s;
+      double w[kGramRowTiles], tc[kGramColTiles];
+#pragma unroll
+      for (int a = 0; a < kGramRowTiles; ++a) w[a] = 0.0;
+#pragma unroll
+      for (int b = 0; b < kGramColTiles; ++b) tc[b] = 0.0;
+      if (i < n) {
+        double rho2 = 0.0;
+        for (int j = 0; j < d; ++j) {
+          const double t = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+          rho2 += t * t;
+        }
+        const double t = (2.0 * rho2 - u0 - u1) / (u1 - u0);
+#pragma unroll
+        for (int a = 0; a < kGramRowTiles; ++a) {
+          const int k = a * 16 + li;
+          if (a < nrt && k <= K) {
+            double pw = 1.0, base = rho2;
+            for (int e = k; e > 0; e >>= 1) {
+              if (e & 1) pw *= base;
+              base *= base;
+            }
+            w[a] = pw;
+          }
+        }
+        // T_c(t) for c = b*16 + li by the three-term recurrence
+        double tm1 = 1.0, t0 = t;
+        const int cmax = nct * 16;
+        for (int c = 0; c < cmax; ++c) {
+          double tcur;
+          if (c == 0) tcur = 1.0;
+          else if (c == 1) tcur = t;
+          else { tcur = 2.0 * t * t0 - tm1; tm1 = t0; t0 = tcur; }
+#pragma unroll
+          for (int b = 0; b < kGramColTiles; ++b)
+            if (c == b * 16 + li && c <= 2 * K) tc[b] = tcur;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < kGramRowTiles; ++a) {
+        if (a >= nrt) continue;
+#pragma unroll
+        for (int b = 0; b < kGramColTiles; ++b) {
+          if (b >= nct) continue;
+          if constexpr (MODE == 2) {
+            const float ah = (float)w[a], al = (float)(w[a] - (double)ah);
+            const float bh = (float)tc[b], bl = (float)(tc[b] - (double)bh);
+            acc[a][b] = Mfma<float>::run(ah, bh, acc[a][b]);
+            acc[a][b] = Mfma<float>::run(ah, bl, acc[a][b]);
+            acc[a][b] = Mfma<float>::run(al, bh, acc[a][b]);
+          } else {
+            acc[a][b] = Mfma<T>::run((T)w[a], (T)tc[b], acc[a][b]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kGramRowTiles; ++a)
+#pragma unroll
+      for (int b = 0; b < kGramColTiles; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dacc[a][b][e] += (double)acc[a][b][e];
+  }
+  // combine the four waves in a fixed order, one 16x16 tile at a time
+  const int rows = nrt * 16, cols = nct * 16;
+  double* out = part + (int64_t)blockIdx.x * rows * cols;
+#pragma unroll
+  for (int a = 0; a < kGramRowTiles; ++a)
+#pragma unroll
+    for (int b = 0; b < kGramColTiles; ++b) {
+      if (a >= nrt || b >= nct) continue;
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sh[wave][e * 64 + lane] = dacc[a][b][e];
+      __syncthreads();
+      const int idx = threadIdx.x;             // 256 = 4 elements x 64 lanes
+      const int ln = idx & 63, e = idx >> 6;
+      const double v = sh[0][idx] + sh[1][idx] + sh[2][idx] + sh[3][idx];
+      const int row = a * 16 + Mfma<T>::row(ln >> 4, e), col = b * 16 + (ln & 15);
+      out[row * cols + col] = v;
+    }
+}
+
+__global__ void k_gram_fin(const double* __restrict__ part, int nblk, int total,
+                           double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * total + e];
+  out[e] = s;
+}
+
+int gram_blocks(int64_t n) {
+  const int64_t chunks = (n + 63) / 64;
+  int64_t b = (chunks + 3) / 4;
+  if (b > kGramBlocks) b = kGramBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                       const GeoDev* geo, double u0, double u1, int K, int mode,
+                       double* partials, double* moments, hipStream_t s) {
+  const int nrt = (K + 1 + 15) / 16, nct = (2 * K + 1 + 15) / 16;
+  if (nrt > kGramRowTiles || nct > kGramColTiles) return hipErrorInvalidValue;
+  const int nb = gram_blocks(n);
+#define GRAM_LAUNCH(TIN, MODE)                                                                    \
+  k_gram<TIN, MODE><<<nb, 256, 0, s>>>((const TIN*)x_soa, ldx, n, d, geo, u0, u1, K, nrt, nct, \
+                                       partials)
+  if (dtype == 0) {
+    if (mode == 0) GRAM_LAUNCH(float, 0);
+    else if (mode == 1) GRAM_LAUNCH(float, 1);
+    else GRAM_LAUNCH(float, 2);
+  } else {
+    if (mode == 0) GRAM_LAUNCH(double, 0);
+    else if (mode == 1) GRAM_LAUNCH(double, 1);
+    else GRAM_LAUNCH(double, 2);
+  }
+#undef GRAM_LAUNCH
+  const int total = nrt * 16 * nct * 16;
+  k_gram_fin<<<(total + 255) / 256, 256, 0, s>>>(partials, nb, total, moments);
+  return hipGetLastError();
+}
+
+// Second Gram pass (refinement of the compression, binary64 MFMA): for every
+// degree k, G2_k = sum_i z_i z_i^T with z_i = T1_k^T y_i and
+// y_i[a] = rho_i^k T_a(t_i), a < L_k = K - k + 1.  T1_k (L_k x L_k, row-major)
+// is the preconditioner from the first pass, so the columns Y_k T1_k are
+// nearly orthonormal and their Gram is accurate in binary64 even when Y_k is
+// badly conditioned.  One block owns a range of points and loops over the
+// degrees; partial record per block: [K+1][32][32].
+constexpr int kGram2Blocks = 128;
+
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_gram2(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
+                                                int d, const GeoDev* __restrict__ geo, double u0,
+                                                double u1, int K, const double* __restrict__ T1,
+                                                const int32_t* __restrict__ t1_off,
+                                                double* __restrict__ part) {
+  typedef Mfma<double>::V V;
+  __shared__ double t1s[32 * 32];
+  __shared__ double sh[4][4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const double Reff = geo->Reff;
+  const int64_t per_blk = ((n + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
+  const int64_t p_begin = (int64_t)blockIdx.x * per_blk;
+  const int64_t p_end = (p_begin + per_blk < n) ? p_begin + per_blk : n;
+  for (int k = 0; k <= K; ++k) {
+    const int L = K - k + 1;
+    const int nt = (L + 15) / 16;
+    __syncthreads();
+    for (int e = threadIdx.x; e < L * L; e += 256) t1s[e] = T1[t1_off[k] + e];
+    __syncthreads();
+    V acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
+    for (int64_t ch = p_begin + (int64_t)wave * 64; ch < p_end; ch += 4 * 64) {
+      for (int s = 0; s < 16; ++s) {
+        const int64_t i = ch + g * 16 + s;
+        double z0 = 0.0, z1 = 0.0;
+        if (i < p_end) {
+          double rho2 = 0.0;
+          for (int j = 0; j < d; ++j) {
+            const double t = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+            rho2 += t * t;
+          }
+          const double t = (2.0 * rho2 - u0 - u1) / (u1 - u0);
+          double rk = 1.0, base = sqrt(rho2);
+          for (int e = k; e > 0; e >>= 1) {
+            if (e & 1) rk *= base;
+            base *= base;
+          }
+          double tm1 = 0.0, tc = 1.0;            // T_{a-1}, T_a
+          for (int a = 0; a < L; ++a) {
+            if (a == 1) { tm1 = 1.0; tc = t; }
+            else if (a >= 2) { const double tn = 2.0 * t * tc - tm1; tm1 = tc; tc = tn; }
+            const double ya = rk * tc;
+            if (li < L) z0 += t1s[a * L + li] * ya;
+            if (16 + li < L) z1 += t1s[a * L + 16 + li] * ya;
+          }
+        }
+        const double z[2] = {z0, z1};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            if (a < nt && b < nt) acc[a][b] = Mfma<double>::run(z[a], z[b], acc[a][b]);
+      }
+    }
+    double* out = part + ((int64_t)blockIdx.x * (K + 1) + k) * 1024;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (a >= nt || b >= nt) continue;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sh[wave][e * 64 + lane] = acc[a][b][e];
+        __syncthreads();
+        const int idx = threadIdx.x, ln = idx & 63, e = idx >> 6;
+        const double v = sh[0][idx] + sh[1][idx] + sh[2][idx] + sh[3][idx];
+        const int row = a * 16 + Mfma<double>::row(ln >> 4, e), col = b * 16 + (ln & 15);
+        out[row * 32 + col] = v;
+      }
+  }
+}
+
+int gram2_blocks(int64_t n) {
+  int64_t b = (n + 2047) / 2048;
+  if (b > kGram2Blocks) b = kGram2Blocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                        const GeoDev* geo, double u0, double u1, int K, const double* T1,
+                        const int32_t* t1_off, double* partials, double* out, hipStream_t s) {
+  if (K + 1 > 32) return hipErrorInvalidValue;
+  const int nb = gram2_blocks(n);
+  if (dtype == 0)
+    k_gram2<float><<<nb, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
+  else
+    k_gram2<double><<<nb, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
+  const int total = (K + 1) * 1024;
+  k_gram_fin<<<(total + 255) / 256, 256, 0, s>>>(partials, nb, total, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ build
+// Solid harmonics by nested normalised Gegenbauer chain recurrences.  The
+// loops run from the innermost chain level outwards (azimuthal index first,
+// degree k last), so each level keeps only its two-term recurrence state in
+// registers; every iteration of the innermost loop yields one harmonic,
+// stored to its canonical row col_of[t] (the table follows this loop order).
+template <typename T, int D, int LEVEL>
+struct Chain {
+  typedef typename Vec2<T>::type T2;
+  static __device__ __forceinline__ void run(const T* xt, const T* r2, int b, T prefix, int K,
+                                             const T2* __restrict__ chain,
+                                             const int32_t* __restrict__ col_of, int& t,
+                                             T* __restrict__ phi, int64_t ld, int64_t i,
+                                             bool valid) {
+    const T x = xt[LEVEL - 1], rr = r2[LEVEL - 1];
+    const T2* cf = chain + ((int64_t)(LEVEL - 1) * (K + 1) + b) * (K + 1);
+    T pm1 = 0, p = cf[0].x;
+    for (int nn = 0; nn <= K - b; ++nn) {
+      if (nn == 1) { pm1 = p; p = cf[1].x * x; }
+      else if (nn >= 2) { const T pn = cf[nn].x * x * p - cf[nn].y * rr * pm1; pm1 = p; p = pn; }
+      Chain<T, D, LEVEL - 1>::run(xt, r2, b + nn, prefix * p, K, chain, col_of, t, phi, ld, i, valid);
+    }
+  }
+};
+template <typename T, int D>
+struct Chain<T, D, 0> {
+  typedef typename Vec2<T>::type T2;
+  static __device__ __forceinline__ void run(const T*, const T*, int, T prefix, int,
+                                             const T2* __restrict__, const int32_t* __restrict__ col_of,
+                                             int& t, T* __restrict__ phi, int64_t ld, int64_t i,
+                                             bool valid) {
+    const int col = col_of[t++];
+    if (valid && col >= 0) __builtin_nontemporal_store(prefix, phi + (int64_t)col * ld + i);
+  }
+};
+
+template <typename Tin, typename T, int D>
+__global__ void __launch_bounds__(256) k_build(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
+                                                const GeoDev* __restrict__ geo, double u0, double u1,
+                                                const int32_t* __restrict__ col_of,
+                                                const typename Vec2<T>::type* __restrict__ chain,
+                                                const int32_t* __restrict__ q_len,
+                                                const int32_t* __restrict__ q_off,
+                                                const T* __restrict__ q_coef, int K, int S,
+                                                T* __restrict__ phi, int64_t ld_phi,
+                                                T* __restrict__ q, int64_t ld_q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const int64_t ii = valid ? i : 0;
+  T xt[D], r2[D];
+  double rho2 = 0.0;
+  {
+#pragma clang fp contract(off)
+    const double Reff = geo->Reff;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double v = ((double)x_soa[(int64_t)j * ldx + ii] - geo->c[j]) / Reff;
+      xt[j] = (T)v;
+      rho2 = rho2 + v * v;
+    }
+  }
+  T acc = 0;
+#pragma unroll
+  for (int j = D - 1; j >= 0; --j) {
+    acc += xt[j] * xt[j];
+    r2[j] = acc;
+  }
+  // harmonics: azimuthal part (x_{D-1} + i x_D)^m outermost
+  int t = 0;
+  const T ax = xt[D - 2], ay = xt[D - 1];
+  T cr = 1, ci = 0;
+  const T inv_sqrt_2pi = (T)0.39894228040143267794, inv_sqrt_pi = (T)0.56418958354775628695;
+  for (int mm = 0; mm <= K; ++mm) {
+    if (mm > 0) { const T ncr = ax * cr - ay * ci; ci = ay * cr + ax * ci; cr = ncr; }
+    const T cm = (mm == 0) ? inv_sqrt_2pi : inv_sqrt_pi;
+    Chain<T, D, D - 2>::run(xt, r2, mm, cm * cr, K, chain, col_of, t, phi, ld_phi, i, valid);
+    if (mm > 0) Chain<T, D, D - 2>::run(xt, r2, mm, cm * ci, K, chain, col_of, t, phi, ld_phi, i, valid);
+  }
+  // radial functions: Clenshaw in the basis T_a(t)
+  const T tt = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
+  for (int row = 0; row < S; ++row) {
+    const int L = q_len[row];
+    const T* cf = q_coef + q_off[row];
+    T b1 = 0, b2 = 0;
+    for (int a = L - 1; a >= 1; --a) {
+      const T b0 = 2 * tt * b1 - b2 + cf[a];
+      b2 = b1;
+      b1 = b0;
+    }
+    const T val = tt * b1 - b2 + cf[0];
+    if (valid) __builtin_nontemporal_store(val, q + (int64_t)row * ld_q + i);
+  }
+}
+
+template <typename Tin, typename T>
+static hipError_t launch_build_t(const void* x_soa, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                                 double u0, double u1, const BuildTables& tb, void* phi,
+                                 int64_t ld_phi, void* q, int64_t ld_q, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256));
+  typedef typename Vec2<T>::type T2;
+#define BUILD_CASE(DD)                                                                        \
+  case DD:                                                                                    \
+    k_build<Tin, T, DD><<<grid, 256, 0, s>>>((const Tin*)x_soa, ldx, n, geo, u0, u1, tb.col_of, \
+                                             (const T2*)tb.chain, tb.q_len, tb.q_off,         \
+                                             (const T*)tb.q_coef, tb.K, tb.S, (T*)phi, ld_phi,  \
+                                             (T*)q, ld_q);                                    \
+    break;
+  switch (d) {
+    BUILD_CASE(3)
+    BUILD_CASE(4)
+    BUILD_CASE(5)
+    BUILD_CASE(6)
+    BUILD_CASE(7)
+    BUILD_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef BUILD_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                        const GeoDev* geo, double u0, double u1, const BuildTables& tb,
+                        int prec, void* phi, int64_t ld_phi, void* q, int64_t ld_q,
+                        hipStream_t s) {
+  if (prec == 1 && dtype == 0)
+    return launch_build_t<float, float>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
+  if (prec == 0 && dtype == 1)
+    return launch_build_t<double, double>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ matvec
+// Pass 1, W = U^T V.  Per degree k this is the product Phi_k (Q_k o V)
+// (Khatri-Rao: column (k,h,l) of U is phi_h * q_{k,l}).  One wavefront owns
+// a 16-harmonic tile of one degree and a contiguous range of points; columns
+// j = l * m16 + c of the tile product are produced NCT 16-wide tiles at a
+// time.  The reduction index (points) is assigned so that lane group g reads
+// 4 consecutive points of each harmonic row.
+template <typename T, int NCT>
+__global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t ld_phi,
+                                              const T* __restrict__ q, int64_t ld_q,
+                                              const DegDev* __restrict__ degs,
+                                              const TileDev* __restrict__ tiles,
+                                              const T* __restrict__ V, int64_t ldv, int64_t n,
+                                              int m, int m16, int64_t split_len, int64_t rank,
+                                              double* __restrict__ part) {
+  typedef typename Mfma<T>::V Acc;
+  const TileDev tile = tiles[blockIdx.x];
+  const DegDev dg = degs[tile.deg];
+  const int split = blockIdx.y;
+  const int cpl = m16 / 16;                      // column tiles per radial function
+  const int nct_all = dg.s * cpl;
+  const int ct0 = blockIdx.z * NCT;
+  if (ct0 >= nct_all) return;
+  const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+  const int row = tile.h0 + li;
+  const bool rowv = row < dg.nh;
+  const T* prow = phi + (int64_t)(dg.hoff + (rowv ? row : 0)) * ld_phi;
+  const T* qrow[NCT];
+  int cc[NCT];
+  bool cv[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int tix = ct0 + ct;
+    const int l = tix / cpl;
+    cc[ct] = (tix % cpl) * 16 + li;
+    cv[ct] = (tix < nct_all) && (cc[ct] < m);
+    qrow[ct] = q + (int64_t)(dg.qoff + (tix < nct_all ? l : 0)) * ld_q;
+  }
+  Acc acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = Acc{0, 0, 0, 0};
+  const int64_t p_begin = (int64_t)split * split_len;
+  const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
+  for (int64_t p = p_begin; p < p_end; p += 16) {
+    const int64_t pb = p + 4 * g;
+    T a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = (rowv && pb + t < p_end) ? prow[pb + t] : (T)0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t pt = pb + t;
+      const bool pv = pt < p_end;
+      const T* vrow = V + (pv ? pt : 0) * ldv;
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const T b = (pv && cv[ct]) ? qrow[ct][pt] * vrow[cc[ct]] : (T)0;
+        acc[ct] = Mfma<T>::run(a[t], b, acc[ct]);
+      }
+    }
+  }
+  double* out = part + (int64_t)split * rank * m16;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int tix = ct0 + ct;
+    if (tix >= nct_all) continue;
+    const int l = tix / cpl;
+    const int c = (tix % cpl) * 16 + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int h = tile.h0 + Mfma<T>::row(g, e);
+      if (h < dg.nh) out[(int64_t)(dg.roff + h * dg.s + l) * m16 + c] = (double)acc[ct][e];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_mv_reduce(const double* __restrict__ part, int n_splits, int64_t total, int m16,
+                            const double* __restrict__ lam_row, double* __restrict__ W,
+                            T* __restrict__ Wd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  double s = 0.0;
+  for (int sp = 0; sp < n_splits; ++sp) s += part[(int64_t)sp * total + e];
+  W[e] = s;
+  Wd[e] = (T)(lam_row[e / m16] * s);
+}
+
+// Pass 2, KV = U (D W).  One wavefront owns 32 points and one 16-column
+// chunk of the right-hand sides; per degree it forms Z[i][(l,c)] =
+// sum_h phi_h(i) Wd[(k,h,l)][c] on MFMA (reduction over harmonics) and folds
+// Z into KV with the radial functions q_{k,l}(i).
+template <typename T, int NCT>
+__global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t ld_phi,
+                                              const T* __restrict__ q, int64_t ld_q,
+                                              const DegDev* __restrict__ degs, int n_deg,
+                                              const T* __restrict__ Wd, int m16,
+                                              T* __restrict__ KV, int64_t ldkv, int64_t n, int m) {
+  typedef typename Mfma<T>::V Acc;
+  const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 16;
+  T kv[2][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) kv[u][e] = 0;
+  for (int di = 0; di < n_deg; ++di) {
+    const DegDev dg = degs[di];
+    for (int l0 = 0; l0 < dg.s; l0 += NCT) {
+      Acc acc[2][NCT];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = Acc{0, 0, 0, 0};
+      for (int h0 = 0; h0 < dg.nh; h0 += 4) {
+        const int hh = h0 + g;
+        const bool hv = hh < dg.nh;
+        const T* prow = phi + (int64_t)(dg.hoff + (hv ? hh : 0)) * ld_phi;
+        T a[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int64_t pt = p0 + 16 * u + li;
+          a[u] = (hv && pt < n) ? prow[pt] : (T)0;
+        }
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int l = l0 + ct;
+          const T b = (hv && l < dg.s) ? Wd[(int64_t)(dg.roff + hh * dg.s + l) * m16 + c0 + li] : (T)0;
+#pragma unroll
+          for (int u = 0; u < 2; ++u) acc[u][ct] = Mfma<T>::run(a[u], b, acc[u][ct]);
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int l = l0 + ct;
+        if (l >= dg.s) continue;
+        const T* qrow = q + (int64_t)(dg.qoff + l) * ld_q;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t pt = p0 + 16 * u + Mfma<T>::row(g, e);
+            const T qv = (pt < n) ? qrow[pt] : (T)0;
+            kv[u][e] += qv * acc[u][ct][e];
+          }
+      }
+    }
+  }
+  const int c = c0 + li;
+  if (c < m) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t pt = p0 + 16 * u + Mfma<T>::row(g, e);
+        if (pt < n) KV[pt * ldkv + c] = kv[u][e];
+      }
+  }
+}
+
+constexpr int kMvNct = 4;
+
+hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                           const DegDev* degs, const TileDev* tiles, int n_tiles, int max_nct,
+                           const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
+                           int64_t split_len, int64_t rank, double* partials, int prec,
+                           hipStream_t s) {
+  const dim3 grid(n_tiles, n_splits, (max_nct + kMvNct - 1) / kMvNct);
+  if (prec == 1)
+    k_mv_t<float, kMvNct><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
+                                             tiles, (const float*)V, ldv, n, m, m16, split_len, rank,
+                                             partials);
+  else
+    k_mv_t<double, kMvNct><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
+                                              degs, tiles, (const double*)V, ldv, n, m, m16,
+                                              split_len, rank, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t rank, int m16,
+                                const double* lam_row, double* W, void* Wd, int prec,
+                                hipStream_t s) {
+  const int64_t total = rank * m16;
+  const unsigned nb = (unsigned)((total + 255) / 256);
+  if (prec == 1)
+    k_mv_reduce<float><<<nb, 256, 0, s>>>(partials, n_splits, total, m16, lam_row, W, (float*)Wd);
+  else
+    k_mv_reduce<double><<<nb, 256, 0, s>>>(partials, n_splits, total, m16, lam_row, W, (double*)Wd);
+  return hipGetLastError();
+}
+
+hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                           const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
+                           void* KV, int64_t ldkv, int64_t n, int m, int prec, hipStream_t s) {
+  (void)max_s;
+  const dim3 grid((unsigned)((n + 31) / 32), (unsigned)(m16 / 16));
+  if (prec == 1)
+    k_mv_n<float, kMvNct><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
+                                             n_deg, (const float*)Wd, m16, (float*)KV, ldkv, n, m);
+  else
+    k_mv_n<double, kMvNct><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
+                                              degs, n_deg, (const double*)Wd, m16, (double*)KV,
+                                              ldkv, n, m);
+  return hipGetLastError();
+}
+
+}  // namespace hdf

@@ -1,0 +1,95 @@
+// Launchers of the gfx950 kernels of the HDF hot path (host-callable).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <cstdint>
+
+namespace hdf {
+
+// Device geometry record written by the prep pass (binary64).
+struct GeoDev {
+  double c[8];
+  double R2, R, Reff, inv_unused;
+  double nu2_sum;
+  double rho2_min, rho2_max;
+  double nonfinite;
+};
+
+constexpr int kPrepBlocks = 512;
+constexpr int kNuPairs = 65536;
+constexpr uint64_t kNuSeed = 0x48444600ull;
+
+// Geometry: SoA copy of the points, bounding-box centre, radius, rho^2 range
+// and the ||K||_F sample.  dtype 0 = float32, 1 = float64.
+hipError_t launch_prep(const void* pts, int dtype, int64_t n, int d, int64_t ld, void* x_soa,
+                       int64_t ldx, int kernel, double l, double* partials, GeoDev* geo,
+                       hipStream_t s);
+
+// Weighted Chebyshev moments mu[k][c] = sum_i rho_i^{2k} T_c(t_i), k <= K,
+// c <= 2K, written to `moments` (rows 16*nrt x cols 16*nct, binary64).
+// mode 0: binary64 MFMA; 1: binary32 MFMA; 2: binary32 hi/lo split MFMA.
+int gram_blocks(int64_t n);
+hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                       const GeoDev* geo, double u0, double u1, int K, int mode,
+                       double* partials, double* moments, hipStream_t s);
+
+// Refinement Gram: G2_k = (Y_k T1_k)^T (Y_k T1_k) for k = 0..K (binary64),
+// written to out[k][32][32]; T1 packed per degree at t1_off[k] (L_k x L_k).
+int gram2_blocks(int64_t n);
+hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                        const GeoDev* geo, double u0, double u1, int K, const double* T1,
+                        const int32_t* t1_off, double* partials, double* out, hipStream_t s);
+
+// Tables of the factor-evaluation kernel.
+struct BuildTables {
+  const int32_t* col_of;     // loop-order iteration -> harmonic row (or -1)
+  const void* chain;         // (level, b, n) -> (A, B) pairs, storage type
+  const int32_t* q_len;      // per radial row: L
+  const int32_t* q_off;      // per radial row: offset into q_coef
+  const void* q_coef;        // radial coefficients, storage type
+  int K, S;
+};
+hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                        const GeoDev* geo, double u0, double u1, const BuildTables& tb,
+                        int prec, void* phi, int64_t ld_phi, void* q, int64_t ld_q,
+                        hipStream_t s);
+
+// Per-degree description for the contraction kernels.
+struct DegDev {
+  int32_t hoff;   // first harmonic row of the degree in phi
+  int32_t nh;     // |H_k|
+  int32_t qoff;   // first radial row in q
+  int32_t s;      // s_k
+  int32_t roff;   // first rank row (k, h=0, l=0)
+  int32_t pad[3];
+};
+struct TileDev {
+  int32_t deg;    // index into DegDev
+  int32_t h0;     // first harmonic of the 16-row tile
+};
+
+// Pass 1: partial[split][row][c] = sum_{i in split} U[i,row] V[i,c]
+// (row = (k,h,l), c < m16, binary64 partials).
+hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                           const DegDev* degs, const TileDev* tiles, int n_tiles, int max_nct,
+                           const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
+                           int64_t split_len, int64_t rank, double* partials, int prec,
+                           hipStream_t s);
+// Reduce over splits: W[row][c] = sum_split partial (binary64) and
+// Wd[row][c] = lambda_row * W (storage type) for pass 2.
+hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t rank, int m16,
+                                const double* lam_row, double* W, void* Wd, int prec,
+                                hipStream_t s);
+// Pass 2: KV[i][c] = sum_rows U[i,row] Wd[row][c].
+hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                           const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
+                           void* KV, int64_t ldkv, int64_t n, int m, int prec, hipStream_t s);
+
+// Adjoint: dX[i] = dF/dx_i for F = sum_c w_c^T U C U^T v_c with the two
+// r x m16 matrices CGv = C (U^T V), CGw = C (U^T W) (storage type).
+hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                          const GeoDev* geo, double u0, double u1, const BuildTables& tb,
+                          const DegDev* degs_by_k, const void* Wm, const void* Vm, int64_t ld,
+                          int m, int m16, const void* CGv, const void* CGw, void* dX,
+                          int64_t lddx, int prec, hipStream_t s);
+
+}  // namespace hdf

@@ -1,0 +1,570 @@
+// Host planner: kernel expansion (data-free) and the small compression step.
+//
+// Radial cores.  The paper (Sec. 3.3 and App. A) expands the degree-p
+// Chebyshev series of the kernel through powers of ||x||, ||y|| and cos(g)
+// and re-expands the powers of cos(g) in Gegenbauer polynomials.  That route
+// needs exact arithmetic (the power coefficients cancel catastrophically,
+// Sec. 3.7).  The same degree-k coefficient function is obtained here
+// directly, in extended precision, from the Rodrigues form of the Gegenbauer
+// projection: with F(S) = f(sqrt(S)) (a Chebyshev series in S = s^2 since f
+// is even), U = |z_x|^2, V = |z_y|^2 and w = sqrt(UV),
+//
+//   coeff of C_k^alpha(t) in F(U + V - 2 w t)
+//     = w^k (-1)^k (k+alpha) Gamma(alpha) / (sqrt(pi) Gamma(alpha+k+1/2))
+//       * int_{-1}^{1} F^{(k)}(U + V - 2 w t) (1 - t^2)^{k+alpha-1/2} dt,
+//
+// (k integrations by parts of the projection against Rodrigues' formula),
+// so no division by w^k is ever performed.  Multiplying by Z_k (addition
+// theorem) and 4^-k (|z| = rho/2) gives the core as a polynomial in
+// (rho_x^2, rho_y^2), which is sampled on a tensor Chebyshev grid and turned
+// into Chebyshev coefficients by a 2-D DCT (exact for its degree).  The
+// integral is exact by Gauss-Legendre (d odd: the weight is a polynomial) or
+// Gauss-Chebyshev of the second kind (d even: weight sqrt(1-t^2) times a
+// polynomial).
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <stdexcept>
+
+namespace hdf {
+
+typedef long double ld;
+static const ld kPiL = 3.141592653589793238462643383279502884L;
+
+double kernel_value(int kind, double r, double l) {
+  switch (kind) {
+    case 0: return std::exp(-(r * r) / (2.0 * l * l));
+    case 1: return 1.0 / (1.0 + (r * r) / (l * l));
+    case 2: { double z = std::sqrt(3.0) * r / l; return (1.0 + z) * std::exp(-z); }
+    case 3: { double z = std::sqrt(5.0) * r / l; return (1.0 + z + z * z / 3.0) * std::exp(-z); }
+  }
+  return NAN;
+}
+
+double kernel_dl(int kind, double r, double l) {
+  switch (kind) {
+    case 0: return kernel_value(0, r, l) * r * r / (l * l * l);
+    case 1: { double k = kernel_value(1, r, l); return 2.0 * r * r * k * k / (l * l * l); }
+    case 2: { double z = std::sqrt(3.0) * r / l; return z * z * std::exp(-z) / l; }
+    case 3: { double z = std::sqrt(5.0) * r / l; return (z / 3.0) * (1.0 + z) * z * std::exp(-z) / l; }
+  }
+  return NAN;
+}
+
+// ---------------------------------------------------------------- DCT-II
+// Radix-2 iterative complex FFT (in place, forward sign -1).
+static void fft(std::vector<std::complex<double>>& x) {
+  const size_t n = x.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(x[i], x[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    const double ang = -2.0 * M_PI / (double)len;
+    for (size_t i = 0; i < n; i += len) {
+      for (size_t k = 0; k < len / 2; ++k) {
+        std::complex<double> w(std::cos(ang * (double)k), std::sin(ang * (double)k));
+        std::complex<double> u = x[i + k], v = x[i + k + len / 2] * w;
+        x[i + k] = u + v;
+        x[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+// y_i = sum_j f_j cos(pi i (2j+1) / (2n)) via one length-n FFT (Makhoul).
+static void dct2(const std::vector<double>& f, std::vector<double>& y) {
+  const size_t n = f.size();
+  std::vector<std::complex<double>> v(n);
+  for (size_t j = 0; j < n / 2; ++j) {
+    v[j] = f[2 * j];
+    v[n - 1 - j] = f[2 * j + 1];
+  }
+  fft(v);
+  y.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    const double ang = -M_PI * (double)i / (2.0 * (double)n);
+    y[i] = (v[i] * std::complex<double>(std::cos(ang), std::sin(ang))).real();
+  }
+}
+
+void chebyshev_coeffs(int kind, double D, double l, int n, bool derivative, double* a) {
+  std::vector<double> f(n), y;
+  for (int j = 0; j < n; ++j) {
+    const double s = std::cos(M_PI * (j + 0.5) / n);
+    const double r = D * std::fabs(s);
+    f[j] = derivative ? kernel_dl(kind, r, l) : kernel_value(kind, r, l);
+  }
+  dct2(f, y);
+  for (int i = 0; i < n; ++i) a[i] = (i % 2) ? 0.0 : y[i] * 2.0 / n;
+  a[0] *= 0.5;
+}
+
+int choose_degree(const double* a, int n, double thr, int p_max, double* tail_at_p) {
+  std::vector<double> tail(n, 0.0);
+  double acc = 0.0;
+  for (int i = n - 1; i >= 1; --i) {
+    acc += std::fabs(a[i]);
+    tail[i - 1] = acc;
+  }
+  for (int p = 0; p <= std::min(p_max, n - 1); p += 2) {
+    if (tail[p] <= thr) {
+      if (tail_at_p) *tail_at_p = tail[p];
+      return p;
+    }
+  }
+  return -1;
+}
+
+// ------------------------------------------------------------ quadrature
+static void gauss_legendre(int n, std::vector<ld>& x, std::vector<ld>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    ld z = cosl(kPiL * (i + 0.75L) / (n + 0.5L));
+    ld dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      ld p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        ld p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      ld dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-21L * (1 + fabsl(z))) {
+        // refresh the derivative at the converged node
+        p0 = 1; p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          ld p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1);
+        break;
+      }
+    }
+    x[i] = z;
+    w[i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Clenshaw evaluation of sum_n c_n T_n(x).
+static ld clenshaw(const std::vector<ld>& c, ld x) {
+  ld b1 = 0, b2 = 0;
+  for (int n = (int)c.size() - 1; n >= 1; --n) {
+    ld b0 = 2 * x * b1 - b2 + c[n];
+    b2 = b1;
+    b1 = b0;
+  }
+  return x * b1 - b2 + (c.empty() ? 0 : c[0]);
+}
+
+// d/dx of a Chebyshev series (coefficients), length shrinks by one.
+static std::vector<ld> cheb_derivative(const std::vector<ld>& c) {
+  const int N = (int)c.size() - 1;
+  if (N <= 0) return std::vector<ld>(1, 0);
+  std::vector<ld> d(N + 2, 0);
+  for (int n = N; n >= 1; --n) d[n - 1] = d[n + 1] + 2 * n * c[n];
+  d[0] *= 0.5L;
+  d.resize(N);
+  return d;
+}
+
+void radial_interval(double rmin2, double rmax2, double* u0, double* u1) {
+  double a = rmin2, b = rmax2;
+  if (!(b > a)) {
+    a = 0.0;
+    if (!(b > 0.0)) b = 1.0;
+  }
+  *u0 = a;
+  *u1 = b;
+}
+
+void radial_cores(const double* a, int p, int d, double u0, double u1,
+                  std::vector<std::vector<double>>& cores) {
+  const int K = p / 2;
+  const ld alpha = (ld)(d - 2) / 2;
+  // F(S) = sum_n c_n T_n(2S - 1), c_n = a_{2n}; derivatives in S carry 2^k.
+  std::vector<std::vector<ld>> der(K + 1);
+  std::vector<ld> cur(K + 1);
+  for (int n = 0; n <= K; ++n) cur[n] = a[2 * n];
+  for (int k = 0; k <= K; ++k) {
+    der[k] = cur;
+    std::vector<ld> nx = cheb_derivative(cur);
+    for (auto& v : nx) v *= 2;
+    cur = nx;
+  }
+  const ld a0 = ((ld)u0 + (ld)u1) / 2, a1 = ((ld)u1 - (ld)u0) / 2;
+  cores.assign(K + 1, std::vector<double>());
+  for (int k = 0; k <= K; ++k) {
+    const int L = K - k + 1;
+    // quadrature for int F^(k)(A - B t) (1 - t^2)^{k + alpha - 1/2} dt
+    std::vector<ld> tq, wq;
+    if (d % 2) {
+      const int beta = k + (d - 3) / 2;
+      const int deg = (K - k) + 2 * beta;
+      gauss_legendre(deg / 2 + 1, tq, wq);
+      for (size_t q = 0; q < tq.size(); ++q) wq[q] *= powl(1 - tq[q] * tq[q], beta);
+    } else {
+      const int m = k + (d - 4) / 2;            // (1-t^2)^{m} sqrt(1-t^2)
+      const int deg = (K - k) + 2 * m;
+      const int nq = deg / 2 + 1;
+      tq.resize(nq);
+      wq.resize(nq);
+      for (int q = 0; q < nq; ++q) {
+        const ld th = kPiL * (q + 1) / (nq + 1);
+        tq[q] = cosl(th);
+        wq[q] = kPiL / (nq + 1) * sinl(th) * sinl(th) * powl(1 - tq[q] * tq[q], m);
+      }
+    }
+    const ld pref = ((k % 2) ? -1 : 1) * 2 * powl(kPiL, alpha + 0.5L) * powl(0.25L, k) /
+                    tgammal(alpha + k + 0.5L);
+    std::vector<ld> th(L), r2(L);
+    for (int i = 0; i < L; ++i) {
+      th[i] = kPiL * (i + 0.5L) / L;
+      r2[i] = a0 + a1 * cosl(th[i]);
+    }
+    std::vector<ld> G((size_t)L * L);
+    for (int i = 0; i < L; ++i)
+      for (int j = i; j < L; ++j) {
+        const ld A = (r2[i] + r2[j]) / 4, B = sqrtl(r2[i] * r2[j]) / 2;
+        ld acc = 0;
+        for (size_t q = 0; q < tq.size(); ++q) acc += wq[q] * clenshaw(der[k], 2 * (A - B * tq[q]) - 1);
+        G[(size_t)i * L + j] = G[(size_t)j * L + i] = pref * acc;
+      }
+    // 2-D DCT: M[a][b] = (2/L)^2 sum_ij G_ij cos(a th_i) cos(b th_j), halved at 0
+    std::vector<ld> C((size_t)L * L);
+    for (int aa = 0; aa < L; ++aa)
+      for (int i = 0; i < L; ++i) C[(size_t)aa * L + i] = cosl(aa * th[i]);
+    std::vector<ld> T1((size_t)L * L, 0);
+    for (int aa = 0; aa < L; ++aa)
+      for (int j = 0; j < L; ++j) {
+        ld s = 0;
+        for (int i = 0; i < L; ++i) s += C[(size_t)aa * L + i] * G[(size_t)i * L + j];
+        T1[(size_t)aa * L + j] = s;
+      }
+    std::vector<double>& M = cores[k];
+    M.assign((size_t)L * L, 0.0);
+    for (int aa = 0; aa < L; ++aa)
+      for (int bb = 0; bb < L; ++bb) {
+        ld s = 0;
+        for (int j = 0; j < L; ++j) s += T1[(size_t)aa * L + j] * C[(size_t)bb * L + j];
+        s *= (ld)4 / ((ld)L * L);
+        if (aa == 0) s *= 0.5L;
+        if (bb == 0) s *= 0.5L;
+        M[(size_t)aa * L + bb] = (double)s;
+      }
+    // exact symmetry (the grid values are symmetric; rounding may differ)
+    for (int aa = 0; aa < L; ++aa)
+      for (int bb = aa + 1; bb < L; ++bb) {
+        double v = 0.5 * (M[(size_t)aa * L + bb] + M[(size_t)bb * L + aa]);
+        M[(size_t)aa * L + bb] = M[(size_t)bb * L + aa] = v;
+      }
+  }
+}
+
+// ------------------------------------------------------------ harmonics
+static void index_rec(int d, int depth, int upper, std::vector<int32_t>& prefix,
+                      std::vector<int32_t>& out) {
+  if (depth == d - 2) {
+    for (int m = -upper; m <= upper; ++m) {
+      out.insert(out.end(), prefix.begin(), prefix.end());
+      out.push_back(m);
+    }
+    return;
+  }
+  for (int mu = 0; mu <= upper; ++mu) {
+    prefix.push_back(mu);
+    index_rec(d, depth + 1, mu, prefix, out);
+    prefix.pop_back();
+  }
+}
+
+void index_set(int d, int k, std::vector<int32_t>& out) {
+  out.clear();
+  std::vector<int32_t> prefix;
+  index_rec(d, 1, k, prefix, out);
+}
+
+static int64_t binom(int64_t n, int64_t k) {
+  if (k < 0 || n < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int64_t i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+int64_t index_count(int d, int k) {
+  if (k < 0) return 0;
+  return binom(k + d - 1, k) - (k >= 2 ? binom(k + d - 3, k - 2) : 0);
+}
+
+double sphere_area(int d) {
+  return (double)(2 * powl(kPiL, (ld)d / 2) / tgammal((ld)d / 2));
+}
+
+double tau_threshold(double tol, double nu, int64_t N, int d, int p) {
+  const int K = p / 2;
+  const double area = sphere_area(d);
+  double denom = 0.0;
+  for (int k = 0; k <= K; ++k) denom += (double)index_count(d, k) / area * std::sqrt((double)(K - k + 1));
+  return (tol * nu * (double)N / 2.0) / denom;
+}
+
+void chain_coeffs(int d, int K, ChainCoeffs& out) {
+  out.d = d;
+  out.K = K;
+  const size_t sz = (size_t)(d - 2) * (K + 1) * (K + 1);
+  out.A.assign(sz, 0.0);
+  out.B.assign(sz, 0.0);
+  for (int level = 1; level <= d - 2; ++level) {
+    for (int b = 0; b <= K; ++b) {
+      const ld lam = b + (ld)(d - level - 1) / 2;
+      // log h_n^lam = log(pi) + (1 - 2 lam) log 2 + lgamma(n + 2 lam) - lgamma(n + 1)
+      //               - log(n + lam) - 2 lgamma(lam)
+      auto logh = [&](int n) {
+        return logl(kPiL) + (1 - 2 * lam) * logl(2.0L) + lgammal(n + 2 * lam) - lgammal(n + 1.0L) -
+               logl(n + lam) - 2 * lgammal(lam);
+      };
+      const size_t base = out.idx(level, b, 0);
+      out.A[base + 0] = (double)expl(-0.5L * logh(0));                 // c0
+      out.A[base + 1] = (double)(2 * lam * expl(-0.5L * logh(1)));     // c1
+      for (int n = 1; n + 1 <= K - b; ++n) {
+        const ld an = 2 * (n + lam) / (n + 1) * expl(0.5L * (logh(n) - logh(n + 1)));
+        const ld bn = (n + 2 * lam - 1) / (n + 1) * expl(0.5L * (logh(n - 1) - logh(n + 1)));
+        out.A[base + n + 1] = (double)an;   // step producing P_{n+1}
+        out.B[base + n + 1] = (double)bn;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ eigen
+void jacobi_eigh(int n, double* A, double* w, double* V) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double v = A[i * n + j] * A[i * n + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[p * n + p], aqq = A[q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {           // A <- A J (columns p, q)
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {           // A <- J^T A (rows p, q)
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        A[p * n + q] = A[q * n + p] = 0.0;
+        for (int k = 0; k < n; ++k) {           // V <- V J
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
+}
+
+void compress_degree(int k, int L, const double* G, const double* M, double tau,
+                     double null_rel, DegreeFactor& out) {
+  out.k = k;
+  out.L = L;
+  out.s = 0;
+  out.lam.clear();
+  out.E.clear();
+  out.Ep.clear();
+  std::vector<double> Gc(G, G + (size_t)L * L), wg(L), Vg((size_t)L * L);
+  jacobi_eigh(L, Gc.data(), wg.data(), Vg.data());
+  double gmax = 0.0;
+  for (int i = 0; i < L; ++i) gmax = std::max(gmax, wg[i]);
+  if (!(gmax > 0.0)) return;
+  std::vector<int> kept;
+  for (int i = 0; i < L; ++i)
+    if (wg[i] > null_rel * gmax) kept.push_back(i);
+  const int r = (int)kept.size();
+  // B = diag(sqrt(w)) V_kept^T  (r x L);  A = B M B^T
+  std::vector<double> B((size_t)r * L);
+  for (int i = 0; i < r; ++i)
+    for (int a = 0; a < L; ++a) B[(size_t)i * L + a] = std::sqrt(wg[kept[i]]) * Vg[(size_t)a * L + kept[i]];
+  std::vector<double> BM((size_t)r * L, 0.0), A((size_t)r * r, 0.0);
+  for (int i = 0; i < r; ++i)
+    for (int b = 0; b < L; ++b) {
+      double s = 0.0;
+      for (int a = 0; a < L; ++a) s += B[(size_t)i * L + a] * M[(size_t)a * L + b];
+      BM[(size_t)i * L + b] = s;
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      double s = 0.0;
+      for (int b = 0; b < L; ++b) s += BM[(size_t)i * L + b] * B[(size_t)j * L + b];
+      A[(size_t)i * r + j] = s;
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = i + 1; j < r; ++j) {
+      const double v = 0.5 * (A[(size_t)i * r + j] + A[(size_t)j * r + i]);
+      A[(size_t)i * r + j] = A[(size_t)j * r + i] = v;
+    }
+  std::vector<double> mu(r), W((size_t)r * r);
+  jacobi_eigh(r, A.data(), mu.data(), W.data());
+  std::vector<int> ord(r);
+  for (int i = 0; i < r; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const double ax = std::fabs(mu[x]), ay = std::fabs(mu[y]);
+    if (ax != ay) return ax > ay;
+    const int nx = mu[x] < 0, ny = mu[y] < 0;
+    if (nx != ny) return nx < ny;
+    return x < y;
+  });
+  for (int c = 0; c < r; ++c) {
+    const int i = ord[c];
+    if (!(std::fabs(mu[i]) > tau)) break;
+    std::vector<double> e(L, 0.0), ep(L, 0.0);
+    for (int a = 0; a < L; ++a) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int j = 0; j < r; ++j) {
+        const double v = Vg[(size_t)a * L + kept[j]] * W[(size_t)j * r + i];
+        s1 += v / std::sqrt(wg[kept[j]]);
+        s2 += v * std::sqrt(wg[kept[j]]);
+      }
+      e[a] = s1;
+      ep[a] = s2;
+    }
+    int piv = 0;
+    for (int a = 1; a < L; ++a)
+      if (std::fabs(e[a]) > std::fabs(e[piv])) piv = a;
+    if (e[piv] < 0)
+      for (int a = 0; a < L; ++a) { e[a] = -e[a]; ep[a] = -ep[a]; }
+    out.lam.push_back(mu[i]);
+    out.E.insert(out.E.end(), e.begin(), e.end());
+    out.Ep.insert(out.Ep.end(), ep.begin(), ep.end());
+    out.s++;
+  }
+}
+
+void gram_precondition(int L, const double* G1, double floor_rel, Precond& pc) {
+  pc.L = L;
+  std::vector<double> Gc(G1, G1 + (size_t)L * L), w(L);
+  pc.V1.assign((size_t)L * L, 0.0);
+  jacobi_eigh(L, Gc.data(), w.data(), pc.V1.data());
+  double gmax = 0.0;
+  for (int i = 0; i < L; ++i) gmax = std::max(gmax, w[i]);
+  if (!(gmax > 0.0)) gmax = 1.0;
+  const double floor_v = floor_rel * gmax;
+  pc.lam1c.resize(L);
+  for (int i = 0; i < L; ++i) pc.lam1c[i] = std::max(w[i], floor_v);
+  pc.T1.assign((size_t)L * L, 0.0);
+  for (int a = 0; a < L; ++a)
+    for (int j = 0; j < L; ++j) pc.T1[(size_t)a * L + j] = pc.V1[(size_t)a * L + j] / std::sqrt(pc.lam1c[j]);
+}
+
+void compress_degree_refined(int k, int L, const double* G2, const Precond& pc, const double* M,
+                             double tau, double null_rel, DegreeFactor& out) {
+  out.k = k;
+  out.L = L;
+  out.s = 0;
+  out.lam.clear();
+  out.E.clear();
+  out.Ep.clear();
+  std::vector<double> Gc(G2, G2 + (size_t)L * L), w2(L), V2((size_t)L * L);
+  jacobi_eigh(L, Gc.data(), w2.data(), V2.data());
+  double gmax = 0.0;
+  for (int i = 0; i < L; ++i) gmax = std::max(gmax, w2[i]);
+  if (!(gmax > 0.0)) return;
+  std::vector<int> kept;
+  for (int i = 0; i < L; ++i)
+    if (w2[i] > null_rel * gmax) kept.push_back(i);
+  const int r = (int)kept.size();
+  // R (r x L) = diag(sqrt(w2)) V2_kept^T diag(sqrt(lam1c)) V1^T
+  // T (L x r) = V1 diag(lam1c^-1/2) V2_kept diag(w2^-1/2)  (R T = I)
+  std::vector<double> R((size_t)r * L, 0.0), T((size_t)L * r, 0.0);
+  for (int i = 0; i < r; ++i) {
+    const int ki = kept[i];
+    const double s2 = std::sqrt(w2[ki]);
+    for (int a = 0; a < L; ++a) {
+      double acc = 0.0, acc2 = 0.0;
+      for (int j = 0; j < L; ++j) {
+        acc += V2[(size_t)j * L + ki] * std::sqrt(pc.lam1c[j]) * pc.V1[(size_t)a * L + j];
+        acc2 += pc.V1[(size_t)a * L + j] / std::sqrt(pc.lam1c[j]) * V2[(size_t)j * L + ki];
+      }
+      R[(size_t)i * L + a] = s2 * acc;
+      T[(size_t)a * r + i] = acc2 / s2;
+    }
+  }
+  std::vector<double> RM((size_t)r * L, 0.0), A((size_t)r * r, 0.0);
+  for (int i = 0; i < r; ++i)
+    for (int b = 0; b < L; ++b) {
+      double s = 0.0;
+      for (int a = 0; a < L; ++a) s += R[(size_t)i * L + a] * M[(size_t)a * L + b];
+      RM[(size_t)i * L + b] = s;
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      double s = 0.0;
+      for (int b = 0; b < L; ++b) s += RM[(size_t)i * L + b] * R[(size_t)j * L + b];
+      A[(size_t)i * r + j] = s;
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = i + 1; j < r; ++j) {
+      const double v = 0.5 * (A[(size_t)i * r + j] + A[(size_t)j * r + i]);
+      A[(size_t)i * r + j] = A[(size_t)j * r + i] = v;
+    }
+  std::vector<double> mu(r), W((size_t)r * r);
+  jacobi_eigh(r, A.data(), mu.data(), W.data());
+  std::vector<int> ord(r);
+  for (int i = 0; i < r; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const double ax = std::fabs(mu[x]), ay = std::fabs(mu[y]);
+    if (ax != ay) return ax > ay;
+    const int nx = mu[x] < 0, ny = mu[y] < 0;
+    if (nx != ny) return nx < ny;
+    return x < y;
+  });
+  for (int c = 0; c < r; ++c) {
+    const int i = ord[c];
+    if (!(std::fabs(mu[i]) > tau)) break;
+    std::vector<double> e(L, 0.0), ep(L, 0.0);
+    for (int a = 0; a < L; ++a) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int j = 0; j < r; ++j) {
+        s1 += T[(size_t)a * r + j] * W[(size_t)j * r + i];
+        s2 += R[(size_t)j * L + a] * W[(size_t)j * r + i];
+      }
+      e[a] = s1;
+      ep[a] = s2;
+    }
+    int piv = 0;
+    for (int a = 1; a < L; ++a)
+      if (std::fabs(e[a]) > std::fabs(e[piv])) piv = a;
+    if (e[piv] < 0)
+      for (int a = 0; a < L; ++a) { e[a] = -e[a]; ep[a] = -ep[a]; }
+    out.lam.push_back(mu[i]);
+    out.E.insert(out.E.end(), e.begin(), e.end());
+    out.Ep.insert(out.Ep.end(), ep.begin(), ep.end());
+    out.s++;
+  }
+}
+
+}  // namespace hdf

@@ -1,0 +1,85 @@
+// Host planner of the HDF build: the data-free expansion of the kernel and
+// the small dense linear algebra of the compression step.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace hdf {
+
+constexpr int kChebNodes = 8192;     // first-kind nodes of the Chebyshev transform
+constexpr int kMaxDim = 8;
+
+// k(r; l) and dk/dl for the four kernels (kind = hdf_kernel value).
+double kernel_value(int kind, double r, double l);
+double kernel_dl(int kind, double r, double l);
+
+// Chebyshev coefficients of f(s) = k(D|s|; l) from the DCT-II at n first-kind
+// nodes (n a power of two); odd coefficients set to zero.
+void chebyshev_coeffs(int kind, double D, double l, int n, bool derivative, double* a);
+
+// Smallest even p <= p_max with sum_{i>p}|a_i| <= thr; -1 if none.
+int choose_degree(const double* a, int n, double thr, int p_max, double* tail_at_p);
+
+// Radial cores M_k (k = 0..p/2), row-major, L_k = p/2 - k + 1, basis
+// T_a(t), t = (2 rho^2 - u0 - u1)/(u1 - u0); Z_k folded in.
+void radial_cores(const double* a, int p, int d, double u0, double u1,
+                  std::vector<std::vector<double>>& cores);
+
+// Index set H_k (flat, d-2 ints per harmonic) in the enumeration order.
+void index_set(int d, int k, std::vector<int32_t>& out);
+int64_t index_count(int d, int k);
+double sphere_area(int d);
+
+// Symmetric eigendecomposition (cyclic Jacobi): A (n x n row-major, destroyed)
+// -> eigenvalues w (unsorted) and eigenvectors as columns of V (row-major).
+void jacobi_eigh(int n, double* A, double* w, double* V);
+
+// Interval of rho^2 carrying the radial basis (widened when degenerate).
+void radial_interval(double rmin2, double rmax2, double* u0, double* u1);
+
+// Per-degree compression from the radial Gram G (L x L) and core M (L x L).
+struct DegreeFactor {
+  int k = 0, L = 0, s = 0;
+  std::vector<double> lam;   // s kept eigenvalues, ordered
+  std::vector<double> E;     // L x s, column-major by l: E[l*L + a]
+  std::vector<double> Ep;    // L x s, column-major by l
+};
+void compress_degree(int k, int L, const double* G, const double* M, double tau,
+                     double null_rel, DegreeFactor& out);
+
+// Two-pass (CholeskyQR2-style) compression.  Pass 1: from the radial Gram G1
+// (L x L) build the preconditioner T1 = V1 diag(lam1c)^{-1/2} (L x L,
+// row-major), eigenvalues clamped from below at floor_rel * max.  Pass 2:
+// G2 = (Y T1)^T (Y T1) is recomputed from the data; with G2 = V2 L2 V2^T,
+// R = diag(sqrt(L2)) V2^T diag(sqrt(lam1c)) V1^T satisfies Y = Q R with Q
+// orthonormal to working accuracy, and the degree is compressed from
+// eig(R M R^T) as in the single-pass routine.
+struct Precond {
+  int L = 0;
+  std::vector<double> V1, lam1c, T1;   // L x L row-major; T1 = V1 diag(lam1c^-1/2)
+};
+void gram_precondition(int L, const double* G1, double floor_rel, Precond& pc);
+void compress_degree_refined(int k, int L, const double* G2, const Precond& pc, const double* M,
+                             double tau, double null_rel, DegreeFactor& out);
+
+// The kernel-matrix threshold tau of the Frobenius-form error budget.
+double tau_threshold(double tol, double nu, int64_t N, int d, int p);
+
+// Normalised Gegenbauer chain recurrences of the solid harmonics.
+//   level j = 1..d-2 (coordinate x_j, partial radius r_j^2), lower index b:
+//   P_0 = c0, P_1 = c1 * x, P_{n+1} = A_n x P_n - B_n r^2 P_{n-1}.
+// Values are r^n C_n^lam(x/r) / sqrt(h_n^lam), lam = b + (d-j-1)/2.
+struct ChainCoeffs {
+  int d = 0, K = 0;
+  // layout [level-1][b][n] with n = 0..K (entries for n < 2 hold c0, c1)
+  std::vector<double> A, B;        // size (d-2)*(K+1)*(K+1)
+  double c0(int level, int b) const { return A[idx(level, b, 0)]; }
+  double c1(int level, int b) const { return A[idx(level, b, 1)]; }
+  std::size_t idx(int level, int b, int n) const {
+    return ((std::size_t)(level - 1) * (K + 1) + b) * (K + 1) + n;
+  }
+};
+void chain_coeffs(int d, int K, ChainCoeffs& out);
+
+}  // namespace hdf

@@ -1,0 +1,264 @@
+"""Python binding of the HDF C ABI (include/hdf.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the computation runs in the library's kernels.  The
+library must have been built in-tree (``__graft_entry__.build()``); importing
+this module without it raises, there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libhdf.so")
+
+KERNELS = {"gaussian": 0, "cauchy": 1, "matern32": 2, "matern52": 3}
+HDF_FP64, HDF_MIXED = 0, 1
+HDF_MAX_DEGREE = 60
+STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
+          -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP"}
+
+EXPORTS = ["hdf_build", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
+           "hdf_copy_factor", "hdf_free", "hdf_status_string", "hdf_last_error",
+           "hdf_plan_chebyshev", "hdf_plan_degree", "hdf_plan_cores", "hdf_plan_index_set"]
+
+
+class HDFInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_dim", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_points", ctypes.c_int64),
+        ("degree_p", ctypes.c_int32), ("n_degrees", ctypes.c_int32),
+        ("n_harmonics", ctypes.c_int64), ("n_radial", ctypes.c_int64), ("rank", ctypes.c_int64),
+        ("tau", ctypes.c_double), ("nu", ctypes.c_double), ("cheb_tail", ctypes.c_double),
+        ("center_radius", ctypes.c_double), ("rho2_min", ctypes.c_double),
+        ("rho2_max", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
+        ("t_prep_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double),
+        ("t_gram_ms", ctypes.c_double), ("t_compress_ms", ctypes.c_double),
+        ("t_build_ms", ctypes.c_double),
+        ("s_k", ctypes.c_int32 * (HDF_MAX_DEGREE // 2 + 1)),
+    ]
+
+
+class HDFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.hdf_build.argtypes = [vp, i32, i64, i32, i64, i32, dbl, dbl, i32, vp, ctypes.POINTER(vp)]
+    L.hdf_matvec.argtypes = [vp, vp, i64, i64, vp, i64, vp]
+    L.hdf_backward.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl), vp, i64, vp]
+    L.hdf_info.argtypes = [vp, ctypes.POINTER(HDFInfo)]
+    L.hdf_get_plan.argtypes = [vp, vp, vp, vp, vp]
+    L.hdf_copy_factor.argtypes = [vp, vp, i64, vp, i64, vp]
+    L.hdf_free.argtypes = [vp]
+    L.hdf_free.restype = None
+    L.hdf_status_string.argtypes = [i32]
+    L.hdf_status_string.restype = ctypes.c_char_p
+    L.hdf_last_error.restype = ctypes.c_char_p
+    L.hdf_plan_chebyshev.argtypes = [i32, dbl, dbl, i32, i32, vp]
+    L.hdf_plan_degree.argtypes = [vp, i32, dbl, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.hdf_plan_cores.argtypes = [vp, i32, i32, dbl, dbl, vp]
+    L.hdf_plan_index_set.argtypes = [i32, i32, vp, ctypes.POINTER(i64)]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("hdf_free", "hdf_status_string", "hdf_last_error"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise HDFError(status, lib().hdf_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev2d(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() == 1:
+        t = t.unsqueeze(1)
+    if t.dim() != 2 or t.stride(1) != 1:
+        t = t.contiguous()
+    return t
+
+
+class Factor:
+    """Handle of a built HDF factor K ~ U D U^T (owns the library handle)."""
+
+    def __init__(self, X, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None):
+        L = lib()
+        if precision is None:
+            precision = HDF_FP64 if X.dtype == torch.float64 else HDF_MIXED
+        dtype = torch.float64 if precision == HDF_FP64 else torch.float32
+        X = _dev2d(X, dtype, "X")
+        self.n, self.d = X.shape
+        self.dtype = dtype
+        self.precision = precision
+        self.kernel = kernel
+        self.lengthscale = float(lengthscale)
+        self.tol = float(tol)
+        self.device = X.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(X.device):
+            _check(L.hdf_build(X.data_ptr(), 0 if dtype == torch.float32 else 1, self.n, self.d,
+                               X.stride(0), KERNELS[kernel], self.lengthscale, self.tol,
+                               precision, _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hdf_free(h)
+            self._h = None
+
+    # -- application ------------------------------------------------------
+    def matvec(self, V, out=None):
+        """K~ V for V of shape (n,) or (n, m)."""
+        squeeze = V.dim() == 1
+        V2 = _dev2d(V, self.dtype, "V")
+        if V2.shape[0] != self.n:
+            raise ValueError("V must have n rows")
+        m = V2.shape[1]
+        if out is None:
+            out = torch.empty((self.n, m), dtype=self.dtype, device=V2.device)
+        _check(lib().hdf_matvec(self._h, V2.data_ptr(), m, V2.stride(0), out.data_ptr(),
+                                out.stride(0), _stream()))
+        return out[:, 0] if squeeze else out
+
+    def backward(self, W, V, need_l=True, need_x=True):
+        """(dF/dl, dF/dX) for F = sum_c w_c^T K~ v_c (structure frozen)."""
+        W2 = _dev2d(W, self.dtype, "W")
+        V2 = _dev2d(V, self.dtype, "V")
+        if W2.shape != V2.shape or W2.shape[0] != self.n:
+            raise ValueError("W and V must both be n x m")
+        if W2.stride(0) != V2.stride(0):
+            W2, V2 = W2.contiguous(), V2.contiguous()
+        m = W2.shape[1]
+        dl = ctypes.c_double(0.0)
+        dX = torch.empty((self.n, self.d), dtype=self.dtype, device=W2.device) if need_x else None
+        _check(lib().hdf_backward(self._h, W2.data_ptr(), V2.data_ptr(), m, W2.stride(0),
+                                  ctypes.byref(dl) if need_l else None,
+                                  dX.data_ptr() if need_x else None, self.d, _stream()))
+        return (dl.value if need_l else None), dX
+
+    # -- inspection -------------------------------------------------------
+    def info(self):
+        inf = HDFInfo()
+        _check(lib().hdf_info(self._h, ctypes.byref(inf)))
+        out = {name: getattr(inf, name) for name, _ in HDFInfo._fields_ if name != "s_k"}
+        out["s_k"] = [inf.s_k[k] for k in range(inf.n_degrees)]
+        return out
+
+    def plan(self):
+        import numpy as np
+        inf = self.info()
+        H, S, d, p = inf["n_harmonics"], inf["n_radial"], self.d, inf["degree_p"]
+        K = p // 2
+        ncoef = sum((K - k + 1) * s for k, s in enumerate(inf["s_k"]))
+        table = np.zeros((max(H, 1), d - 1), dtype=np.int32)
+        lam = np.zeros(max(S, 1))
+        coef = np.zeros(max(ncoef, 1))
+        a = np.zeros(p + 1)
+        _check(lib().hdf_get_plan(self._h, table.ctypes.data, lam.ctypes.data, coef.ctypes.data,
+                                  a.ctypes.data))
+        return dict(index_table=table[:H], lam=lam[:S], radial_coef=coef[:ncoef], a=a, info=inf)
+
+    def factor_parts(self):
+        """(phi, q) copies: H x n harmonics and S x n radial functions."""
+        inf = self.info()
+        phi = torch.empty((inf["n_harmonics"], self.n), dtype=self.dtype, device=self.device)
+        q = torch.empty((inf["n_radial"], self.n), dtype=self.dtype, device=self.device)
+        _check(lib().hdf_copy_factor(self._h, phi.data_ptr() if phi.numel() else None, self.n,
+                                     q.data_ptr() if q.numel() else None, self.n, _stream()))
+        return phi, q
+
+
+def build(X, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None):
+    return Factor(X, kernel, lengthscale, tol, precision)
+
+
+class HDFMatvec(torch.autograd.Function):
+    """y = K~(X, l) V with gradients for V, l and X (structure frozen at build)."""
+
+    @staticmethod
+    def forward(ctx, X, lengthscale, V, factor):
+        ctx.factor = factor
+        ctx.save_for_backward(V)
+        return factor.matvec(V)
+
+    @staticmethod
+    def backward(ctx, G):
+        (V,) = ctx.saved_tensors
+        f = ctx.factor
+        G = G.contiguous()
+        dV = f.matvec(G) if ctx.needs_input_grad[2] else None
+        need_l, need_x = ctx.needs_input_grad[1], ctx.needs_input_grad[0]
+        dl = dX = None
+        if need_l or need_x:
+            Vm = V if V.dim() == 2 else V.unsqueeze(1)
+            Gm = G if G.dim() == 2 else G.unsqueeze(1)
+            dlv, dX = f.backward(Gm, Vm, need_l=need_l, need_x=need_x)
+            if need_l:
+                dl = torch.tensor(dlv, dtype=f.dtype, device=G.device)
+        return dX, dl, dV, None
+
+
+# -- host planner (no device work) ------------------------------------------
+def plan_chebyshev(kernel, D, lengthscale, n_nodes=8192, derivative=False):
+    import numpy as np
+    a = np.zeros(n_nodes)
+    _check(lib().hdf_plan_chebyshev(KERNELS[kernel], float(D), float(lengthscale), n_nodes,
+                                    int(derivative), a.ctypes.data))
+    return a
+
+
+def plan_degree(a, eps, nu, p_max=HDF_MAX_DEGREE):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    p = ctypes.c_int(0)
+    tail = ctypes.c_double(0.0)
+    _check(lib().hdf_plan_degree(a.ctypes.data, len(a), float(eps), float(nu), p_max,
+                                 ctypes.byref(p), ctypes.byref(tail)))
+    return p.value, tail.value
+
+
+def plan_cores(a, p, d, u0, u1):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    K = p // 2
+    tot = sum((K - k + 1) ** 2 for k in range(K + 1))
+    out = np.zeros(tot)
+    _check(lib().hdf_plan_cores(a.ctypes.data, p, d, float(u0), float(u1), out.ctypes.data))
+    cores, o = [], 0
+    for k in range(K + 1):
+        L = K - k + 1
+        cores.append(out[o:o + L * L].reshape(L, L))
+        o += L * L
+    return cores
+
+
+def plan_index_set(d, k):
+    import numpy as np
+    cnt = ctypes.c_int64(0)
+    _check(lib().hdf_plan_index_set(d, k, None, ctypes.byref(cnt)))
+    t = np.zeros((max(cnt.value, 1), d - 2), dtype=np.int32)
+    _check(lib().hdf_plan_index_set(d, k, t.ctypes.data, ctypes.byref(cnt)))
+    return t[:cnt.value]

@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU tests: run the HIP path and the oracle on the
+same inputs and compare what is unique (knife-edge rank and degree decisions
+are reported as ambiguous instead of compared)."""
+import numpy as np
+import torch
+
+from oracle import harmonics, hdf as ohdf
+
+AMBIG = 1e-9
+
+
+def to_dev(X, dtype):
+    return torch.tensor(np.ascontiguousarray(X), dtype=dtype, device="cuda")
+
+
+def gpu_build(X, kernel, l, tol, mixed=False):
+    from paper_2202_03655_amd import hdf
+    dt = torch.float32 if mixed else torch.float64
+    Xd = to_dev(X, dt)
+    f = hdf.Factor(Xd, kernel, l, tol, precision=hdf.HDF_MIXED if mixed else hdf.HDF_FP64)
+    return f, Xd
+
+
+def oracle_for(X, kernel, l, tol, mixed=False):
+    """Oracle on exactly the values the device consumed."""
+    Xo = np.asarray(X, dtype=np.float32 if mixed else np.float64).astype(np.float64)
+    return ohdf.build(Xo, kernel, l, tol), Xo
+
+
+def ambiguous_ranks(st):
+    """True if a rank or degree decision lies within AMBIG of its threshold."""
+    for dd in st["deg"]:
+        lam = np.abs(dd["lam_all"])
+        if np.any(np.abs(lam - st["tau"]) <= AMBIG * st["tau"]):
+            return True
+    if st["tail_at_p"] is not None:
+        thr = st["tol"] * st["nu"] / 2
+        if abs(st["tail_at_p"] - thr) <= AMBIG * thr:
+            return True
+    return False
+
+
+def oracle_phi(st, kept):
+    """H x N harmonics of the kept degrees, canonical order (oracle)."""
+    Sh = harmonics.solid_harmonics(st["geo"]["xt"], st["K"], degrees=kept)
+    return np.concatenate([Sh[k].T for k in kept], axis=0)
+
+
+def rel_fro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
