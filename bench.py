@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the HDF hot path on one MI355X.
+
+One step = the whole hot path on one batch: factor build (geometry, degree,
+radial Gram, compression, factor evaluation) + K~V with 16 right-hand sides
++ the adjoint (dF/dl and dF/dX of w^T K~ v), inputs resident in HBM.
+Prints one JSON line.  Default workload: N = 1e6 points in d = 5 (10-component
+Gaussian mixture scaled to max-norm 1), Cauchy kernel l = 1, tol 1e-4,
+binary32 MFMA path; the plain binary64 path on the same inputs is timed
+beside it, and the FP64 CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "factor-build Mpoints/s + K~V GFLOP/s at tol 1e-4, FP32-MFMA vs plain FP64 on GPU"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2202_03655_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.txt")
+
+WORKLOAD_DESC = {
+    "gmm5_cauchy_1e-4": "N=1e6 d=5 10-component Gaussian mixture (means N(0,4I), cov 0.25I) centred "
+                        "and scaled to max-norm 1; Cauchy l=1; tol 1e-4; 16 RHS",
+    "gmm5_cauchy_1e-3": "N=1e6 d=5 10-component Gaussian mixture scaled to max-norm 1; Cauchy l=1; "
+                        "tol 1e-3; 16 RHS",
+    "cube4_gauss": "N=2e5 uniform in [-1,1]^4; Gaussian l=0.7; tol 1e-5",
+    "ball3_gauss": "N=2000 uniform in the unit ball, d=3; Gaussian l=1; tol 1e-6",
+    "shell6_matern52_l8": "N=5e5 shell r in [0.9,1.1], d=6; Matern-5/2 l=8; tol 1e-7",
+}
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries (or None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = kernel_source_hash()
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        # kernel workload source_sha fetch_kib write_kib copy_factor
+        if len(f) >= 6 and f[0] == kernel and f[1] == workload:
+            if f[2] != src:
+                return None          # kernel changed since the counters were taken
+            return (float(f[3]) + float(f[4])) * 1024.0 * float(f[5])
+    return None
+
+
+def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
+    import torch
+    from paper_2202_03655_amd import hdf
+    cfg = hdf_cfg(wname)
+    dt = torch.float32 if precision == "mixed" else torch.float64
+    prec = hdf.HDF_MIXED if precision == "mixed" else hdf.HDF_FP64
+    Xd = torch.tensor(X, dtype=dt, device="cuda")
+    Vd = torch.tensor(V, dtype=dt, device="cuda")
+    Wd = torch.tensor(Wm, dtype=dt, device="cuda")
+    out = torch.empty_like(Vd)
+
+    def step():
+        t0 = time.perf_counter()
+        f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec)
+        t1 = time.perf_counter()
+        f.matvec(Vd, out=out)
+        grads = f.backward(Wd[:, :1], Vd[:, :1]) if with_backward else None
+        return f, t1 - t0, grads
+
+    for _ in range(warmup):
+        f, _, _ = step()
+        f.info()
+        del f
+    torch.cuda.synchronize()
+    rec = dict(build_s=[], k_build=[], k_mv_t=[], k_mv_n=[], k_mv_red=[])
+    t_start = time.perf_counter()
+    info = None
+    for _ in range(steps):
+        f, tb, _ = step()
+        info = f.info()                      # waits for the step's last kernel
+        rec["build_s"].append(tb)
+        rec["k_build"].append(info["t_build_ms"])
+        rec["k_mv_t"].append(info["t_mv_t_ms"])
+        rec["k_mv_n"].append(info["t_mv_n_ms"])
+        rec["k_mv_red"].append(info["t_mv_reduce_ms"])
+        del f
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    # separate matvec timing on a resident factor (wall clock of the call)
+    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec)
+    for _ in range(2):
+        f.matvec(Vd, out=out)
+    torch.cuda.synchronize()
+    reps = max(3, steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.matvec(Vd, out=out)
+    torch.cuda.synchronize()
+    mv_s = (time.perf_counter() - t0) / reps
+    del f
+    avg = {k: sum(v) / len(v) for k, v in rec.items()}
+    return dict(ms_per_step=1e3 * t_total / steps, build_ms=1e3 * avg["build_s"], matvec_ms=1e3 * mv_s,
+                k_build_ms=avg["k_build"], k_mv_t_ms=avg["k_mv_t"], k_mv_n_ms=avg["k_mv_n"],
+                k_mv_reduce_ms=avg["k_mv_red"], info=info)
+
+
+def hdf_cfg(wname):
+    from paper_2202_03655_amd import workloads
+    return workloads.CONFIGS[wname]
+
+
+def cpu_baseline(wname, X, V, n_sample):
+    """The FP64 oracle (as it stands) on the first n_sample points of the workload."""
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(limits=cores)
+    except Exception:                        # pragma: no cover
+        ctx = None
+    from oracle import hdf as ohdf
+    cfg = hdf_cfg(wname)
+    Xs = np.asarray(X[:n_sample], dtype=np.float64)
+    Vs = np.asarray(V[:n_sample], dtype=np.float64)
+    t0 = time.perf_counter()
+    st = ohdf.build(Xs, cfg["kernel"], cfg["l"], cfg["tol"])
+    t1 = time.perf_counter()
+    ohdf.matvec_chunked(st, Vs, chunk=8192)
+    t2 = time.perf_counter()
+    if ctx is not None:
+        ctx.unregister() if hasattr(ctx, "unregister") else None
+    return dict(value=n_sample / (t2 - t0) / 1e6, unit="Mpoints/s", cores=cores, kind="oracle",
+                sample=f"first {n_sample} points of the workload (same cloud, same kernel/l/tol), "
+                       f"oracle build + K~V with {Vs.shape[1]} RHS; build {t1 - t0:.2f}s, "
+                       f"matvec {t2 - t1:.2f}s, rank {st['r']}")
+
+
+def calibrate_copy(nbytes):
+    """Plain device copy of known size, used to scale the PMC byte counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": nbytes, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gmm5_cauchy_1e-4")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--rhs", type=int, default=16)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 comparison path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every box has a single MI355X); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    from paper_2202_03655_amd import hdf, workloads
+    hdf.lib()
+    cfg = workloads.CONFIGS[args.workload]
+    X = workloads.points(args.workload)
+    if args.precision == "mixed":
+        X = X.astype(np.float32).astype(np.float64)     # the values the mixed path consumes
+    N, d = X.shape
+    m = args.rhs
+    V = workloads.rhs(N, m, 7)
+    Wm = workloads.rhs(N, m, 8)
+    with_backward = hasattr(hdf.lib(), "hdf_backward") and _backward_available()
+    print(f"# workload {args.workload}: N={N} d={d} precision={args.precision}", file=sys.stderr, flush=True)
+    res = run_gpu(args.workload, X, V, Wm, args.precision, args.steps, args.warmup, with_backward)
+    info = res["info"]
+    r, H, S = info["rank"], info["n_harmonics"], info["n_radial"]
+    el = 4 if args.precision == "mixed" else 8
+    # algorithmic work per launch
+    build_bytes = N * (d * el + (H + S) * el)
+    mv_flops = 4.0 * N * r * m
+    mvt_bytes = N * (H + S + m) * el
+    mvn_bytes = N * (H + S + m) * el
+    kernels = {"k_build": (res["k_build_ms"], build_bytes), "k_mv_t": (res["k_mv_t_ms"], mvt_bytes),
+               "k_mv_n": (res["k_mv_n_ms"], mvn_bytes)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    t_ms, nbytes = kernels[dom]
+    achieved = nbytes / (t_ms * 1e-3) / 1e9
+    traffic = read_traffic(dom, args.workload)
+    print(f"# step {res['ms_per_step']:.2f} ms (build {res['build_ms']:.2f} ms, matvec {res['matvec_ms']:.3f} ms); "
+          f"kernels build {res['k_build_ms']:.3f} mv_t {res['k_mv_t_ms']:.3f} mv_n {res['k_mv_n_ms']:.3f} ms; "
+          f"p={info['degree_p']} r={r} H={H} S={S}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "value": round(N / (res["ms_per_step"] * 1e-3) / 1e6, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "desc": WORKLOAD_DESC.get(args.workload, ""),
+                   "n_points": N, "dim": d, "kernel": cfg["kernel"], "lengthscale": cfg["l"],
+                   "tol": cfg["tol"], "rhs": m, "precision": args.precision,
+                   "step": "hdf_build + hdf_matvec(16 RHS)" + (" + hdf_backward" if with_backward else "")},
+        "build_mpoints_s": round(N / (res["build_ms"] * 1e-3) / 1e6, 3),
+        "matvec_gflops": round(mv_flops / (res["matvec_ms"] * 1e-3) / 1e9, 1),
+        "kernel_ms": {"build": round(res["k_build_ms"], 4), "matvec_pass1": round(res["k_mv_t_ms"], 4),
+                      "matvec_reduce": round(res["k_mv_reduce_ms"], 4), "matvec_pass2": round(res["k_mv_n_ms"], 4)},
+        "factor": {"p": info["degree_p"], "rank": r, "harmonics": H, "radial": S,
+                   "bytes": info["factor_bytes"]},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (t_ms * 1e-3) / 1e9, 1),
+                     "algorithmic_bytes": nbytes},
+    }
+    if args.precision == "mixed" and not args.no_fp64:
+        r64 = run_gpu(args.workload, X, V, Wm, "fp64", max(2, args.steps // 2), 1, with_backward)
+        out["fp64"] = {"ms_per_step": round(r64["ms_per_step"], 3),
+                       "value": round(N / (r64["ms_per_step"] * 1e-3) / 1e6, 3),
+                       "build_mpoints_s": round(N / (r64["build_ms"] * 1e-3) / 1e6, 3),
+                       "matvec_gflops": round(4.0 * N * r64["info"]["rank"] * m / (r64["matvec_ms"] * 1e-3) / 1e9, 1),
+                       "rank": r64["info"]["rank"]}
+        out["speedup_vs_fp64"] = round(r64["ms_per_step"] / res["ms_per_step"], 3)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, X, V, min(args.cpu_sample, N))
+    print(json.dumps(out), flush=True)
+
+
+def _backward_available():
+    from paper_2202_03655_amd import hdf
+    import torch
+    X = torch.rand((64, 3), dtype=torch.float64, device="cuda")
+    f = hdf.Factor(X, "gaussian", 1.0, 1e-3, precision=hdf.HDF_FP64)
+    try:
+        f.backward(X[:, :1], X[:, :1], need_l=True, need_x=False)
+        return True
+    except hdf.HDFError:
+        return False
+
+
+if __name__ == "__main__":
+    main()

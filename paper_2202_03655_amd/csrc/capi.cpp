@@ -71,15 +71,20 @@ struct hdf_factor {
   int max_s = 0;
   double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_build = -1;
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
+  hipEvent_t ev_mv[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool mv_timed = false;
   // device storage
   DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
       lam_row, moments;
   int n_tiles = 0;
-  // matvec workspace
-  DevBuf ws_part, ws_W, ws_Wd;
+  // matvec / adjoint workspace
+  DevBuf ws_part, ws_W, ws_Wd, bw_GV, bw_GVd, bw_GW, bw_GWd, degs_by_k;
+  hdf::BuildTables tables{};
   ~hdf_factor() {
     if (ev_b0) hipEventDestroy(ev_b0);
     if (ev_b1) hipEventDestroy(ev_b1);
+    for (auto& e : ev_mv)
+      if (e) hipEventDestroy(e);
   }
   size_t elem() const { return prec == HDF_MIXED ? 4 : 8; }
 };
@@ -246,7 +251,7 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   }
   {
     DevBuf t1d, t1o, g2, g2part;
-    const int gb2 = hdf::gram2_blocks(n);
+    const int gb2 = hdf::gram2_blocks(n, K);
     HIPCHK(t1d.ensure(t1_all.size() * 8));
     HIPCHK(t1o.ensure(t1_off.size() * 4));
     HIPCHK(g2.ensure((size_t)(K + 1) * 1024 * 8));
@@ -382,6 +387,13 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
     tb.q_coef = f->q_coef.p;
     tb.K = K;
     tb.S = (int)f->S;
+    f->tables = tb;
+    std::vector<hdf::DegDev> dbk(K + 1);
+    for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
+    for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
+    HIPCHK(f->degs_by_k.ensure(dbk.size() * sizeof(hdf::DegDev)));
+    HIPCHK(hipMemcpyAsync(f->degs_by_k.p, dbk.data(), dbk.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipEventCreate(&f->ev_b0));
     HIPCHK(hipEventCreate(&f->ev_b1));
     HIPCHK(hipEventRecord(f->ev_b0, s));
@@ -394,17 +406,12 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
 }
 
 // ------------------------------------------------------------------ matvec
-static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV,
-                              int64_t ldkv, hipStream_t s, double** W_out) {
+// Pass 1 (W = U^T V, binary64) and the scaled copy Wd = D W for pass 2.
+static hdf_status pass1(hdf_handle h, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
+                        DevBuf& Wd, hipStream_t s, bool timed) {
   const int64_t n = h->N;
   const size_t el = h->elem();
-  if (h->r == 0) {
-    HIPCHK(hipMemset2DAsync(KV, ldkv * el, 0, m * el, n, s));
-    return HDF_OK;
-  }
-  const int m16 = (int)((m + 15) / 16 * 16);
-  int max_nct = h->max_s * (m16 / 16);
-  // splits of the point range for pass 1 (partials <= ~96 MB)
+  const int max_nct = h->max_s * (m16 / 16);
   const size_t per_split = (size_t)h->r * m16 * sizeof(double);
   int n_splits = (int)std::min<int64_t>(256, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
   n_splits = (int)std::min<int64_t>(n_splits, (n + 1023) / 1024);
@@ -413,19 +420,40 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
   split_len = (split_len + 15) / 16 * 16;
   n_splits = (int)((n + split_len - 1) / split_len);
   HIPCHK(h->ws_part.ensure(per_split * n_splits));
-  HIPCHK(h->ws_W.ensure((size_t)h->r * m16 * sizeof(double)));
-  HIPCHK(h->ws_Wd.ensure((size_t)h->r * m16 * el));
+  HIPCHK(W.ensure((size_t)h->r * m16 * sizeof(double)));
+  HIPCHK(Wd.ensure((size_t)h->r * m16 * el));
+  if (timed) {
+    if (!h->ev_mv[0])
+      for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(h->ev_mv[0], s));
+  }
   HIPCHK(hdf::launch_matvec_t(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
                               (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, max_nct, V, ldv, n,
                               (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
                               h->prec, s));
+  if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
   HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
-                                   (const double*)h->lam_row.p, (double*)h->ws_W.p, h->ws_Wd.p,
-                                   h->prec, s));
+                                   (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->prec, s));
+  if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
+  return HDF_OK;
+}
+
+static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV,
+                              int64_t ldkv, hipStream_t s) {
+  const int64_t n = h->N;
+  const size_t el = h->elem();
+  if (h->r == 0) {
+    HIPCHK(hipMemset2DAsync(KV, ldkv * el, 0, m * el, n, s));
+    return HDF_OK;
+  }
+  const int m16 = (int)((m + 15) / 16 * 16);
+  hdf_status st = pass1(h, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
+  if (st != HDF_OK) return st;
   HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
                               (int)h->degs.size(), h->max_s, h->ws_Wd.p, m16, KV, ldkv, n, (int)m,
                               h->prec, s));
-  if (W_out) *W_out = (double*)h->ws_W.p;
+  HIPCHK(hipEventRecord(h->ev_mv[3], s));
+  h->mv_timed = true;
   return HDF_OK;
 }
 
@@ -442,14 +470,96 @@ hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv, void*
   const char* k0 = (const char*)KV;
   const char* k1 = k0 + ((h->N - 1) * ldkv + m) * el;
   if (v0 < k1 && k0 < v1) return fail(HDF_E_ARG, "V and KV overlap");
-  return matvec_impl(h, V, m, ldv, KV, ldkv, (hipStream_t)hip_stream, nullptr);
+  return matvec_impl(h, V, m, ldv, KV, ldkv, (hipStream_t)hip_stream);
 }
 
 hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
                         double* dlength, void* dX, int64_t lddx, void* hip_stream) {
-  (void)Wm; (void)Vm; (void)m; (void)ld; (void)dlength; (void)dX; (void)lddx; (void)hip_stream;
+  g_err.clear();
   if (!h) return fail(HDF_E_ARG, "handle is NULL");
-  return fail(HDF_E_ARG, "hdf_backward: not available in this build");
+  if (!Wm || !Vm) return fail(HDF_E_ARG, "W or V is NULL");
+  if (m < 1 || m > HDF_MAX_RHS) return fail(HDF_E_ARG, "m must be in [1, 256]");
+  if (ld < m) return fail(HDF_E_ARG, "ld must be >= m");
+  if (dX && lddx < h->d) return fail(HDF_E_ARG, "lddx must be >= d");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t el = h->elem();
+  if (!dlength && !dX) return HDF_OK;
+  if (h->r == 0) {
+    if (dlength) *dlength = 0.0;
+    if (dX) HIPCHK(hipMemset2DAsync(dX, lddx * el, 0, h->d * el, h->N, s));
+    return HDF_OK;
+  }
+  const int m16 = (int)((m + 15) / 16 * 16);
+  hdf_status st = pass1(h, Vm, m, ld, m16, h->bw_GV, h->bw_GVd, s, false);
+  if (st != HDF_OK) return st;
+  st = pass1(h, Wm, m, ld, m16, h->bw_GW, h->bw_GWd, s, false);
+  if (st != HDF_OK) return st;
+  if (dX) {
+    // radial rows staged in LDS per launch: at most 64 KiB (values + derivatives)
+    const int max_rows = (int)(65536 / (2 * 64 * el));
+    bool first = true;
+    size_t di = 0;
+    while (di < h->degs.size()) {
+      const int row0 = h->degs[di].qoff;
+      size_t dj = di;
+      while (dj < h->degs.size() && h->degs[dj].qoff + h->degs[dj].s - row0 <= max_rows) ++dj;
+      if (dj == di) return fail(HDF_E_INFEASIBLE, "radial rank of one degree exceeds the adjoint staging");
+      const int row1 = h->degs[dj - 1].qoff + h->degs[dj - 1].s;
+      const int cstep = (m == 1) ? 1 : 4;
+      for (int c0 = 0; c0 < m; c0 += cstep) {
+        const int mc = (int)std::min<int64_t>(cstep, m - c0);
+        HIPCHK(hdf::launch_adjoint(h->x_soa.p, h->dtype, h->ldN, h->N, h->d,
+                                   (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, row0, row1,
+                                   (const hdf::DegDev*)h->degs_by_k.p, Wm, Vm, ld, c0, mc, m16,
+                                   h->bw_GVd.p, h->bw_GWd.p, dX, lddx, first ? 0 : 1, h->prec, s));
+        first = false;
+      }
+      di = dj;
+    }
+  }
+  if (dlength) {
+    // dF/dl = sum_{k,h,c} gw^T (E'_k^T dM_k/dl E'_k) gv, dM/dl from the Chebyshev
+    // coefficients of dk/dl with the structure (degree, radius, basis) frozen.
+    std::vector<double> gv((size_t)h->r * m16), gw((size_t)h->r * m16);
+    HIPCHK(hipMemcpyAsync(gv.data(), h->bw_GV.p, gv.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(gw.data(), h->bw_GW.p, gw.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> da(hdf::kChebNodes);
+    hdf::chebyshev_coeffs(h->kernel, 2.0 * h->geo.R, h->l, hdf::kChebNodes, true, da.data());
+    std::vector<std::vector<double>> dM;
+    hdf::radial_cores(da.data(), h->p, h->d, h->u0, h->u1, dM);
+    double dl = 0.0;
+    for (size_t dj = 0; dj < h->degs.size(); ++dj) {
+      const hdf::DegDev& dg = h->degs[dj];
+      const hdf::DegreeFactor& df = h->deg[h->kept_k[dj]];
+      const int L = df.L, sk = df.s;
+      const std::vector<double>& M = dM[df.k];
+      std::vector<double> MEp((size_t)L * sk, 0.0), dC((size_t)sk * sk, 0.0);
+      for (int a = 0; a < L; ++a)
+        for (int l = 0; l < sk; ++l) {
+          double acc = 0.0;
+          for (int b = 0; b < L; ++b) acc += M[(size_t)a * L + b] * df.Ep[(size_t)l * L + b];
+          MEp[(size_t)a * sk + l] = acc;
+        }
+      for (int l = 0; l < sk; ++l)
+        for (int l2 = 0; l2 < sk; ++l2) {
+          double acc = 0.0;
+          for (int a = 0; a < L; ++a) acc += df.Ep[(size_t)l * L + a] * MEp[(size_t)a * sk + l2];
+          dC[(size_t)l * sk + l2] = acc;
+        }
+      for (int hh = 0; hh < dg.nh; ++hh)
+        for (int c = 0; c < m; ++c)
+          for (int l = 0; l < sk; ++l) {
+            const double gwl = gw[(size_t)(dg.roff + hh * sk + l) * m16 + c];
+            if (gwl == 0.0) continue;
+            double acc = 0.0;
+            for (int l2 = 0; l2 < sk; ++l2) acc += dC[(size_t)l * sk + l2] * gv[(size_t)(dg.roff + hh * sk + l2) * m16 + c];
+            dl += gwl * acc;
+          }
+    }
+    *dlength = dl;
+  }
+  return HDF_OK;
 }
 
 // ------------------------------------------------------------------ info
@@ -482,6 +592,13 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
       h->t_build = ms;
   }
   info->t_build_ms = h->t_build;
+  info->t_mv_t_ms = info->t_mv_reduce_ms = info->t_mv_n_ms = -1.0;
+  if (h->mv_timed && hipEventSynchronize(h->ev_mv[3]) == hipSuccess) {
+    float a = 0.f, b = 0.f, c2 = 0.f;
+    if (hipEventElapsedTime(&a, h->ev_mv[0], h->ev_mv[1]) == hipSuccess) info->t_mv_t_ms = a;
+    if (hipEventElapsedTime(&b, h->ev_mv[1], h->ev_mv[2]) == hipSuccess) info->t_mv_reduce_ms = b;
+    if (hipEventElapsedTime(&c2, h->ev_mv[2], h->ev_mv[3]) == hipSuccess) info->t_mv_n_ms = c2;
+  }
   for (int k = 0; k <= h->K && k <= HDF_MAX_DEGREE / 2; ++k) info->s_k[k] = h->deg[k].s;
   return HDF_OK;
 }

@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -253,8 +254,27 @@ hipError_t launch_prep(const void* pts, int dtype, int64_t n, int d, int64_t ld,
 // Gram blocks follow on the host from T_a T_b = (T_{a+b} + T_{|a-b|}) / 2.
 constexpr int kGramRowTiles = 2;   // k <= 31
 constexpr int kGramColTiles = 4;   // c <= 63
-constexpr int kGramBlocks = 480;
+constexpr int kGramWaves = 4096;   // target wavefronts per Gram launch
 
+// Per-point radial variables: rho^2 = ||(x - c)/R||^2 and the Chebyshev
+// argument t of the radial basis.
+template <typename Tin>
+__device__ __forceinline__ void radial_point(const Tin* __restrict__ x_soa, int64_t ldx, int64_t i,
+                                             int d, const GeoDev* __restrict__ geo, double Reff,
+                                             double u0, double u1, double& rho2, double& t) {
+  double s = 0.0;
+  for (int j = 0; j < d; ++j) {
+    const double v = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+    s += v * v;
+  }
+  rho2 = s;
+  t = (2.0 * s - u0 - u1) / (u1 - u0);
+}
+
+// A 16-point tile feeds four MFMA K-steps: in step e, lane group g (lanes
+// 16g..16g+15) supplies point tile*16 + g + 4e, lane r of the group supplies
+// row / column index r of the two operands.  Any bijection between (g, e)
+// and the 16 points is valid because the points are summed over.
 template <typename Tin, int MODE>
 __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
                                                int d, const GeoDev* __restrict__ geo, double u0,
@@ -273,78 +293,97 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
     for (int b = 0; b < kGramColTiles; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) dacc[a][b][e] = 0.0;
-  const int64_t nchunks = (n + 63) / 64;
-  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
-    V acc[kGramRowTiles][kGramColTiles];
+  const int64_t ntile = (n + 15) / 16;
+  int since_flush = 0;
+  V acc[kGramRowTiles][kGramColTiles];
 #pragma unroll
-    for (int a = 0; a < kGramRowTiles; ++a)
+  for (int a = 0; a < kGramRowTiles; ++a)
 #pragma unroll
-      for (int b = 0; b < kGramColTiles; ++b) acc[a][b] = V{0, 0, 0, 0};
-    // lane group g handles 16 consecutive points of the 64-point chunk
-    for (int s = 0; s < 16; ++s) {
-      const int64_t i = ch * 64 + g * 16 + s;
-      double w[kGramRowTiles], tc[kGramColTiles];
+    for (int b = 0; b < kGramColTiles; ++b) acc[a][b] = V{0, 0, 0, 0};
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    double t[4], w[kGramRowTiles][4], tc[kGramColTiles][4];
 #pragma unroll
-      for (int a = 0; a < kGramRowTiles; ++a) w[a] = 0.0;
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = tile * 16 + g + 4 * e;
+      double rho2 = 0.0, tt = 0.0;
+      if (i < n) radial_point(x_soa, ldx, i, d, geo, Reff, u0, u1, rho2, tt);
+      t[e] = tt;
 #pragma unroll
-      for (int b = 0; b < kGramColTiles; ++b) tc[b] = 0.0;
-      if (i < n) {
-        double rho2 = 0.0;
-        for (int j = 0; j < d; ++j) {
-          const double t = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
-          rho2 += t * t;
-        }
-        const double t = (2.0 * rho2 - u0 - u1) / (u1 - u0);
-#pragma unroll
-        for (int a = 0; a < kGramRowTiles; ++a) {
-          const int k = a * 16 + li;
-          if (a < nrt && k <= K) {
-            double pw = 1.0, base = rho2;
-            for (int e = k; e > 0; e >>= 1) {
-              if (e & 1) pw *= base;
-              base *= base;
-            }
-            w[a] = pw;
+      for (int a = 0; a < kGramRowTiles; ++a) {
+        const int k = a * 16 + li;
+        double pw = 0.0;
+        if (i < n && a < nrt && k <= K) {
+          pw = 1.0;
+          double base = rho2;
+          for (int q = k; q > 0; q >>= 1) {
+            if (q & 1) pw *= base;
+            base *= base;
           }
         }
-        // T_c(t) for c = b*16 + li by the three-term recurrence
-        double tm1 = 1.0, t0 = t;
-        const int cmax = nct * 16;
-        for (int c = 0; c < cmax; ++c) {
-          double tcur;
-          if (c == 0) tcur = 1.0;
-          else if (c == 1) tcur = t;
-          else { tcur = 2.0 * t * t0 - tm1; tm1 = t0; t0 = tcur; }
+        w[a][e] = pw;
+      }
+    }
+    // T_c(t) for c = b*16 + li, four points in flight
+    double tm1[4], t0[4];
 #pragma unroll
-          for (int b = 0; b < kGramColTiles; ++b)
-            if (c == b * 16 + li && c <= 2 * K) tc[b] = tcur;
+    for (int e = 0; e < 4; ++e) { tm1[e] = 1.0; t0[e] = t[e]; }
+#pragma unroll
+    for (int b = 0; b < kGramColTiles; ++b) {
+      if (b >= nct) break;
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        const int c = b * 16 + cc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double cur;
+          if (c == 0) cur = 1.0;
+          else if (c == 1) cur = t[e];
+          else { cur = 2.0 * t[e] * t0[e] - tm1[e]; tm1[e] = t0[e]; t0[e] = cur; }
+          if (cc == li) tc[b][e] = (c <= 2 * K) ? cur : 0.0;
         }
       }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = tile * 16 + g + 4 * e;
 #pragma unroll
       for (int a = 0; a < kGramRowTiles; ++a) {
         if (a >= nrt) continue;
 #pragma unroll
         for (int b = 0; b < kGramColTiles; ++b) {
           if (b >= nct) continue;
+          const double wv = (i < n) ? w[a][e] : 0.0;
           if constexpr (MODE == 2) {
-            const float ah = (float)w[a], al = (float)(w[a] - (double)ah);
-            const float bh = (float)tc[b], bl = (float)(tc[b] - (double)bh);
+            const float ah = (float)wv, al = (float)(wv - (double)ah);
+            const float bh = (float)tc[b][e], bl = (float)(tc[b][e] - (double)bh);
             acc[a][b] = Mfma<float>::run(ah, bh, acc[a][b]);
             acc[a][b] = Mfma<float>::run(ah, bl, acc[a][b]);
             acc[a][b] = Mfma<float>::run(al, bh, acc[a][b]);
           } else {
-            acc[a][b] = Mfma<T>::run((T)w[a], (T)tc[b], acc[a][b]);
+            acc[a][b] = Mfma<T>::run((T)wv, (T)tc[b][e], acc[a][b]);
           }
         }
       }
     }
+    // binary32 accumulators are flushed to binary64 every 4 tiles (64 points)
+    if (MODE != 0 && ++since_flush == 4) {
+      since_flush = 0;
 #pragma unroll
-    for (int a = 0; a < kGramRowTiles; ++a)
+      for (int a = 0; a < kGramRowTiles; ++a)
 #pragma unroll
-      for (int b = 0; b < kGramColTiles; ++b)
+        for (int b = 0; b < kGramColTiles; ++b) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dacc[a][b][e] += (double)acc[a][b][e];
+          for (int e = 0; e < 4; ++e) dacc[a][b][e] += (double)acc[a][b][e];
+          acc[a][b] = V{0, 0, 0, 0};
+        }
+    }
   }
+#pragma unroll
+  for (int a = 0; a < kGramRowTiles; ++a)
+#pragma unroll
+    for (int b = 0; b < kGramColTiles; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dacc[a][b][e] += (double)acc[a][b][e];
   // combine the four waves in a fixed order, one 16x16 tile at a time
   const int rows = nrt * 16, cols = nct * 16;
   double* out = part + (int64_t)blockIdx.x * rows * cols;
@@ -365,6 +404,7 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
     }
 }
 
+// Fixed-order sum over block partial records: out[e] = sum_b part[b][e].
 __global__ void k_gram_fin(const double* __restrict__ part, int nblk, int total,
                            double* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -375,9 +415,9 @@ __global__ void k_gram_fin(const double* __restrict__ part, int nblk, int total,
 }
 
 int gram_blocks(int64_t n) {
-  const int64_t chunks = (n + 63) / 64;
-  int64_t b = (chunks + 3) / 4;
-  if (b > kGramBlocks) b = kGramBlocks;
+  const int64_t tiles = (n + 15) / 16;
+  int64_t b = (tiles + 3) / 4;
+  if (b > kGramWaves / 4) b = kGramWaves / 4;
   if (b < 1) b = 1;
   return (int)b;
 }
@@ -406,15 +446,15 @@ hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int
   return hipGetLastError();
 }
 
-// Second Gram pass (refinement of the compression, binary64 MFMA): for every
-// degree k, G2_k = sum_i z_i z_i^T with z_i = T1_k^T y_i and
+// Second Gram pass (refinement of the compression, binary64 MFMA): for degree
+// k = blockIdx.y, G2_k = sum_i z_i z_i^T with z_i = T1_k^T y_i and
 // y_i[a] = rho_i^k T_a(t_i), a < L_k = K - k + 1.  T1_k (L_k x L_k, row-major)
 // is the preconditioner from the first pass, so the columns Y_k T1_k are
 // nearly orthonormal and their Gram is accurate in binary64 even when Y_k is
-// badly conditioned.  One block owns a range of points and loops over the
-// degrees; partial record per block: [K+1][32][32].
-constexpr int kGram2Blocks = 128;
-
+// badly conditioned.  z is formed on the VALU (lane r of group g holds z_r
+// and z_{16+r} of four points), then accumulated as z z^T on MFMA with the
+// same (g, e) -> point bijection as the first pass.  Partial record per
+// block and degree: [32][32].
 template <typename Tin>
 __global__ void __launch_bounds__(256) k_gram2(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
                                                 int d, const GeoDev* __restrict__ geo, double u0,
@@ -426,75 +466,85 @@ __global__ void __launch_bounds__(256) k_gram2(const Tin* __restrict__ x_soa, in
   __shared__ double sh[4][4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
+  const int k = blockIdx.y;
+  const int L = K - k + 1;
+  const int nt = (L + 15) / 16;
   const double Reff = geo->Reff;
-  const int64_t per_blk = ((n + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
-  const int64_t p_begin = (int64_t)blockIdx.x * per_blk;
-  const int64_t p_end = (p_begin + per_blk < n) ? p_begin + per_blk : n;
-  for (int k = 0; k <= K; ++k) {
-    const int L = K - k + 1;
-    const int nt = (L + 15) / 16;
-    __syncthreads();
-    for (int e = threadIdx.x; e < L * L; e += 256) t1s[e] = T1[t1_off[k] + e];
-    __syncthreads();
-    V acc[2][2];
+  for (int e = threadIdx.x; e < L * L; e += 256) t1s[e] = T1[t1_off[k] + e];
+  __syncthreads();
+  V acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
-    for (int64_t ch = p_begin + (int64_t)wave * 64; ch < p_end; ch += 4 * 64) {
-      for (int s = 0; s < 16; ++s) {
-        const int64_t i = ch + g * 16 + s;
-        double z0 = 0.0, z1 = 0.0;
-        if (i < p_end) {
-          double rho2 = 0.0;
-          for (int j = 0; j < d; ++j) {
-            const double t = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
-            rho2 += t * t;
-          }
-          const double t = (2.0 * rho2 - u0 - u1) / (u1 - u0);
-          double rk = 1.0, base = sqrt(rho2);
-          for (int e = k; e > 0; e >>= 1) {
-            if (e & 1) rk *= base;
-            base *= base;
-          }
-          double tm1 = 0.0, tc = 1.0;            // T_{a-1}, T_a
-          for (int a = 0; a < L; ++a) {
-            if (a == 1) { tm1 = 1.0; tc = t; }
-            else if (a >= 2) { const double tn = 2.0 * t * tc - tm1; tm1 = tc; tc = tn; }
-            const double ya = rk * tc;
-            if (li < L) z0 += t1s[a * L + li] * ya;
-            if (16 + li < L) z1 += t1s[a * L + 16 + li] * ya;
-          }
+    for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
+  const bool j0 = li < L, j1 = 16 + li < L;
+  const int64_t ntile = (n + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    double t[4], rk[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = tile * 16 + g + 4 * e;
+      double rho2 = 0.0, tt = 0.0, pw = 0.0;
+      if (i < n) {
+        radial_point(x_soa, ldx, i, d, geo, Reff, u0, u1, rho2, tt);
+        pw = 1.0;
+        double base = sqrt(rho2);
+        for (int q = k; q > 0; q >>= 1) {
+          if (q & 1) pw *= base;
+          base *= base;
         }
-        const double z[2] = {z0, z1};
+      }
+      t[e] = tt;
+      rk[e] = pw;
+    }
+    double z0[4] = {0, 0, 0, 0}, z1[4] = {0, 0, 0, 0};
+    double tm1[4], tc[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 4; ++e) { tm1[e] = 0.0; tc[e] = 1.0; }
+    for (int a = 0; a < L; ++a) {
+      const double c0 = j0 ? t1s[a * L + li] : 0.0;
+      const double c1 = j1 ? t1s[a * L + 16 + li] : 0.0;
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-            if (a < nt && b < nt) acc[a][b] = Mfma<double>::run(z[a], z[b], acc[a][b]);
+      for (int e = 0; e < 4; ++e) {
+        if (a == 1) { tm1[e] = 1.0; tc[e] = t[e]; }
+        else if (a >= 2) { const double tn = 2.0 * t[e] * tc[e] - tm1[e]; tm1[e] = tc[e]; tc[e] = tn; }
+        const double ya = rk[e] * tc[e];
+        z0[e] += c0 * ya;
+        z1[e] += c1 * ya;
       }
     }
-    double* out = part + ((int64_t)blockIdx.x * (K + 1) + k) * 1024;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if (a >= nt || b >= nt) continue;
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sh[wave][e * 64 + lane] = acc[a][b][e];
-        __syncthreads();
-        const int idx = threadIdx.x, ln = idx & 63, e = idx >> 6;
-        const double v = sh[0][idx] + sh[1][idx] + sh[2][idx] + sh[3][idx];
-        const int row = a * 16 + Mfma<double>::row(ln >> 4, e), col = b * 16 + (ln & 15);
-        out[row * 32 + col] = v;
+    for (int e = 0; e < 4; ++e) {
+      acc[0][0] = Mfma<double>::run(z0[e], z0[e], acc[0][0]);
+      if (nt > 1) {
+        acc[0][1] = Mfma<double>::run(z0[e], z1[e], acc[0][1]);
+        acc[1][0] = Mfma<double>::run(z1[e], z0[e], acc[1][0]);
+        acc[1][1] = Mfma<double>::run(z1[e], z1[e], acc[1][1]);
       }
+    }
   }
+  double* out = part + ((int64_t)blockIdx.x * (K + 1) + k) * 1024;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (a >= nt || b >= nt) continue;
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sh[wave][e * 64 + lane] = acc[a][b][e];
+      __syncthreads();
+      const int idx = threadIdx.x, ln = idx & 63, e = idx >> 6;
+      const double v = sh[0][idx] + sh[1][idx] + sh[2][idx] + sh[3][idx];
+      const int row = a * 16 + Mfma<double>::row(ln >> 4, e), col = b * 16 + (ln & 15);
+      out[row * 32 + col] = v;
+    }
 }
 
-int gram2_blocks(int64_t n) {
-  int64_t b = (n + 2047) / 2048;
-  if (b > kGram2Blocks) b = kGram2Blocks;
+int gram2_blocks(int64_t n, int K) {
+  const int64_t tiles = (n + 15) / 16;
+  int64_t b = (tiles + 3) / 4;
+  const int64_t cap = std::max<int64_t>(1, kGramWaves / (4 * (K + 1)));
+  if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;
 }
@@ -503,11 +553,12 @@ hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
                         const GeoDev* geo, double u0, double u1, int K, const double* T1,
                         const int32_t* t1_off, double* partials, double* out, hipStream_t s) {
   if (K + 1 > 32) return hipErrorInvalidValue;
-  const int nb = gram2_blocks(n);
+  const int nb = gram2_blocks(n, K);
+  const dim3 grid(nb, K + 1);
   if (dtype == 0)
-    k_gram2<float><<<nb, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
+    k_gram2<float><<<grid, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
   else
-    k_gram2<double><<<nb, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
+    k_gram2<double><<<grid, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
   const int total = (K + 1) * 1024;
   k_gram_fin<<<(total + 255) / 256, 256, 0, s>>>(partials, nb, total, out);
   return hipGetLastError();
@@ -641,6 +692,248 @@ hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
     return launch_build_t<float, float>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
   if (prec == 0 && dtype == 1)
     return launch_build_t<double, double>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ adjoint
+// dF/dx_i for F = sum_c w_c^T U C U^T v_c, C = diag(lambda) (structure
+// frozen).  With U[i,(k,h,l)] = S_h(xt_i) q_{k,l}(rho_i^2), xt = (x - c)/R:
+//   dF/dx_i = (1/R) sum_{k,h} [ a_h(i) grad S_h(xt_i) + 2 xt_i b_h(i) S_h(xt_i) ],
+//   a_h = sum_l q_{k,l} alpha_{h,l},  b_h = sum_l q'_{k,l} alpha_{h,l},
+//   alpha_{h,l} = sum_c w_ic Gv[(k,h,l)][c] + v_ic Gw[(k,h,l)][c],
+// where Gv = C U^T V, Gw = C U^T W and q' = dq/d(rho^2).  The harmonics and
+// their gradients are recomputed in the loop order of the factor kernel,
+// forward mode: every chain level carries (P, dP/dx_j, dP/dr_j^2) through its
+// recurrence, the running prefix product carries its full gradient.  One
+// wavefront per block; the per-point radial values and derivatives of the
+// rows [row0, row1) are staged in LDS, thread-major.
+template <typename T, int D>
+struct AdjState {
+  T xt[D], r2[D];
+  T gacc[D];
+  T sacc;
+};
+
+template <typename T, int D, int MB>
+struct AdjCtx {
+  const int32_t* col_of;
+  const typename Vec2<T>::type* chain;
+  const DegDev* degs_by_k;
+  const T* Gv;
+  const T* Gw;
+  int m16, mcols, K, row0, row1;
+  const T* qs;        // LDS: [2][nrows][64]
+  int lane;
+  T wv[MB], vv[MB];
+};
+
+template <typename T, int D, int MB, int LEVEL>
+struct AdjChain {
+  typedef typename Vec2<T>::type T2;
+  static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int b,
+                                             T pre, const T* gpre, int& t) {
+    const int cj = LEVEL - 1;                     // coordinate index of this level
+    const T x = st.xt[cj], rr = st.r2[cj];
+    const T2* cf = cx.chain + ((int64_t)(LEVEL - 1) * (cx.K + 1) + b) * (cx.K + 1);
+    T pm1 = 0, pxm1 = 0, prm1 = 0;                // P_{n-1} and its partials
+    T p = cf[0].x, px = 0, pr = 0;                // P_n
+    for (int nn = 0; nn <= cx.K - b; ++nn) {
+      if (nn == 1) {
+        pm1 = p; pxm1 = px; prm1 = pr;
+        p = cf[1].x * x; px = cf[1].x; pr = 0;
+      } else if (nn >= 2) {
+        const T A = cf[nn].x, B = cf[nn].y;
+        const T pn = A * x * p - B * rr * pm1;
+        const T pxn = A * (p + x * px) - B * rr * pxm1;
+        const T prn = A * x * pr - B * (pm1 + rr * prm1);
+        pm1 = p; pxm1 = px; prm1 = pr;
+        p = pn; px = pxn; pr = prn;
+      }
+      T g[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        T dP = 0;
+        if (q == cj) dP = px + 2 * st.xt[q] * pr;
+        else if (q > cj) dP = 2 * st.xt[q] * pr;
+        g[q] = gpre[q] * p + pre * dP;
+      }
+      AdjChain<T, D, MB, LEVEL - 1>::run(st, cx, b + nn, pre * p, g, t);
+    }
+  }
+};
+
+template <typename T, int D, int MB>
+struct AdjChain<T, D, MB, 0> {
+  static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int k,
+                                             T S, const T* gS, int& t) {
+    const int col = cx.col_of[t++];
+    if (col < 0) return;
+    const DegDev dg = cx.degs_by_k[k];
+    if (dg.qoff < cx.row0 || dg.qoff + dg.s > cx.row1) return;
+    const int h = col - dg.hoff;
+    T a = 0, bq = 0;
+    for (int l = 0; l < dg.s; ++l) {
+      const int64_t row = (int64_t)(dg.roff + h * dg.s + l) * cx.m16;
+      T alpha = 0;
+#pragma unroll
+      for (int c = 0; c < MB; ++c)
+        if (c < cx.mcols) alpha += cx.wv[c] * cx.Gv[row + c] + cx.vv[c] * cx.Gw[row + c];
+      const int qr = dg.qoff + l - cx.row0;
+      const int nrows = cx.row1 - cx.row0;
+      a += cx.qs[qr * 64 + cx.lane] * alpha;
+      bq += cx.qs[(nrows + qr) * 64 + cx.lane] * alpha;
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) st.gacc[q] += a * gS[q];
+    st.sacc += bq * S;
+  }
+};
+
+template <typename Tin, typename T, int D, int MB>
+__global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
+                                                 const GeoDev* __restrict__ geo, double u0, double u1,
+                                                 const int32_t* __restrict__ col_of,
+                                                 const typename Vec2<T>::type* __restrict__ chain,
+                                                 const int32_t* __restrict__ q_len,
+                                                 const int32_t* __restrict__ q_off,
+                                                 const T* __restrict__ q_coef, int K, int row0, int row1,
+                                                 const DegDev* __restrict__ degs_by_k,
+                                                 const T* __restrict__ Wm, const T* __restrict__ Vm,
+                                                 int64_t ld, int c0, int mcols, int m16,
+                                                 const T* __restrict__ Gv, const T* __restrict__ Gw,
+                                                 T* __restrict__ dX, int64_t lddx, int accumulate) {
+  extern __shared__ unsigned char smem_raw[];
+  T* qs = reinterpret_cast<T*>(smem_raw);
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = i < n;
+  const int64_t ii = valid ? i : 0;
+  AdjState<T, D> st;
+  double rho2 = 0.0;
+  const double Reff = geo->Reff;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double v = ((double)x_soa[(int64_t)j * ldx + ii] - geo->c[j]) / Reff;
+    st.xt[j] = (T)v;
+    rho2 += v * v;
+  }
+  T acc = 0;
+#pragma unroll
+  for (int j = D - 1; j >= 0; --j) {
+    acc += st.xt[j] * st.xt[j];
+    st.r2[j] = acc;
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) st.gacc[q] = 0;
+  st.sacc = 0;
+  // radial values and d/d(rho^2) for the rows of this launch (Clenshaw)
+  const T tt = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
+  const T dt_drho2 = (T)(2.0 / (u1 - u0));
+  const int nrows = row1 - row0;
+  for (int r = 0; r < nrows; ++r) {
+    const int L = q_len[row0 + r];
+    const T* cf = q_coef + q_off[row0 + r];
+    T b1 = 0, b2 = 0, d1 = 0, d2 = 0;
+    for (int a = L - 1; a >= 1; --a) {
+      const T b0 = 2 * tt * b1 - b2 + cf[a];
+      const T d0 = 2 * b1 + 2 * tt * d1 - d2;
+      b2 = b1; b1 = b0;
+      d2 = d1; d1 = d0;
+    }
+    qs[r * 64 + lane] = tt * b1 - b2 + cf[0];
+    qs[(nrows + r) * 64 + lane] = (b1 + tt * d1 - d2) * dt_drho2;
+  }
+  AdjCtx<T, D, MB> cx;
+  cx.col_of = col_of; cx.chain = chain; cx.degs_by_k = degs_by_k; cx.Gv = Gv + c0; cx.Gw = Gw + c0;
+  cx.m16 = m16; cx.mcols = mcols; cx.K = K; cx.row0 = row0; cx.row1 = row1; cx.qs = qs; cx.lane = lane;
+#pragma unroll
+  for (int c = 0; c < MB; ++c) {
+    cx.wv[c] = (valid && c < mcols) ? Wm[ii * ld + c0 + c] : (T)0;
+    cx.vv[c] = (valid && c < mcols) ? Vm[ii * ld + c0 + c] : (T)0;
+  }
+  // azimuthal part outermost, exactly as the factor kernel
+  int t = 0;
+  const T ax = st.xt[D - 2], ay = st.xt[D - 1];
+  T cr = 1, ci = 0, pcr = 0, pci = 0;             // z^mm and z^(mm-1)
+  const T inv_sqrt_2pi = (T)0.39894228040143267794, inv_sqrt_pi = (T)0.56418958354775628695;
+  for (int mm = 0; mm <= K; ++mm) {
+    if (mm > 0) {
+      pcr = cr; pci = ci;
+      const T ncr = ax * cr - ay * ci;
+      ci = ay * cr + ax * ci;
+      cr = ncr;
+    }
+    const T cm = (mm == 0) ? inv_sqrt_2pi : inv_sqrt_pi;
+    T g[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) g[q] = 0;
+    // Re z^m: d/dx = m Re z^{m-1}, d/dy = -m Im z^{m-1}
+    g[D - 2] = cm * (T)mm * pcr;
+    g[D - 1] = -cm * (T)mm * pci;
+    AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * cr, g, t);
+    if (mm > 0) {
+      // Im z^m: d/dx = m Im z^{m-1}, d/dy = m Re z^{m-1}
+      g[D - 2] = cm * (T)mm * pci;
+      g[D - 1] = cm * (T)mm * pcr;
+      AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * ci, g, t);
+    }
+  }
+  if (valid) {
+    const T invR = (T)(1.0 / Reff);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const T v = (st.gacc[q] + 2 * st.xt[q] * st.sacc) * invR;
+      T* o = dX + ii * lddx + q;
+      *o = accumulate ? *o + v : v;
+    }
+  }
+}
+
+template <typename Tin, typename T, int MB>
+static hipError_t launch_adjoint_t(const void* x_soa, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                                   double u0, double u1, const BuildTables& tb, int row0, int row1,
+                                   const DegDev* degs_by_k, const void* Wm, const void* Vm, int64_t ld,
+                                   int c0, int mcols, int m16, const void* Gv, const void* Gw, void* dX,
+                                   int64_t lddx, int accumulate, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 63) / 64));
+  const size_t lds = (size_t)2 * (row1 - row0) * 64 * sizeof(T);
+  typedef typename Vec2<T>::type T2;
+#define ADJ_CASE(DD)                                                                               \
+  case DD:                                                                                         \
+    k_adjoint<Tin, T, DD, MB><<<grid, 64, lds, s>>>(                                               \
+        (const Tin*)x_soa, ldx, n, geo, u0, u1, tb.col_of, (const T2*)tb.chain, tb.q_len, tb.q_off, \
+        (const T*)tb.q_coef, tb.K, row0, row1, degs_by_k, (const T*)Wm, (const T*)Vm, ld, c0, mcols, \
+        m16, (const T*)Gv, (const T*)Gw, (T*)dX, lddx, accumulate);                                \
+    break;
+  switch (d) {
+    ADJ_CASE(3)
+    ADJ_CASE(4)
+    ADJ_CASE(5)
+    ADJ_CASE(6)
+    ADJ_CASE(7)
+    ADJ_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef ADJ_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
+                          const GeoDev* geo, double u0, double u1, const BuildTables& tb,
+                          int row0, int row1, const DegDev* degs_by_k, const void* Wm,
+                          const void* Vm, int64_t ld, int c0, int mcols, int m16, const void* Gv,
+                          const void* Gw, void* dX, int64_t lddx, int accumulate, int prec,
+                          hipStream_t s) {
+  if (prec == 1 && dtype == 0) {
+    if (mcols <= 1)
+      return launch_adjoint_t<float, float, 1>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
+    return launch_adjoint_t<float, float, 4>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
+  }
+  if (prec == 0 && dtype == 1) {
+    if (mcols <= 1)
+      return launch_adjoint_t<double, double, 1>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
+    return launch_adjoint_t<double, double, 4>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
+  }
   return hipErrorInvalidValue;
 }
 

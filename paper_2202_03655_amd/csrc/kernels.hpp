@@ -34,7 +34,7 @@ hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int
 
 // Refinement Gram: G2_k = (Y_k T1_k)^T (Y_k T1_k) for k = 0..K (binary64),
 // written to out[k][32][32]; T1 packed per degree at t1_off[k] (L_k x L_k).
-int gram2_blocks(int64_t n);
+int gram2_blocks(int64_t n, int K);
 hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                         const GeoDev* geo, double u0, double u1, int K, const double* T1,
                         const int32_t* t1_off, double* partials, double* out, hipStream_t s);
@@ -84,12 +84,16 @@ hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64
                            const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
                            void* KV, int64_t ldkv, int64_t n, int m, int prec, hipStream_t s);
 
-// Adjoint: dX[i] = dF/dx_i for F = sum_c w_c^T U C U^T v_c with the two
-// r x m16 matrices CGv = C (U^T V), CGw = C (U^T W) (storage type).
+// Adjoint: dX[i] (+)= dF/dx_i for F = sum_c w_c^T U C U^T v_c, restricted to
+// the radial rows [row0, row1) (degrees whose rows lie inside) and the
+// right-hand-side columns [c0, c0 + mcols), mcols <= 4.  Gv = C U^T V and
+// Gw = C U^T W (rank x m16, storage type).  degs_by_k: one DegDev per degree
+// 0..K (s = 0 for dropped degrees).  accumulate != 0 adds into dX.
 hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                           const GeoDev* geo, double u0, double u1, const BuildTables& tb,
-                          const DegDev* degs_by_k, const void* Wm, const void* Vm, int64_t ld,
-                          int m, int m16, const void* CGv, const void* CGw, void* dX,
-                          int64_t lddx, int prec, hipStream_t s);
+                          int row0, int row1, const DegDev* degs_by_k, const void* Wm,
+                          const void* Vm, int64_t ld, int c0, int mcols, int m16, const void* Gv,
+                          const void* Gw, void* dX, int64_t lddx, int accumulate, int prec,
+                          hipStream_t s);
 
 }  // namespace hdf

@@ -34,7 +34,8 @@ class HDFInfo(ctypes.Structure):
         ("rho2_max", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
         ("t_prep_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double),
         ("t_gram_ms", ctypes.c_double), ("t_compress_ms", ctypes.c_double),
-        ("t_build_ms", ctypes.c_double),
+        ("t_build_ms", ctypes.c_double), ("t_mv_t_ms", ctypes.c_double),
+        ("t_mv_reduce_ms", ctypes.c_double), ("t_mv_n_ms", ctypes.c_double),
         ("s_k", ctypes.c_int32 * (HDF_MAX_DEGREE // 2 + 1)),
     ]
 
