@@ -69,6 +69,7 @@ struct hdf_factor {
   std::vector<int32_t> index_table;               // H x (d-1)
   int64_t H = 0, S = 0, r = 0;
   int max_s = 0;
+  int n_refined = 0;                              // degrees refined by the second Gram pass
   double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_build = -1;
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
   hipEvent_t ev_mv[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -231,14 +232,22 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   HIPCHK(hipStreamSynchronize(s));
   f->t_gram = now_ms() - t0;
 
-  // 4. compression per degree, two passes (CholeskyQR2-style): precondition
-  // with the first Gram, recompute the Gram of the preconditioned radial
-  // columns on the device in binary64 (third sync), compress on the host.
+  // 4. compression per degree.  The single-pass result from the first Gram
+  // is accepted for a degree when its first-pass error stays below the
+  // target: eta1 * cond(G_k) * tau / |lambda|_max,k <= target, with eta1 the
+  // relative accuracy of the first Gram (binary64 1e-16, split binary32
+  // 1e-9) and target 1e-14 (binary64) or 1e-3 tol (mixed).  The other
+  // degrees are refined by a second, binary64 Gram pass over the
+  // preconditioned radial columns (CholeskyQR2-style; one more sync).
   t0 = now_ms();
-  const double floor_rel = (gram_mode == 0) ? 1e-15 : 1e-10;
+  const double eta1 = (gram_mode == 0) ? 1e-16 : (gram_mode == 2 ? 1e-9 : 1e-6);
+  const double target = (prec == HDF_FP64) ? 1e-14 : 1e-3 * tol;
+  const double floor_rel = (gram_mode == 0) ? 1e-15 : (gram_mode == 2 ? 1e-10 : 1e-6);
+  f->deg.resize(K + 1);
   std::vector<hdf::Precond> pcs(K + 1);
   std::vector<double> t1_all;
-  std::vector<int32_t> t1_off(K + 1);
+  std::vector<int32_t> t1_off(K + 1, 0);
+  std::vector<int> refine;
   for (int k = 0; k <= K; ++k) {
     const int L = K - k + 1;
     std::vector<double> G((size_t)L * L);
@@ -246,30 +255,43 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
       for (int bb = 0; bb < L; ++bb)
         G[(size_t)aa * L + bb] = 0.5 * (mom[(size_t)k * mcols + aa + bb] + mom[(size_t)k * mcols + std::abs(aa - bb)]);
     hdf::gram_precondition(L, G.data(), floor_rel, pcs[k]);
+    double gmax = 0.0, gmin = INFINITY;
+    for (double v : pcs[k].lam1c) { gmax = std::max(gmax, v); gmin = std::min(gmin, v); }
+    const double cond = gmax / gmin;
+    hdf::compress_degree(k, L, G.data(), f->cores[k].data(), f->tau, floor_rel, f->deg[k]);
+    double lmax = 0.0;
+    for (double v : f->deg[k].lam) lmax = std::max(lmax, std::fabs(v));
+    const double est = eta1 * cond * (lmax > 0 ? f->tau / lmax : 1.0);
+    if (est > target) refine.push_back(k);
     t1_off[k] = (int32_t)t1_all.size();
     t1_all.insert(t1_all.end(), pcs[k].T1.begin(), pcs[k].T1.end());
   }
-  {
-    DevBuf t1d, t1o, g2, g2part;
-    const int gb2 = hdf::gram2_blocks(n, K);
+  f->n_refined = (int)refine.size();
+  if (!refine.empty()) {
+    DevBuf t1d, t1o, g2, g2part, selk;
+    const int gb2 = hdf::gram2_blocks(n, (int)refine.size());
     HIPCHK(t1d.ensure(t1_all.size() * 8));
     HIPCHK(t1o.ensure(t1_off.size() * 4));
-    HIPCHK(g2.ensure((size_t)(K + 1) * 1024 * 8));
-    HIPCHK(g2part.ensure((size_t)gb2 * (K + 1) * 1024 * 8));
+    HIPCHK(selk.ensure(refine.size() * 4));
+    HIPCHK(g2.ensure(refine.size() * 1024 * 8));
+    HIPCHK(g2part.ensure((size_t)gb2 * refine.size() * 1024 * 8));
+    std::vector<int32_t> sel(refine.begin(), refine.end());
     HIPCHK(hipMemcpyAsync(t1d.p, t1_all.data(), t1_all.size() * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(t1o.p, t1_off.data(), t1_off.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(selk.p, sel.data(), sel.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hdf::launch_gram2(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p, f->u0,
                              f->u1, K, (const double*)t1d.p, (const int32_t*)t1o.p,
-                             (double*)g2part.p, (double*)g2.p, s));
-    std::vector<double> g2h((size_t)(K + 1) * 1024);
+                             (const int32_t*)selk.p, (int)sel.size(), (double*)g2part.p,
+                             (double*)g2.p, s));
+    std::vector<double> g2h(refine.size() * 1024);
     HIPCHK(hipMemcpyAsync(g2h.data(), g2.p, g2h.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    f->deg.resize(K + 1);
-    for (int k = 0; k <= K; ++k) {
+    for (size_t ri = 0; ri < refine.size(); ++ri) {
+      const int k = refine[ri];
       const int L = K - k + 1;
       std::vector<double> G2((size_t)L * L);
       for (int aa = 0; aa < L; ++aa)
-        for (int bb = 0; bb < L; ++bb) G2[(size_t)aa * L + bb] = g2h[(size_t)k * 1024 + aa * 32 + bb];
+        for (int bb = 0; bb < L; ++bb) G2[(size_t)aa * L + bb] = g2h[ri * 1024 + aa * 32 + bb];
       hdf::compress_degree_refined(k, L, G2.data(), pcs[k], f->cores[k].data(), f->tau, 1e-14, f->deg[k]);
     }
   }
@@ -592,6 +614,7 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
       h->t_build = ms;
   }
   info->t_build_ms = h->t_build;
+  info->n_refined = h->n_refined;
   info->t_mv_t_ms = info->t_mv_reduce_ms = info->t_mv_n_ms = -1.0;
   if (h->mv_timed && hipEventSynchronize(h->ev_mv[3]) == hipSuccess) {
     float a = 0.f, b = 0.f, c2 = 0.f;

@@ -460,13 +460,14 @@ __global__ void __launch_bounds__(256) k_gram2(const Tin* __restrict__ x_soa, in
                                                 int d, const GeoDev* __restrict__ geo, double u0,
                                                 double u1, int K, const double* __restrict__ T1,
                                                 const int32_t* __restrict__ t1_off,
+                                                const int32_t* __restrict__ sel, int n_sel,
                                                 double* __restrict__ part) {
   typedef Mfma<double>::V V;
   __shared__ double t1s[32 * 32];
   __shared__ double sh[4][4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int k = blockIdx.y;
+  const int k = sel[blockIdx.y];
   const int L = K - k + 1;
   const int nt = (L + 15) / 16;
   const double Reff = geo->Reff;
@@ -523,7 +524,7 @@ __global__ void __launch_bounds__(256) k_gram2(const Tin* __restrict__ x_soa, in
       }
     }
   }
-  double* out = part + ((int64_t)blockIdx.x * (K + 1) + k) * 1024;
+  double* out = part + ((int64_t)blockIdx.x * n_sel + blockIdx.y) * 1024;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -540,10 +541,10 @@ __global__ void __launch_bounds__(256) k_gram2(const Tin* __restrict__ x_soa, in
     }
 }
 
-int gram2_blocks(int64_t n, int K) {
+int gram2_blocks(int64_t n, int n_sel) {
   const int64_t tiles = (n + 15) / 16;
   int64_t b = (tiles + 3) / 4;
-  const int64_t cap = std::max<int64_t>(1, kGramWaves / (4 * (K + 1)));
+  const int64_t cap = std::max<int64_t>(1, kGramWaves / (4 * n_sel));
   if (b > cap) b = cap;
   if (b < 1) b = 1;
   return (int)b;
@@ -551,15 +552,18 @@ int gram2_blocks(int64_t n, int K) {
 
 hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                         const GeoDev* geo, double u0, double u1, int K, const double* T1,
-                        const int32_t* t1_off, double* partials, double* out, hipStream_t s) {
-  if (K + 1 > 32) return hipErrorInvalidValue;
-  const int nb = gram2_blocks(n, K);
-  const dim3 grid(nb, K + 1);
+                        const int32_t* t1_off, const int32_t* sel, int n_sel, double* partials,
+                        double* out, hipStream_t s) {
+  if (K + 1 > 32 || n_sel < 1) return hipErrorInvalidValue;
+  const int nb = gram2_blocks(n, n_sel);
+  const dim3 grid(nb, n_sel);
   if (dtype == 0)
-    k_gram2<float><<<grid, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
+    k_gram2<float><<<grid, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, sel,
+                                        n_sel, partials);
   else
-    k_gram2<double><<<grid, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, partials);
-  const int total = (K + 1) * 1024;
+    k_gram2<double><<<grid, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, sel,
+                                         n_sel, partials);
+  const int total = n_sel * 1024;
   k_gram_fin<<<(total + 255) / 256, 256, 0, s>>>(partials, nb, total, out);
   return hipGetLastError();
 }

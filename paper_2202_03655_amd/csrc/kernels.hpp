@@ -32,12 +32,14 @@ hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int
                        const GeoDev* geo, double u0, double u1, int K, int mode,
                        double* partials, double* moments, hipStream_t s);
 
-// Refinement Gram: G2_k = (Y_k T1_k)^T (Y_k T1_k) for k = 0..K (binary64),
-// written to out[k][32][32]; T1 packed per degree at t1_off[k] (L_k x L_k).
-int gram2_blocks(int64_t n, int K);
+// Refinement Gram: G2_k = (Y_k T1_k)^T (Y_k T1_k) for the selected degrees
+// k = sel[0..n_sel) (binary64), written to out[i][32][32]; T1 packed per degree
+// at t1_off[k] (L_k x L_k).
+int gram2_blocks(int64_t n, int n_sel);
 hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                         const GeoDev* geo, double u0, double u1, int K, const double* T1,
-                        const int32_t* t1_off, double* partials, double* out, hipStream_t s);
+                        const int32_t* t1_off, const int32_t* sel, int n_sel, double* partials,
+                        double* out, hipStream_t s);
 
 // Tables of the factor-evaluation kernel.
 struct BuildTables {

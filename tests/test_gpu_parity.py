@@ -43,6 +43,7 @@ def test_fp64_parity(case):
     f, Xd = gpu_build(X, kernel, l, tol)
     inf = f.info()
     plan = f.plan()
+    print(f"{name}: p={inf['degree_p']} rank={inf['rank']} refined degrees={inf['n_refined']}")
     # geometry: exact (same IEEE operations in the same order)
     assert inf["center_radius"] == st["R"]
     assert inf["rho2_min"] == st["u0"] and inf["rho2_max"] == st["u1"]
