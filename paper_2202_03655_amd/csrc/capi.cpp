@@ -77,7 +77,10 @@ struct hdf_factor {
   // device storage
   DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
       lam_row, moments;
-  int n_tiles = 0;
+  int n_tiles = 0, tiles_cpl = 0;                 // pass-1 work items for cpl = m16/16
+  // LDS-staged pass 1: items (degree, 16-row tile, column tile), groups
+  DevBuf items_dev, gitems_dev, gq_dev;
+  int items_cpl = 0, n_groups = 0, max_nq = 0;
   // matvec / adjoint workspace
   DevBuf ws_part, ws_W, ws_Wd, bw_GV, bw_GVd, bw_GW, bw_GWd, degs_by_k;
   hdf::BuildTables tables{};
@@ -176,7 +179,9 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   std::unique_ptr<hdf_factor> f(new hdf_factor());
   f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
   f->N = n; f->l = lengthscale; f->tol = tol;
-  f->ldN = (n + 63) / 64 * 64;
+  // rows of the factor are padded by at least 64 points: the streaming kernels
+  // issue unconditional 16-byte loads up to 63 points past the last point
+  f->ldN = (n + 63) / 64 * 64 + 64;
   const size_t in_elem = dtype == 0 ? 4 : 8;
 
   // 1. geometry on the device, one sync
@@ -382,14 +387,8 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
     HIPCHK(hipMemcpyAsync(f->q_len.p, ql.data(), ql.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(f->q_off.p, qo.data(), qo.size() * 4, hipMemcpyHostToDevice, s));
     // contraction tables
-    std::vector<hdf::TileDev> tiles;
-    for (size_t di = 0; di < f->degs.size(); ++di)
-      for (int h0 = 0; h0 < f->degs[di].nh; h0 += 16) tiles.push_back(hdf::TileDev{(int32_t)di, h0});
-    f->n_tiles = (int)tiles.size();
     HIPCHK(f->degs_dev.ensure(f->degs.size() * sizeof(hdf::DegDev)));
-    HIPCHK(f->tiles_dev.ensure(tiles.size() * sizeof(hdf::TileDev)));
     HIPCHK(hipMemcpyAsync(f->degs_dev.p, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(f->tiles_dev.p, tiles.data(), tiles.size() * sizeof(hdf::TileDev), hipMemcpyHostToDevice, s));
     std::vector<double> lr;
     lr.reserve(f->r);
     for (size_t di = 0; di < f->degs.size(); ++di) {
@@ -433,9 +432,86 @@ static hdf_status pass1(hdf_handle h, const void* V, int64_t m, int64_t ldv, int
                         DevBuf& Wd, hipStream_t s, bool timed) {
   const int64_t n = h->N;
   const size_t el = h->elem();
-  const int max_nct = h->max_s * (m16 / 16);
+  const int cpl = m16 / 16;
+  const int max_nct = h->max_s * cpl;
+  if (h->tiles_cpl != cpl) {
+    // work items: (degree, row block, column slice), no empty slices
+    std::vector<hdf::TileDev> tiles;
+    const int nct = hdf::matvec_col_tiles(h->prec);
+    for (size_t di = 0; di < h->degs.size(); ++di)
+      for (int h0 = 0; h0 < h->degs[di].nh; h0 += hdf::matvec_row_block())
+        for (int ct0 = 0; ct0 < h->degs[di].s * cpl; ct0 += nct)
+          tiles.push_back(hdf::TileDev{(int32_t)di, h0, ct0, 0});
+    HIPCHK(h->tiles_dev.ensure(tiles.size() * sizeof(hdf::TileDev)));
+    HIPCHK(hipMemcpyAsync(h->tiles_dev.p, tiles.data(), tiles.size() * sizeof(hdf::TileDev),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->n_tiles = (int)tiles.size();
+    h->tiles_cpl = cpl;
+  }
   const size_t per_split = (size_t)h->r * m16 * sizeof(double);
-  int n_splits = (int)std::min<int64_t>(256, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
+  if (m16 <= 64) {
+    // LDS-staged variant: B operand staged once per workgroup and chunk
+    if (h->items_cpl != cpl) {
+      std::vector<hdf::TileDev> items;
+      for (size_t di = 0; di < h->degs.size(); ++di)
+        for (int h0 = 0; h0 < h->degs[di].nh; h0 += 16)
+          for (int ct = 0; ct < h->degs[di].s * cpl; ++ct) items.push_back(hdf::TileDev{(int32_t)di, h0, ct, 0});
+      const int per = hdf::matvec_items_per_group();
+      std::vector<int32_t> gi, gq;
+      int max_nq = 0;
+      for (size_t i0 = 0; i0 < items.size(); i0 += per) {
+        const size_t i1 = std::min(items.size(), i0 + per);
+        gi.push_back((int32_t)i0);
+        const int qlo = h->degs[items[i0].deg].qoff;
+        const int qhi = h->degs[items[i1 - 1].deg].qoff + h->degs[items[i1 - 1].deg].s;
+        gq.push_back(qlo);
+        gq.push_back(qhi);
+        max_nq = std::max(max_nq, qhi - qlo);
+      }
+      gi.push_back((int32_t)items.size());
+      HIPCHK(h->items_dev.ensure(items.size() * sizeof(hdf::TileDev)));
+      HIPCHK(h->gitems_dev.ensure(gi.size() * 4));
+      HIPCHK(h->gq_dev.ensure(gq.size() * 4));
+      HIPCHK(hipMemcpyAsync(h->items_dev.p, items.data(), items.size() * sizeof(hdf::TileDev), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->gitems_dev.p, gi.data(), gi.size() * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->gq_dev.p, gq.data(), gq.size() * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      h->n_groups = (int)gi.size() - 1;
+      h->max_nq = max_nq;
+      h->items_cpl = cpl;
+    }
+    if (hdf::matvec_lds_bytes(m16, h->max_nq, h->prec) <= 65536) {
+      int n_splits = (int)std::max<int64_t>(1, 1024 / std::max(1, h->n_groups));
+      n_splits = (int)std::min<int64_t>(n_splits, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
+      n_splits = (int)std::min<int64_t>(n_splits, (n + 255) / 256);
+      n_splits = std::max(n_splits, 1);
+      int64_t split_len = (n + n_splits - 1) / n_splits;
+      split_len = (split_len + 31) / 32 * 32;
+      n_splits = (int)((n + split_len - 1) / split_len);
+      HIPCHK(h->ws_part.ensure(per_split * n_splits));
+      HIPCHK(W.ensure((size_t)h->r * m16 * sizeof(double)));
+      HIPCHK(Wd.ensure((size_t)h->r * m16 * el));
+      if (timed) {
+        if (!h->ev_mv[0])
+          for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventRecord(h->ev_mv[0], s));
+      }
+      HIPCHK(hdf::launch_matvec_t_lds(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+                                      (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
+                                      (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, V, ldv, n,
+                                      (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
+                                      h->prec, s));
+      if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
+      HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
+                                       (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->prec, s));
+      if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
+      return HDF_OK;
+    }
+  }
+  // about 16k wavefronts in pass 1, partial records capped at ~96 MB
+  int n_splits = (int)std::max<int64_t>(1, 16384 / std::max<int64_t>(1, (int64_t)h->n_tiles));
+  n_splits = (int)std::min<int64_t>(n_splits, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
   n_splits = (int)std::min<int64_t>(n_splits, (n + 1023) / 1024);
   n_splits = std::max(n_splits, 1);
   int64_t split_len = (n + n_splits - 1) / n_splits;

@@ -1,7 +1,9 @@
 // gfx950 kernels of the HDF hot path: geometry, radial Gram moments, factor
 // evaluation and the two contraction passes of the matvec.
 //
-// Layout in HBM (N points, padded leading dimension ldN):
+// Layout in HBM (N points, leading dimension ldN >= roundup(N, 64) + 64, so
+// that vector loads of a row may run up to 63 points past N without leaving
+// the row):
 //   x_soa : d rows of ldN coordinates (input type), one row per coordinate;
 //   phi   : H rows of ldN values, row h = solid harmonic h at every point;
 //   q     : S rows of ldN values, row (k,l) = radial function l of degree k.
@@ -574,37 +576,66 @@ hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
 // degree k last), so each level keeps only its two-term recurrence state in
 // registers; every iteration of the innermost loop yields one harmonic,
 // stored to its canonical row col_of[t] (the table follows this loop order).
-template <typename T, int D, int LEVEL>
+// Each thread evaluates PPT consecutive points (independent recurrence chains
+// in flight) and writes them with one 16-byte nontemporal store per row.
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+template <typename T, int PPT> struct PVec;
+template <> struct PVec<float, 4> { typedef floatx4 type; };
+template <> struct PVec<double, 2> { typedef doublex2 type; };
+
+template <typename T, int PPT>
+__device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&v)[PPT]) {
+  typedef typename PVec<T, PPT>::type V;
+  V w;
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) w[e] = v[e];
+  __builtin_nontemporal_store(w, reinterpret_cast<V*>(dst));
+}
+
+template <typename T, int D, int PPT, int LEVEL>
 struct Chain {
   typedef typename Vec2<T>::type T2;
-  static __device__ __forceinline__ void run(const T* xt, const T* r2, int b, T prefix, int K,
+  static __device__ __forceinline__ void run(const T (&xt)[PPT][D], const T (&r2)[PPT][D], int b,
+                                             const T (&prefix)[PPT], int K,
                                              const T2* __restrict__ chain,
                                              const int32_t* __restrict__ col_of, int& t,
-                                             T* __restrict__ phi, int64_t ld, int64_t i,
-                                             bool valid) {
-    const T x = xt[LEVEL - 1], rr = r2[LEVEL - 1];
+                                             T* __restrict__ phi_base, int64_t ld) {
     const T2* cf = chain + ((int64_t)(LEVEL - 1) * (K + 1) + b) * (K + 1);
-    T pm1 = 0, p = cf[0].x;
+    T pm1[PPT], p[PPT], pre[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) { pm1[e] = 0; p[e] = cf[0].x; }
     for (int nn = 0; nn <= K - b; ++nn) {
-      if (nn == 1) { pm1 = p; p = cf[1].x * x; }
-      else if (nn >= 2) { const T pn = cf[nn].x * x * p - cf[nn].y * rr * pm1; pm1 = p; p = pn; }
-      Chain<T, D, LEVEL - 1>::run(xt, r2, b + nn, prefix * p, K, chain, col_of, t, phi, ld, i, valid);
+      if (nn == 1) {
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) { pm1[e] = p[e]; p[e] = cf[1].x * xt[e][LEVEL - 1]; }
+      } else if (nn >= 2) {
+        const T A = cf[nn].x, B = cf[nn].y;
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) {
+          const T pn = A * xt[e][LEVEL - 1] * p[e] - B * r2[e][LEVEL - 1] * pm1[e];
+          pm1[e] = p[e];
+          p[e] = pn;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) pre[e] = prefix[e] * p[e];
+      Chain<T, D, PPT, LEVEL - 1>::run(xt, r2, b + nn, pre, K, chain, col_of, t, phi_base, ld);
     }
   }
 };
-template <typename T, int D>
-struct Chain<T, D, 0> {
+template <typename T, int D, int PPT>
+struct Chain<T, D, PPT, 0> {
   typedef typename Vec2<T>::type T2;
-  static __device__ __forceinline__ void run(const T*, const T*, int, T prefix, int,
-                                             const T2* __restrict__, const int32_t* __restrict__ col_of,
-                                             int& t, T* __restrict__ phi, int64_t ld, int64_t i,
-                                             bool valid) {
+  static __device__ __forceinline__ void run(const T (&)[PPT][D], const T (&)[PPT][D], int,
+                                             const T (&prefix)[PPT], int, const T2* __restrict__,
+                                             const int32_t* __restrict__ col_of, int& t,
+                                             T* __restrict__ phi_base, int64_t ld) {
     const int col = col_of[t++];
-    if (valid && col >= 0) __builtin_nontemporal_store(prefix, phi + (int64_t)col * ld + i);
+    if (col >= 0) store_row<T, PPT>(phi_base + (int64_t)col * ld, prefix);
   }
 };
 
-template <typename Tin, typename T, int D>
+template <typename Tin, typename T, int D, int PPT>
 __global__ void __launch_bounds__(256) k_build(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
                                                 const GeoDev* __restrict__ geo, double u0, double u1,
                                                 const int32_t* __restrict__ col_of,
@@ -614,51 +645,80 @@ __global__ void __launch_bounds__(256) k_build(const Tin* __restrict__ x_soa, in
                                                 const T* __restrict__ q_coef, int K, int S,
                                                 T* __restrict__ phi, int64_t ld_phi,
                                                 T* __restrict__ q, int64_t ld_q) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  const int64_t ii = valid ? i : 0;
-  T xt[D], r2[D];
-  double rho2 = 0.0;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * PPT;
+  if (i0 >= n) return;      // whole thread past the end (ld is padded to 64)
+  T xt[PPT][D], r2[PPT][D], tt[PPT];
   {
 #pragma clang fp contract(off)
     const double Reff = geo->Reff;
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const double v = ((double)x_soa[(int64_t)j * ldx + ii] - geo->c[j]) / Reff;
-      xt[j] = (T)v;
-      rho2 = rho2 + v * v;
+    for (int e = 0; e < PPT; ++e) {
+      const int64_t i = (i0 + e < n) ? i0 + e : n - 1;
+      double rho2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double v = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+        xt[e][j] = (T)v;
+        rho2 = rho2 + v * v;
+      }
+      tt[e] = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
     }
   }
-  T acc = 0;
 #pragma unroll
-  for (int j = D - 1; j >= 0; --j) {
-    acc += xt[j] * xt[j];
-    r2[j] = acc;
+  for (int e = 0; e < PPT; ++e) {
+    T acc = 0;
+#pragma unroll
+    for (int j = D - 1; j >= 0; --j) {
+      acc += xt[e][j] * xt[e][j];
+      r2[e][j] = acc;
+    }
   }
   // harmonics: azimuthal part (x_{D-1} + i x_D)^m outermost
   int t = 0;
-  const T ax = xt[D - 2], ay = xt[D - 1];
-  T cr = 1, ci = 0;
+  T cr[PPT], ci[PPT], pre[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) { cr[e] = 1; ci[e] = 0; }
   const T inv_sqrt_2pi = (T)0.39894228040143267794, inv_sqrt_pi = (T)0.56418958354775628695;
+  T* phi_base = phi + i0;
   for (int mm = 0; mm <= K; ++mm) {
-    if (mm > 0) { const T ncr = ax * cr - ay * ci; ci = ay * cr + ax * ci; cr = ncr; }
+    if (mm > 0) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const T ax = xt[e][D - 2], ay = xt[e][D - 1];
+        const T ncr = ax * cr[e] - ay * ci[e];
+        ci[e] = ay * cr[e] + ax * ci[e];
+        cr[e] = ncr;
+      }
+    }
     const T cm = (mm == 0) ? inv_sqrt_2pi : inv_sqrt_pi;
-    Chain<T, D, D - 2>::run(xt, r2, mm, cm * cr, K, chain, col_of, t, phi, ld_phi, i, valid);
-    if (mm > 0) Chain<T, D, D - 2>::run(xt, r2, mm, cm * ci, K, chain, col_of, t, phi, ld_phi, i, valid);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) pre[e] = cm * cr[e];
+    Chain<T, D, PPT, D - 2>::run(xt, r2, mm, pre, K, chain, col_of, t, phi_base, ld_phi);
+    if (mm > 0) {
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) pre[e] = cm * ci[e];
+      Chain<T, D, PPT, D - 2>::run(xt, r2, mm, pre, K, chain, col_of, t, phi_base, ld_phi);
+    }
   }
   // radial functions: Clenshaw in the basis T_a(t)
-  const T tt = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
   for (int row = 0; row < S; ++row) {
     const int L = q_len[row];
     const T* cf = q_coef + q_off[row];
-    T b1 = 0, b2 = 0;
+    T b1[PPT], b2[PPT], val[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) { b1[e] = 0; b2[e] = 0; }
     for (int a = L - 1; a >= 1; --a) {
-      const T b0 = 2 * tt * b1 - b2 + cf[a];
-      b2 = b1;
-      b1 = b0;
+      const T c = cf[a];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const T b0 = 2 * tt[e] * b1[e] - b2[e] + c;
+        b2[e] = b1[e];
+        b1[e] = b0;
+      }
     }
-    const T val = tt * b1 - b2 + cf[0];
-    if (valid) __builtin_nontemporal_store(val, q + (int64_t)row * ld_q + i);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) val[e] = tt[e] * b1[e] - b2[e] + cf[0];
+    store_row<T, PPT>(q + (int64_t)row * ld_q + i0, val);
   }
 }
 
@@ -666,14 +726,15 @@ template <typename Tin, typename T>
 static hipError_t launch_build_t(const void* x_soa, int64_t ldx, int64_t n, int d, const GeoDev* geo,
                                  double u0, double u1, const BuildTables& tb, void* phi,
                                  int64_t ld_phi, void* q, int64_t ld_q, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256));
+  constexpr int PPT = 16 / sizeof(T);
+  const dim3 grid((unsigned)((n + 256 * PPT - 1) / (256 * PPT)));
   typedef typename Vec2<T>::type T2;
 #define BUILD_CASE(DD)                                                                        \
   case DD:                                                                                    \
-    k_build<Tin, T, DD><<<grid, 256, 0, s>>>((const Tin*)x_soa, ldx, n, geo, u0, u1, tb.col_of, \
-                                             (const T2*)tb.chain, tb.q_len, tb.q_off,         \
-                                             (const T*)tb.q_coef, tb.K, tb.S, (T*)phi, ld_phi,  \
-                                             (T*)q, ld_q);                                    \
+    k_build<Tin, T, DD, PPT><<<grid, 256, 0, s>>>((const Tin*)x_soa, ldx, n, geo, u0, u1,    \
+                                                  tb.col_of, (const T2*)tb.chain, tb.q_len,   \
+                                                  tb.q_off, (const T*)tb.q_coef, tb.K, tb.S,  \
+                                                  (T*)phi, ld_phi, (T*)q, ld_q);              \
     break;
   switch (d) {
     BUILD_CASE(3)
@@ -942,12 +1003,40 @@ hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, 
 }
 
 // ------------------------------------------------------------------ matvec
+// Vector load of 8 consecutive values of a harmonic / radial row starting at
+// p (a multiple of 8, p < N + 56).  Rows are padded by 64 points past N, so
+// the 16-byte loads never leave the row; values at or past `end` (or of an
+// invalid row) are replaced by zero with selects, never by branches, so all
+// loads of an iteration issue back to back.
+template <typename T>
+__device__ __forceinline__ void load8(const T* __restrict__ row, int64_t p, int64_t end, bool ok, T (&a)[8]) {
+  T v[8];
+  if constexpr (sizeof(T) == 4) {
+    const floatx4 v0 = *reinterpret_cast<const floatx4*>(row + p);
+    const floatx4 v1 = *reinterpret_cast<const floatx4*>(row + p + 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { v[e] = v0[e]; v[4 + e] = v1[e]; }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const doublex2 w = *reinterpret_cast<const doublex2*>(row + p + 2 * h);
+      v[2 * h] = w[0];
+      v[2 * h + 1] = w[1];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) a[e] = (ok && p + e < end) ? v[e] : (T)0;
+}
+
 // Pass 1, W = U^T V.  Per degree k this is the product Phi_k (Q_k o V)
 // (Khatri-Rao: column (k,h,l) of U is phi_h * q_{k,l}).  One wavefront owns
-// a 16-harmonic tile of one degree and a contiguous range of points; columns
-// j = l * m16 + c of the tile product are produced NCT 16-wide tiles at a
+// a block of 32 harmonics of one degree (two 16-row MFMA tiles, so every B
+// operand q_{k,l}(i) V[i][c] is reused twice) and a contiguous range of
+// points; output columns j = l * m16 + c are produced NCT 16-wide tiles at a
 // time.  The reduction index (points) is assigned so that lane group g reads
-// 4 consecutive points of each harmonic row.
+// 8 consecutive points of each harmonic row (two 16-byte loads per row).
+constexpr int kMvtRowTiles = 2;
+
 template <typename T, int NCT>
 __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
@@ -962,12 +1051,16 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
   const int split = blockIdx.y;
   const int cpl = m16 / 16;                      // column tiles per radial function
   const int nct_all = dg.s * cpl;
-  const int ct0 = blockIdx.z * NCT;
-  if (ct0 >= nct_all) return;
+  const int ct0 = tile.ct0;
   const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
-  const int row = tile.h0 + li;
-  const bool rowv = row < dg.nh;
-  const T* prow = phi + (int64_t)(dg.hoff + (rowv ? row : 0)) * ld_phi;
+  const T* prow[kMvtRowTiles];
+  bool rowv[kMvtRowTiles];
+#pragma unroll
+  for (int rt = 0; rt < kMvtRowTiles; ++rt) {
+    const int row = tile.h0 + rt * 16 + li;
+    rowv[rt] = row < dg.nh;
+    prow[rt] = phi + (int64_t)(dg.hoff + (rowv[rt] ? row : 0)) * ld_phi;
+  }
   const T* qrow[NCT];
   int cc[NCT];
   bool cv[NCT];
@@ -979,25 +1072,55 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
     cv[ct] = (tix < nct_all) && (cc[ct] < m);
     qrow[ct] = q + (int64_t)(dg.qoff + (tix < nct_all ? l : 0)) * ld_q;
   }
-  Acc acc[NCT];
+  Acc acc[kMvtRowTiles][NCT];
 #pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) acc[ct] = Acc{0, 0, 0, 0};
+  for (int rt = 0; rt < kMvtRowTiles; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = Acc{0, 0, 0, 0};
   const int64_t p_begin = (int64_t)split * split_len;
   const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
-  for (int64_t p = p_begin; p < p_end; p += 16) {
-    const int64_t pb = p + 4 * g;
-    T a[4];
+  // software pipeline: the Phi tiles of the next 32 points are loaded while
+  // the MFMAs of the current ones run
+  T a_nxt[kMvtRowTiles][8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] = (rowv && pb + t < p_end) ? prow[pb + t] : (T)0;
+  for (int rt = 0; rt < kMvtRowTiles; ++rt) load8(prow[rt], p_begin + 8 * g, p_end, rowv[rt], a_nxt[rt]);
+  for (int64_t p = p_begin; p < p_end; p += 32) {
+    const int64_t pb = p + 8 * g;
+    T a[kMvtRowTiles][8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int rt = 0; rt < kMvtRowTiles; ++rt)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[rt][e] = a_nxt[rt][e];
+    if (p + 32 < p_end) {
+#pragma unroll
+      for (int rt = 0; rt < kMvtRowTiles; ++rt) load8(prow[rt], pb + 32, p_end, rowv[rt], a_nxt[rt]);
+    }
+    // B operands: unconditional in-bounds loads (clamped point / column),
+    // invalid entries zeroed by selects
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
       const int64_t pt = pb + t;
       const bool pv = pt < p_end;
-      const T* vrow = V + (pv ? pt : 0) * ldv;
+      const int64_t ptc = pv ? pt : p_begin;
+      const T* vrow = V + ptc * ldv;
+      T b[NCT];
+      // the clamped indices address valid (finite) data, so validity is
+      // applied as a 0/1 factor; a select would be turned back into a branch
+      const T pmask = pv ? (T)1 : (T)0;
+      if (cpl == 1) {
+        const T vv = vrow[li < m ? li : 0] * (li < m ? pmask : (T)0);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) b[ct] = qrow[ct][ptc] * vv;
+      } else {
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          b[ct] = qrow[ct][ptc] * vrow[cc[ct] < m ? cc[ct] : 0] * (cv[ct] ? pmask : (T)0);
+      }
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
-        const T b = (pv && cv[ct]) ? qrow[ct][pt] * vrow[cc[ct]] : (T)0;
-        acc[ct] = Mfma<T>::run(a[t], b, acc[ct]);
+        if (ct0 + ct >= nct_all) break;          // uniform: live column tiles only
+#pragma unroll
+        for (int rt = 0; rt < kMvtRowTiles; ++rt) acc[rt][ct] = Mfma<T>::run(a[rt][t], b[ct], acc[rt][ct]);
       }
     }
   }
@@ -1009,29 +1132,174 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
     const int l = tix / cpl;
     const int c = (tix % cpl) * 16 + li;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int h = tile.h0 + Mfma<T>::row(g, e);
-      if (h < dg.nh) out[(int64_t)(dg.roff + h * dg.s + l) * m16 + c] = (double)acc[ct][e];
+    for (int rt = 0; rt < kMvtRowTiles; ++rt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int h = tile.h0 + rt * 16 + Mfma<T>::row(g, e);
+        if (h < dg.nh) out[(int64_t)(dg.roff + h * dg.s + l) * m16 + c] = (double)acc[rt][ct][e];
+      }
+  }
+}
+
+// Pass 1 with the B operand staged in LDS.  A workgroup (4 wavefronts) owns
+// a group of up to 4 * kMvTPW work items (one 16-harmonic row tile x one
+// 16-wide output column tile each, degrees contiguous) and a range of points.
+// Per 32-point chunk it stages V (32 x m16) and the group's radial rows
+// (nq x 32) in LDS once; every wavefront then streams the Phi rows of its
+// items (two 16-byte loads per lane per item, batches of 4 items issued ahead
+// of their MFMAs) and forms B = q_{k,l}(i) V[i][c] from LDS.  All item
+// accumulators stay in registers for the whole point range, so Phi is read
+// once and V, q once per group.
+constexpr int kMvCH = 32;
+constexpr int kMvTPW = 16;
+constexpr int kMvBatch = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int64_t ld_phi,
+                                                   const T* __restrict__ q, int64_t ld_q,
+                                                   const DegDev* __restrict__ degs,
+                                                   const TileDev* __restrict__ items,
+                                                   const int32_t* __restrict__ group_items,
+                                                   const int32_t* __restrict__ group_q,
+                                                   const T* __restrict__ V, int64_t ldv, int64_t n,
+                                                   int m, int m16, int64_t split_len, int64_t rank,
+                                                   double* __restrict__ part) {
+  typedef typename Mfma<T>::V Acc;
+  extern __shared__ unsigned char smem_raw[];
+  const int grp = blockIdx.y, split = blockIdx.x;
+  const int it0 = group_items[grp], it1 = group_items[grp + 1];
+  const int q_lo = group_q[2 * grp], nq = group_q[2 * grp + 1] - q_lo;
+  const int vst = m16 + 1;                        // padded V row (bank spread)
+  T* vbuf = reinterpret_cast<T*>(smem_raw);       // [kMvCH][vst]
+  T* qbuf = vbuf + kMvCH * vst;                   // [nq][kMvCH]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int cpl = m16 / 16;
+  const int my0 = it0 + wave * kMvTPW;
+  int n_mine = it1 - my0;
+  n_mine = n_mine < 0 ? 0 : (n_mine > kMvTPW ? kMvTPW : n_mine);
+  // per-item descriptors resolved once: first Phi row, rows in the tile,
+  // LDS row of its radial function, output column base
+  __shared__ int64_t d_row[4 * kMvTPW];
+  __shared__ int32_t d_nr[4 * kMvTPW], d_qr[4 * kMvTPW], d_c[4 * kMvTPW];
+  if (tid < 4 * kMvTPW && it0 + tid < it1) {
+    const TileDev it = items[it0 + tid];
+    const DegDev dg = degs[it.deg];
+    const int l = it.ct0 / cpl;
+    d_row[tid] = (int64_t)(dg.hoff + it.h0);
+    d_nr[tid] = dg.nh - it.h0;
+    d_qr[tid] = (dg.qoff + l - q_lo) * kMvCH;
+    d_c[tid] = (it.ct0 - l * cpl) * 16;
+  }
+  Acc acc[kMvTPW];
+#pragma unroll
+  for (int i = 0; i < kMvTPW; ++i) acc[i] = Acc{0, 0, 0, 0};
+  const int64_t p_begin = (int64_t)split * split_len;
+  const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
+  const int wbase = wave * kMvTPW;
+  for (int64_t p = p_begin; p < p_end; p += kMvCH) {
+    __syncthreads();
+    for (int e = tid; e < kMvCH * m16; e += 256) {
+      const int pp = e / m16, c = e - pp * m16;
+      const int64_t pt = p + pp;
+      vbuf[pp * vst + c] = (pt < p_end && c < m) ? V[pt * ldv + c] : (T)0;
+    }
+    for (int e = tid; e < nq * kMvCH; e += 256) {
+      const int r = e / kMvCH, pp = e - r * kMvCH;
+      const int64_t pt = p + pp;
+      qbuf[r * kMvCH + pp] = (pt < p_end) ? q[(int64_t)(q_lo + r) * ld_q + pt] : (T)0;
+    }
+    __syncthreads();
+    const int64_t pb = p + 8 * g;
+#pragma unroll
+    for (int b0 = 0; b0 < kMvTPW; b0 += kMvBatch) {
+      if (b0 < n_mine) {                          // uniform
+        T a[kMvBatch][8];
+#pragma unroll
+        for (int j = 0; j < kMvBatch; ++j) {
+          const int i = b0 + j;
+          const int di = wbase + (i < n_mine ? i : 0);
+          const bool ok = (i < n_mine) && li < d_nr[di];
+          load8(phi + (d_row[di] + (ok ? li : 0)) * ld_phi, pb, p_end, ok, a[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kMvBatch; ++j) {
+          const int i = b0 + j;
+          if (i < n_mine) {                       // uniform
+            const int di = wbase + i;
+            const T* qb = qbuf + d_qr[di] + 8 * g;
+            const T* vb = vbuf + (8 * g) * vst + d_c[di] + li;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[i] = Mfma<T>::run(a[j][t], qb[t] * vb[t * vst], acc[i]);
+          }
+        }
+      }
+    }
+  }
+  double* out = part + (int64_t)split * rank * m16;
+#pragma unroll
+  for (int i = 0; i < kMvTPW; ++i) {
+    if (i < n_mine) {
+      const TileDev it = items[my0 + i];
+      const DegDev dg = degs[it.deg];
+      const int l = it.ct0 / cpl;
+      const int c = (it.ct0 - l * cpl) * 16 + li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int h = it.h0 + Mfma<T>::row(g, e);
+        if (h < dg.nh) out[(int64_t)(dg.roff + h * dg.s + l) * m16 + c] = (double)acc[i][e];
+      }
     }
   }
 }
 
+int matvec_items_per_group() { return 4 * kMvTPW; }
+size_t matvec_lds_bytes(int m16, int nq, int prec) {
+  return (size_t)(kMvCH * (m16 + 1) + nq * kMvCH) * (prec == 1 ? 4 : 8);
+}
+
+hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                               const DegDev* degs, const TileDev* items, const int32_t* group_items,
+                               const int32_t* group_q, int n_groups, int max_nq, const void* V,
+                               int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
+                               int64_t rank, double* partials, int prec, hipStream_t s) {
+  const dim3 grid(n_splits, n_groups);
+  const size_t lds = matvec_lds_bytes(m16, max_nq, prec);
+  if (prec == 1)
+    k_mv_t_lds<float><<<grid, 256, lds, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs, items,
+                                            group_items, group_q, (const float*)V, ldv, n, m, m16,
+                                            split_len, rank, partials);
+  else
+    k_mv_t_lds<double><<<grid, 256, lds, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q, degs,
+                                             items, group_items, group_q, (const double*)V, ldv, n, m,
+                                             m16, split_len, rank, partials);
+  return hipGetLastError();
+}
+
+// Fixed-order reduction over the pass-1 splits (eight independent partial
+// sums combined pairwise, so the order is fixed and the loads pipelined).
 template <typename T>
 __global__ void k_mv_reduce(const double* __restrict__ part, int n_splits, int64_t total, int m16,
                             const double* __restrict__ lam_row, double* __restrict__ W,
                             T* __restrict__ Wd) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  double s = 0.0;
-  for (int sp = 0; sp < n_splits; ++sp) s += part[(int64_t)sp * total + e];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int sp = 0;
+  for (; sp + 8 <= n_splits; sp += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += part[(int64_t)(sp + u) * total + e];
+  for (int u = 0; sp + u < n_splits; ++u) acc[u] += part[(int64_t)(sp + u) * total + e];
+  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   W[e] = s;
   Wd[e] = (T)(lam_row[e / m16] * s);
 }
 
-// Pass 2, KV = U (D W).  One wavefront owns 32 points and one 16-column
+// Pass 2, KV = U (D W).  One wavefront owns 64 points and one 16-column
 // chunk of the right-hand sides; per degree it forms Z[i][(l,c)] =
 // sum_h phi_h(i) Wd[(k,h,l)][c] on MFMA (reduction over harmonics) and folds
-// Z into KV with the radial functions q_{k,l}(i).
+// Z into KV with the radial functions q_{k,l}(i).  MFMA row i of point tile
+// u is point p0 + 4 i + u, so each lane reads 4 consecutive points of a
+// harmonic row with one 16-byte load.
 template <typename T, int NCT>
 __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
@@ -1040,37 +1308,75 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
                                               T* __restrict__ KV, int64_t ldkv, int64_t n, int m) {
   typedef typename Mfma<T>::V Acc;
   const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
-  const int64_t p0 = (int64_t)blockIdx.x * 32;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
   const int c0 = blockIdx.y * 16;
-  T kv[2][4];
+  const int64_t pa = p0 + 4 * li;                // this lane's four A points
+  T kv[4][4];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int e = 0; e < 4; ++e) kv[u][e] = 0;
   for (int di = 0; di < n_deg; ++di) {
     const DegDev dg = degs[di];
     for (int l0 = 0; l0 < dg.s; l0 += NCT) {
-      Acc acc[2][NCT];
+      Acc acc[4][NCT];
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = Acc{0, 0, 0, 0};
-      for (int h0 = 0; h0 < dg.nh; h0 += 4) {
-        const int hh = h0 + g;
-        const bool hv = hh < dg.nh;
-        const T* prow = phi + (int64_t)(dg.hoff + (hv ? hh : 0)) * ld_phi;
-        T a[2];
+      // batches of 4 K-steps (16 harmonics): every load of a batch is issued
+      // before its MFMAs, and the next batch's Phi loads before this batch's
+      // MFMAs (software pipeline)
+      constexpr int KB = 4;
+      T v_nxt[KB][4];
+      auto load_batch = [&](int hb, T (&vv)[KB][4]) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int64_t pt = p0 + 16 * u + li;
-          a[u] = (hv && pt < n) ? prow[pt] : (T)0;
+        for (int kb = 0; kb < KB; ++kb) {
+          const int hh = hb + 4 * kb + g;
+          const T* prow = phi + (int64_t)(dg.hoff + (hh < dg.nh ? hh : 0)) * ld_phi;
+          if constexpr (sizeof(T) == 4) {
+            const floatx4 w = *reinterpret_cast<const floatx4*>(prow + pa);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) vv[kb][u] = w[u];
+          } else {
+            const doublex2 w0 = *reinterpret_cast<const doublex2*>(prow + pa);
+            const doublex2 w1 = *reinterpret_cast<const doublex2*>(prow + pa + 2);
+            vv[kb][0] = w0[0]; vv[kb][1] = w0[1]; vv[kb][2] = w1[0]; vv[kb][3] = w1[1];
+          }
+        }
+      };
+      load_batch(0, v_nxt);
+      for (int hb = 0; hb < dg.nh; hb += 4 * KB) {
+        T v[KB][4];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[kb][u] = v_nxt[kb][u];
+        if (hb + 4 * KB < dg.nh) load_batch(hb + 4 * KB, v_nxt);
+        T bw[KB][NCT];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          const int hh = hb + 4 * kb + g;
+          const T* wrow = Wd + (int64_t)(dg.roff + (hh < dg.nh ? hh : 0) * dg.s) * m16 + c0 + li;
+          const T hmask = hh < dg.nh ? (T)1 : (T)0;
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            const int l = l0 + ct;
+            bw[kb][ct] = (l < dg.s) ? wrow[(int64_t)l * m16] * hmask : (T)0;
+          }
         }
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          const int l = l0 + ct;
-          const T b = (hv && l < dg.s) ? Wd[(int64_t)(dg.roff + hh * dg.s + l) * m16 + c0 + li] : (T)0;
+        for (int kb = 0; kb < KB; ++kb) {
+          const int hh = hb + 4 * kb + g;
+          T a[4];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) acc[u][ct] = Mfma<T>::run(a[u], b, acc[u][ct]);
+          for (int u = 0; u < 4; ++u) a[u] = (hh < dg.nh && pa + u < n) ? v[kb][u] : (T)0;
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            if (l0 + ct >= dg.s) break;           // uniform: live radial functions only
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u][ct] = Mfma<T>::run(a[u], bw[kb][ct], acc[u][ct]);
+          }
         }
       }
 #pragma unroll
@@ -1079,12 +1385,12 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
         if (l >= dg.s) continue;
         const T* qrow = q + (int64_t)(dg.qoff + l) * ld_q;
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int64_t pt = p0 + 16 * u + Mfma<T>::row(g, e);
-            const T qv = (pt < n) ? qrow[pt] : (T)0;
-            kv[u][e] += qv * acc[u][ct][e];
+            const int64_t pt = p0 + 4 * Mfma<T>::row(g, e) + u;
+            const T ql = qrow[pt];                // padded row: in bounds
+            kv[u][e] += ((pt < n) ? ql : (T)0) * acc[u][ct][e];
           }
       }
     }
@@ -1092,31 +1398,36 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
   const int c = c0 + li;
   if (c < m) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t pt = p0 + 16 * u + Mfma<T>::row(g, e);
+        const int64_t pt = p0 + 4 * Mfma<T>::row(g, e) + u;
         if (pt < n) KV[pt * ldkv + c] = kv[u][e];
       }
   }
 }
 
-constexpr int kMvNct = 4;
+constexpr int kMvNctF = 4;   // column tiles per pass, binary32
+constexpr int kMvNctD = 2;   // column tiles per pass, binary64
+
+int matvec_row_block() { return 16 * kMvtRowTiles; }
+int matvec_col_tiles(int prec) { return prec == 1 ? kMvNctF : kMvNctD; }
 
 hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, const TileDev* tiles, int n_tiles, int max_nct,
                            const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
                            int64_t split_len, int64_t rank, double* partials, int prec,
                            hipStream_t s) {
-  const dim3 grid(n_tiles, n_splits, (max_nct + kMvNct - 1) / kMvNct);
+  (void)max_nct;
+  const dim3 grid(n_tiles, n_splits);
   if (prec == 1)
-    k_mv_t<float, kMvNct><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
-                                             tiles, (const float*)V, ldv, n, m, m16, split_len, rank,
-                                             partials);
+    k_mv_t<float, kMvNctF><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
+                                              tiles, (const float*)V, ldv, n, m, m16, split_len, rank,
+                                              partials);
   else
-    k_mv_t<double, kMvNct><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
-                                              degs, tiles, (const double*)V, ldv, n, m, m16,
-                                              split_len, rank, partials);
+    k_mv_t<double, kMvNctD><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
+                                               degs, tiles, (const double*)V, ldv, n, m, m16,
+                                               split_len, rank, partials);
   return hipGetLastError();
 }
 
@@ -1136,14 +1447,14 @@ hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64
                            const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
                            void* KV, int64_t ldkv, int64_t n, int m, int prec, hipStream_t s) {
   (void)max_s;
-  const dim3 grid((unsigned)((n + 31) / 32), (unsigned)(m16 / 16));
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)(m16 / 16));
   if (prec == 1)
-    k_mv_n<float, kMvNct><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
-                                             n_deg, (const float*)Wd, m16, (float*)KV, ldkv, n, m);
+    k_mv_n<float, kMvNctF><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
+                                              n_deg, (const float*)Wd, m16, (float*)KV, ldkv, n, m);
   else
-    k_mv_n<double, kMvNct><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
-                                              degs, n_deg, (const double*)Wd, m16, (double*)KV,
-                                              ldkv, n, m);
+    k_mv_n<double, kMvNctD><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
+                                               degs, n_deg, (const double*)Wd, m16, (double*)KV,
+                                               ldkv, n, m);
   return hipGetLastError();
 }
 

@@ -66,8 +66,12 @@ struct DegDev {
 };
 struct TileDev {
   int32_t deg;    // index into DegDev
-  int32_t h0;     // first harmonic of the 16-row tile
+  int32_t h0;     // first harmonic of the row block
+  int32_t ct0;    // first 16-wide output column tile of the slice
+  int32_t pad;
 };
+int matvec_row_block();          // harmonic rows per pass-1 row block
+int matvec_col_tiles(int prec);  // 16-wide column tiles per pass-1 launch slice
 
 // Pass 1: partial[split][row][c] = sum_{i in split} U[i,row] V[i,c]
 // (row = (k,h,l), c < m16, binary64 partials).
@@ -76,6 +80,17 @@ hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64
                            const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
                            int64_t split_len, int64_t rank, double* partials, int prec,
                            hipStream_t s);
+// Pass 1 with V and the radial rows staged in LDS per workgroup.  Items are
+// (degree, 16-row tile h0, column tile ct0) with degrees contiguous; group g
+// owns items [group_items[g], group_items[g+1]) and radial rows
+// [group_q[2g], group_q[2g+1]).  Requires matvec_lds_bytes(m16, max_nq) <= 64 KiB.
+int matvec_items_per_group();
+size_t matvec_lds_bytes(int m16, int nq, int prec);
+hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                               const DegDev* degs, const TileDev* items, const int32_t* group_items,
+                               const int32_t* group_q, int n_groups, int max_nq, const void* V,
+                               int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
+                               int64_t rank, double* partials, int prec, hipStream_t s);
 // Reduce over splits: W[row][c] = sum_split partial (binary64) and
 // Wd[row][c] = lambda_row * W (storage type) for pass 2.
 hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t rank, int m16,
