@@ -73,21 +73,27 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
         f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec)
         t1 = time.perf_counter()
         f.matvec(Vd, out=out)
+        t2 = time.perf_counter()
         grads = f.backward(Wd[:, :1], Vd[:, :1]) if with_backward else None
-        return f, t1 - t0, grads
+        t3 = time.perf_counter()
+        return f, t1 - t0, grads, t3 - t2
 
     for _ in range(warmup):
-        f, _, _ = step()
+        f, _, _, _ = step()
         f.info()
         del f
     torch.cuda.synchronize()
-    rec = dict(build_s=[], k_build=[], k_mv_t=[], k_mv_n=[], k_mv_red=[])
+    rec = dict(build_s=[], bw_s=[], k_build=[], k_mv_t=[], k_mv_n=[], k_mv_red=[], h_prep=[], h_plan=[],
+               h_gram=[], h_compress=[])
     t_start = time.perf_counter()
     info = None
     for _ in range(steps):
-        f, tb, _ = step()
+        f, tb, _, tbw = step()
         info = f.info()                      # waits for the step's last kernel
         rec["build_s"].append(tb)
+        rec["bw_s"].append(tbw)
+        for key in ("prep", "plan", "gram", "compress"):
+            rec["h_" + key].append(info[f"t_{key}_ms"])
         rec["k_build"].append(info["t_build_ms"])
         rec["k_mv_t"].append(info["t_mv_t_ms"])
         rec["k_mv_n"].append(info["t_mv_n_ms"])
@@ -109,6 +115,8 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
     del f
     avg = {k: sum(v) / len(v) for k, v in rec.items()}
     return dict(ms_per_step=1e3 * t_total / steps, build_ms=1e3 * avg["build_s"], matvec_ms=1e3 * mv_s,
+                backward_ms=1e3 * avg["bw_s"],
+                build_phases_ms={k[2:]: round(avg[k], 3) for k in ("h_prep", "h_plan", "h_gram", "h_compress")},
                 k_build_ms=avg["k_build"], k_mv_t_ms=avg["k_mv_t"], k_mv_n_ms=avg["k_mv_n"],
                 k_mv_reduce_ms=avg["k_mv_red"], info=info)
 
@@ -206,7 +214,8 @@ def main():
     t_ms, nbytes = kernels[dom]
     achieved = nbytes / (t_ms * 1e-3) / 1e9
     traffic = read_traffic(dom, args.workload)
-    print(f"# step {res['ms_per_step']:.2f} ms (build {res['build_ms']:.2f} ms, matvec {res['matvec_ms']:.3f} ms); "
+    print(f"# step {res['ms_per_step']:.2f} ms (build {res['build_ms']:.2f} ms {res['build_phases_ms']}, "
+          f"matvec {res['matvec_ms']:.3f} ms, backward {res['backward_ms']:.2f} ms); "
           f"kernels build {res['k_build_ms']:.3f} mv_t {res['k_mv_t_ms']:.3f} mv_n {res['k_mv_n_ms']:.3f} ms; "
           f"p={info['degree_p']} r={r} H={H} S={S}", file=sys.stderr, flush=True)
     out = {

@@ -86,7 +86,11 @@ typedef struct {
   double   center_radius;  /* R = max_i ||x_i - c||                        */
   double   rho2_min, rho2_max;  /* interval of the radial basis           */
   int64_t  factor_bytes;   /* device bytes of the stored factor            */
-  double   t_prep_ms, t_plan_ms, t_gram_ms, t_compress_ms;
+  double   t_prep_ms;        /* host wall: geometry pass incl. its sync       */
+  double   t_plan_ms;        /* host work of the planner (degree, cores, tau) */
+  double   t_gram_ms;        /* host wall waiting on the Gram pass beyond the
+                                planner work that overlaps it                */
+  double   t_compress_ms;    /* host wall: compression incl. refinement pass */
   double   t_build_ms;       /* factor-evaluation kernel (HIP events)        */
   double   t_mv_t_ms;        /* last hdf_matvec: pass 1 kernel (U^T V)       */
   double   t_mv_reduce_ms;   /* last hdf_matvec: split reduction + scaling   */

@@ -64,6 +64,7 @@ struct hdf_factor {
   std::vector<double> a;                          // p+1 coefficients
   std::vector<std::vector<double>> cores;
   std::vector<hdf::DegreeFactor> deg;             // k = 0..K
+  std::vector<std::vector<double>> dC;            // per kept degree: E'^T (dM/dl) E' (s x s), lazily
   std::vector<hdf::DegDev> degs;                  // kept degrees
   std::vector<int> kept_k;
   std::vector<int32_t> index_table;               // H x (d-1)
@@ -213,11 +214,10 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   f->K = f->p / 2;
   f->a.assign(afull.begin(), afull.begin() + f->p + 1);
   hdf::radial_interval(f->geo.rho2_min, f->geo.rho2_max, &f->u0, &f->u1);
-  hdf::radial_cores(f->a.data(), f->p, d, f->u0, f->u1, f->cores);
-  f->tau = hdf::tau_threshold(tol, f->nu, n, d, f->p);
   f->t_plan = now_ms() - t0;
 
-  // 3. radial Gram moments on the device, second sync
+  // 3. radial Gram moments on the device, second sync; the radial cores and
+  // the threshold are formed on the host while the device runs
   t0 = now_ms();
   const int K = f->K;
   const int nrt = (K + 1 + 15) / 16, nct = (2 * K + 1 + 15) / 16;
@@ -234,8 +234,13 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   const int mcols = nct * 16;
   std::vector<double> mom((size_t)nrt * 16 * mcols);
   HIPCHK(hipMemcpyAsync(mom.data(), f->moments.p, mom.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  const double t_overlap = now_ms();
+  hdf::radial_cores(f->a.data(), f->p, d, f->u0, f->u1, f->cores);
+  f->tau = hdf::tau_threshold(tol, f->nu, n, d, f->p);
+  const double t_cores = now_ms() - t_overlap;
   HIPCHK(hipStreamSynchronize(s));
-  f->t_gram = now_ms() - t0;
+  f->t_plan += t_cores;
+  f->t_gram = now_ms() - t0 - t_cores;
 
   // 4. compression per degree.  The single-pass result from the first Gram
   // is accepted for a degree when its first-pass error stays below the
@@ -344,14 +349,18 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   if (f->H > 0) {
     HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
     HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
+    // The harmonic recurrences run up to the largest kept degree only:
+    // dropped top degrees would be evaluated and discarded by both the factor
+    // kernel and the adjoint.
+    const int Kh = f->kept_k.back();
     // loop-order column table
     std::vector<int32_t> col_of;
-    loop_order_columns(d, K, canon, col_of);
+    loop_order_columns(d, Kh, canon, col_of);
     HIPCHK(f->col_of.ensure(col_of.size() * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(f->col_of.p, col_of.data(), col_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     // recurrence coefficients as (A, B) pairs in the storage type
     hdf::ChainCoeffs cc;
-    hdf::chain_coeffs(d, K, cc);
+    hdf::chain_coeffs(d, Kh, cc);
     const size_t npair = cc.A.size();
     std::vector<double> pd(2 * npair);
     for (size_t i = 0; i < npair; ++i) { pd[2 * i] = cc.A[i]; pd[2 * i + 1] = cc.B[i]; }
@@ -406,7 +415,7 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
     tb.q_len = (const int32_t*)f->q_len.p;
     tb.q_off = (const int32_t*)f->q_off.p;
     tb.q_coef = f->q_coef.p;
-    tb.K = K;
+    tb.K = Kh;
     tb.S = (int)f->S;
     f->tables = tb;
     std::vector<hdf::DegDev> dbk(K + 1);
@@ -618,33 +627,44 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
   if (dlength) {
     // dF/dl = sum_{k,h,c} gw^T (E'_k^T dM_k/dl E'_k) gv, dM/dl from the Chebyshev
     // coefficients of dk/dl with the structure (degree, radius, basis) frozen.
+    // The cores of dk/dl (host work) are formed while the device runs the
+    // passes above, and kept with the factor for later calls.
+    if (h->dC.empty()) {
+      std::vector<double> da(hdf::kChebNodes);
+      hdf::chebyshev_coeffs(h->kernel, 2.0 * h->geo.R, h->l, hdf::kChebNodes, true, da.data());
+      std::vector<std::vector<double>> dM;
+      hdf::radial_cores(da.data(), h->p, h->d, h->u0, h->u1, dM);
+      h->dC.resize(h->degs.size());
+      for (size_t dj = 0; dj < h->degs.size(); ++dj) {
+        const hdf::DegreeFactor& df = h->deg[h->kept_k[dj]];
+        const int L = df.L, sk = df.s;
+        const std::vector<double>& M = dM[df.k];
+        std::vector<double> MEp((size_t)L * sk, 0.0);
+        std::vector<double>& dC = h->dC[dj];
+        dC.assign((size_t)sk * sk, 0.0);
+        for (int a = 0; a < L; ++a)
+          for (int l = 0; l < sk; ++l) {
+            double acc = 0.0;
+            for (int b = 0; b < L; ++b) acc += M[(size_t)a * L + b] * df.Ep[(size_t)l * L + b];
+            MEp[(size_t)a * sk + l] = acc;
+          }
+        for (int l = 0; l < sk; ++l)
+          for (int l2 = 0; l2 < sk; ++l2) {
+            double acc = 0.0;
+            for (int a = 0; a < L; ++a) acc += df.Ep[(size_t)l * L + a] * MEp[(size_t)a * sk + l2];
+            dC[(size_t)l * sk + l2] = acc;
+          }
+      }
+    }
     std::vector<double> gv((size_t)h->r * m16), gw((size_t)h->r * m16);
     HIPCHK(hipMemcpyAsync(gv.data(), h->bw_GV.p, gv.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(gw.data(), h->bw_GW.p, gw.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<double> da(hdf::kChebNodes);
-    hdf::chebyshev_coeffs(h->kernel, 2.0 * h->geo.R, h->l, hdf::kChebNodes, true, da.data());
-    std::vector<std::vector<double>> dM;
-    hdf::radial_cores(da.data(), h->p, h->d, h->u0, h->u1, dM);
     double dl = 0.0;
     for (size_t dj = 0; dj < h->degs.size(); ++dj) {
       const hdf::DegDev& dg = h->degs[dj];
-      const hdf::DegreeFactor& df = h->deg[h->kept_k[dj]];
-      const int L = df.L, sk = df.s;
-      const std::vector<double>& M = dM[df.k];
-      std::vector<double> MEp((size_t)L * sk, 0.0), dC((size_t)sk * sk, 0.0);
-      for (int a = 0; a < L; ++a)
-        for (int l = 0; l < sk; ++l) {
-          double acc = 0.0;
-          for (int b = 0; b < L; ++b) acc += M[(size_t)a * L + b] * df.Ep[(size_t)l * L + b];
-          MEp[(size_t)a * sk + l] = acc;
-        }
-      for (int l = 0; l < sk; ++l)
-        for (int l2 = 0; l2 < sk; ++l2) {
-          double acc = 0.0;
-          for (int a = 0; a < L; ++a) acc += df.Ep[(size_t)l * L + a] * MEp[(size_t)a * sk + l2];
-          dC[(size_t)l * sk + l2] = acc;
-        }
+      const int sk = dg.s;
+      const std::vector<double>& dC = h->dC[dj];
       for (int hh = 0; hh < dg.nh; ++hh)
         for (int c = 0; c < m; ++c)
           for (int l = 0; l < sk; ++l) {

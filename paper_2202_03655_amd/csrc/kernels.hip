@@ -1145,14 +1145,21 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
 // a group of up to 4 * kMvTPW work items (one 16-harmonic row tile x one
 // 16-wide output column tile each, degrees contiguous) and a range of points.
 // Per 32-point chunk it stages V (32 x m16) and the group's radial rows
-// (nq x 32) in LDS once; every wavefront then streams the Phi rows of its
-// items (two 16-byte loads per lane per item, batches of 4 items issued ahead
-// of their MFMAs) and forms B = q_{k,l}(i) V[i][c] from LDS.  All item
-// accumulators stay in registers for the whole point range, so Phi is read
-// once and V, q once per group.
+// (nq x 32) in LDS; every wavefront streams the Phi rows of its items (two
+// 16-byte loads per lane and item, in batches) and forms B = q_{k,l}(i) V[i][c]
+// from LDS.  Software pipeline: the Phi loads of the next batch (possibly the
+// first batch of the next chunk) are issued before the MFMAs of the current
+// one, and the next chunk's V and q are loaded into registers at the start of
+// a chunk and written to the other half of a double-buffered LDS area at its
+// end, so one barrier per chunk suffices.  All item accumulators stay in
+// registers for the whole point range.  Requires m16 <= 64 and nq <= 64
+// (eight staged values per thread and array).
 constexpr int kMvCH = 32;
 constexpr int kMvTPW = 16;
-constexpr int kMvBatch = 4;
+constexpr int kMvStage = 8;
+
+template <typename T>
+struct MvtBatch { static constexpr int value = 2; };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int64_t ld_phi,
@@ -1160,25 +1167,26 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
                                                    const DegDev* __restrict__ degs,
                                                    const TileDev* __restrict__ items,
                                                    const int32_t* __restrict__ group_items,
-                                                   const int32_t* __restrict__ group_q,
+                                                   const int32_t* __restrict__ group_q, int max_nq,
                                                    const T* __restrict__ V, int64_t ldv, int64_t n,
                                                    int m, int m16, int64_t split_len, int64_t rank,
                                                    double* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
+  constexpr int NB = MvtBatch<T>::value;
   extern __shared__ unsigned char smem_raw[];
   const int grp = blockIdx.y, split = blockIdx.x;
   const int it0 = group_items[grp], it1 = group_items[grp + 1];
   const int q_lo = group_q[2 * grp], nq = group_q[2 * grp + 1] - q_lo;
   const int vst = m16 + 1;                        // padded V row (bank spread)
-  T* vbuf = reinterpret_cast<T*>(smem_raw);       // [kMvCH][vst]
-  T* qbuf = vbuf + kMvCH * vst;                   // [nq][kMvCH]
+  const int half = kMvCH * vst + max_nq * kMvCH;  // one buffer: V then q
+  T* lds = reinterpret_cast<T*>(smem_raw);        // [2][half]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
   const int cpl = m16 / 16;
   const int my0 = it0 + wave * kMvTPW;
   int n_mine = it1 - my0;
   n_mine = n_mine < 0 ? 0 : (n_mine > kMvTPW ? kMvTPW : n_mine);
   // per-item descriptors resolved once: first Phi row, rows in the tile,
-  // LDS row of its radial function, output column base
+  // LDS offset of its radial row, output column base
   __shared__ int64_t d_row[4 * kMvTPW];
   __shared__ int32_t d_nr[4 * kMvTPW], d_qr[4 * kMvTPW], d_c[4 * kMvTPW];
   if (tid < 4 * kMvTPW && it0 + tid < it1) {
@@ -1187,53 +1195,93 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
     const int l = it.ct0 / cpl;
     d_row[tid] = (int64_t)(dg.hoff + it.h0);
     d_nr[tid] = dg.nh - it.h0;
-    d_qr[tid] = (dg.qoff + l - q_lo) * kMvCH;
+    d_qr[tid] = kMvCH * vst + (dg.qoff + l - q_lo) * kMvCH;
     d_c[tid] = (it.ct0 - l * cpl) * 16;
   }
-  Acc acc[kMvTPW];
-#pragma unroll
-  for (int i = 0; i < kMvTPW; ++i) acc[i] = Acc{0, 0, 0, 0};
   const int64_t p_begin = (int64_t)split * split_len;
   const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
   const int wbase = wave * kMvTPW;
-  for (int64_t p = p_begin; p < p_end; p += kMvCH) {
-    __syncthreads();
-    for (int e = tid; e < kMvCH * m16; e += 256) {
+
+  // staging of chunk p: thread tid owns V entries e = tid + 256 j (< 32 m16)
+  // and q entries e = tid + 256 j (< 32 nq)
+  T sv[kMvStage], sq[kMvStage];
+  auto stage_load = [&](int64_t p) {
+#pragma unroll
+    for (int j = 0; j < kMvStage; ++j) {
+      const int e = tid + 256 * j;
       const int pp = e / m16, c = e - pp * m16;
       const int64_t pt = p + pp;
-      vbuf[pp * vst + c] = (pt < p_end && c < m) ? V[pt * ldv + c] : (T)0;
+      sv[j] = (e < kMvCH * m16 && pt < p_end && c < m) ? V[pt * ldv + c] : (T)0;
+      const int r = e >> 5, pq = e & 31;
+      sq[j] = (e < kMvCH * nq && p + pq < p_end) ? q[(int64_t)(q_lo + r) * ld_q + p + pq] : (T)0;
     }
-    for (int e = tid; e < nq * kMvCH; e += 256) {
-      const int r = e / kMvCH, pp = e - r * kMvCH;
-      const int64_t pt = p + pp;
-      qbuf[r * kMvCH + pp] = (pt < p_end) ? q[(int64_t)(q_lo + r) * ld_q + pt] : (T)0;
+  };
+  auto stage_store = [&](T* buf) {
+#pragma unroll
+    for (int j = 0; j < kMvStage; ++j) {
+      const int e = tid + 256 * j;
+      const int pp = e / m16, c = e - pp * m16;
+      if (e < kMvCH * m16) buf[pp * vst + c] = sv[j];
+      if (e < kMvCH * nq) buf[kMvCH * vst + e] = sq[j];
     }
-    __syncthreads();
+  };
+  // Phi rows of items [b0, b0 + NB) at chunk p (clamped, in-bounds rows;
+  // callers guarantee n_mine > 0 so every descriptor read is initialised)
+  auto load_batch = [&](int64_t p, int b0, T (&a)[NB][8]) {
     const int64_t pb = p + 8 * g;
 #pragma unroll
-    for (int b0 = 0; b0 < kMvTPW; b0 += kMvBatch) {
-      if (b0 < n_mine) {                          // uniform
-        T a[kMvBatch][8];
+    for (int j = 0; j < NB; ++j) {
+      const int i = b0 + j;
+      const int di = wbase + (i < n_mine ? i : 0);
+      const bool ok = (i < n_mine) && li < d_nr[di];
+      load8(phi + (d_row[di] + (ok ? li : 0)) * ld_phi, pb, p_end, ok, a[j]);
+    }
+  };
+
+  Acc acc[kMvTPW];
 #pragma unroll
-        for (int j = 0; j < kMvBatch; ++j) {
-          const int i = b0 + j;
-          const int di = wbase + (i < n_mine ? i : 0);
-          const bool ok = (i < n_mine) && li < d_nr[di];
-          load8(phi + (d_row[di] + (ok ? li : 0)) * ld_phi, pb, p_end, ok, a[j]);
-        }
+  for (int i = 0; i < kMvTPW; ++i) acc[i] = Acc{0, 0, 0, 0};
+  stage_load(p_begin);
+  __syncthreads();                                // descriptors visible
+  stage_store(lds);
+  T a_cur[NB][8], a_nxt[NB][8];
+  if (n_mine > 0) load_batch(p_begin, 0, a_cur);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t p = p_begin; p < p_end; p += kMvCH) {
+    const int64_t pn = p + kMvCH;
+    const bool has_next = pn < p_end;             // uniform
+    if (has_next) stage_load(pn);
+    const T* cur = lds + buf * half;
+    if (n_mine > 0) {                             // uniform
 #pragma unroll
-        for (int j = 0; j < kMvBatch; ++j) {
-          const int i = b0 + j;
-          if (i < n_mine) {                       // uniform
-            const int di = wbase + i;
-            const T* qb = qbuf + d_qr[di] + 8 * g;
-            const T* vb = vbuf + (8 * g) * vst + d_c[di] + li;
+      for (int b0 = 0; b0 < kMvTPW; b0 += NB) {
+        if (b0 < n_mine) {                        // uniform
+          // next step: the following batch of this chunk, else batch 0 of
+          // the next chunk (re-reads this chunk's first batch at the end)
+          const bool same = b0 + NB < n_mine;
+          load_batch(same ? p : (has_next ? pn : p), same ? b0 + NB : 0, a_nxt);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) acc[i] = Mfma<T>::run(a[j][t], qb[t] * vb[t * vst], acc[i]);
+          for (int j = 0; j < NB; ++j) {
+            const int i = b0 + j;
+            if (i < n_mine) {                     // uniform
+              const int di = wbase + i;
+              const T* qb = cur + d_qr[di] + 8 * g;
+              const T* vb = cur + (8 * g) * vst + d_c[di] + li;
+#pragma unroll
+              for (int t = 0; t < 8; ++t) acc[i] = Mfma<T>::run(a_cur[j][t], qb[t] * vb[t * vst], acc[i]);
+            }
           }
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a_cur[j][t] = a_nxt[j][t];
         }
       }
     }
+    if (has_next) stage_store(lds + (buf ^ 1) * half);
+    __syncthreads();
+    buf ^= 1;
   }
   double* out = part + (int64_t)split * rank * m16;
 #pragma unroll
@@ -1254,7 +1302,8 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
 
 int matvec_items_per_group() { return 4 * kMvTPW; }
 size_t matvec_lds_bytes(int m16, int nq, int prec) {
-  return (size_t)(kMvCH * (m16 + 1) + nq * kMvCH) * (prec == 1 ? 4 : 8);
+  if (m16 > 64 || nq > 64) return SIZE_MAX;      // beyond the per-thread staging
+  return 2 * (size_t)(kMvCH * (m16 + 1) + nq * kMvCH) * (prec == 1 ? 4 : 8);
 }
 
 hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
@@ -1266,11 +1315,11 @@ hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, i
   const size_t lds = matvec_lds_bytes(m16, max_nq, prec);
   if (prec == 1)
     k_mv_t_lds<float><<<grid, 256, lds, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs, items,
-                                            group_items, group_q, (const float*)V, ldv, n, m, m16,
+                                            group_items, group_q, max_nq, (const float*)V, ldv, n, m, m16,
                                             split_len, rank, partials);
   else
     k_mv_t_lds<double><<<grid, 256, lds, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q, degs,
-                                             items, group_items, group_q, (const double*)V, ldv, n, m,
+                                             items, group_items, group_q, max_nq, (const double*)V, ldv, n, m,
                                              m16, split_len, rank, partials);
   return hipGetLastError();
 }

@@ -48,7 +48,8 @@ struct BuildTables {
   const int32_t* q_len;      // per radial row: L
   const int32_t* q_off;      // per radial row: offset into q_coef
   const void* q_coef;        // radial coefficients, storage type
-  int K, S;
+  int K;                     // largest kept degree: depth of the harmonic recurrences
+  int S;                     // radial rows
 };
 hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                         const GeoDev* geo, double u0, double u1, const BuildTables& tb,

@@ -24,8 +24,12 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <complex>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <cstring>
 #include <stdexcept>
 
@@ -55,8 +59,42 @@ double kernel_dl(int kind, double r, double l) {
 }
 
 // ---------------------------------------------------------------- DCT-II
-// Radix-2 iterative complex FFT (in place, forward sign -1).
-static void fft(std::vector<std::complex<double>>& x) {
+// Tables of a length-n DCT-II (FFT twiddles, post-twiddles, Chebyshev
+// nodes), evaluated once per length and kept for the process.
+namespace {
+struct DctTables {
+  std::vector<std::complex<double>> w;    // exp(-2 pi i j / n), j <= n/2
+  std::vector<double> pc, ps;             // cos, sin of -pi i / (2n)
+  std::vector<double> node;               // cos(pi (j + 1/2) / n)
+};
+const DctTables& dct_tables(size_t n) {
+  static std::mutex mu;
+  static std::map<size_t, std::unique_ptr<DctTables>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  std::unique_ptr<DctTables>& t = cache[n];
+  if (!t) {
+    t.reset(new DctTables());
+    t->w.resize(n / 2 + 1);
+    for (size_t j = 0; j < t->w.size(); ++j) {
+      const double ang = -2.0 * M_PI * (double)j / (double)n;
+      t->w[j] = std::complex<double>(std::cos(ang), std::sin(ang));
+    }
+    t->pc.resize(n);
+    t->ps.resize(n);
+    t->node.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+      const double ang = -M_PI * (double)i / (2.0 * (double)n);
+      t->pc[i] = std::cos(ang);
+      t->ps[i] = std::sin(ang);
+      t->node[i] = std::cos(M_PI * ((double)i + 0.5) / (double)n);
+    }
+  }
+  return *t;
+}
+}  // namespace
+
+// Radix-2 iterative complex FFT (in place, forward sign -1), n a power of 2.
+static void fft(std::vector<std::complex<double>>& x, const DctTables& tb) {
   const size_t n = x.size();
   for (size_t i = 1, j = 0; i < n; ++i) {
     size_t bit = n >> 1;
@@ -65,11 +103,13 @@ static void fft(std::vector<std::complex<double>>& x) {
     if (i < j) std::swap(x[i], x[j]);
   }
   for (size_t len = 2; len <= n; len <<= 1) {
-    const double ang = -2.0 * M_PI / (double)len;
+    const size_t stride = n / len;
     for (size_t i = 0; i < n; i += len) {
       for (size_t k = 0; k < len / 2; ++k) {
-        std::complex<double> w(std::cos(ang * (double)k), std::sin(ang * (double)k));
-        std::complex<double> u = x[i + k], v = x[i + k + len / 2] * w;
+        const std::complex<double> u = x[i + k], b = x[i + k + len / 2], t = tb.w[k * stride];
+        // plain product (std::complex's operator* takes a slow inf/nan path)
+        const std::complex<double> v(b.real() * t.real() - b.imag() * t.imag(),
+                                     b.real() * t.imag() + b.imag() * t.real());
         x[i + k] = u + v;
         x[i + k + len / 2] = u - v;
       }
@@ -78,29 +118,26 @@ static void fft(std::vector<std::complex<double>>& x) {
 }
 
 // y_i = sum_j f_j cos(pi i (2j+1) / (2n)) via one length-n FFT (Makhoul).
-static void dct2(const std::vector<double>& f, std::vector<double>& y) {
+static void dct2(const std::vector<double>& f, std::vector<double>& y, const DctTables& tb) {
   const size_t n = f.size();
   std::vector<std::complex<double>> v(n);
   for (size_t j = 0; j < n / 2; ++j) {
     v[j] = f[2 * j];
     v[n - 1 - j] = f[2 * j + 1];
   }
-  fft(v);
+  fft(v, tb);
   y.resize(n);
-  for (size_t i = 0; i < n; ++i) {
-    const double ang = -M_PI * (double)i / (2.0 * (double)n);
-    y[i] = (v[i] * std::complex<double>(std::cos(ang), std::sin(ang))).real();
-  }
+  for (size_t i = 0; i < n; ++i) y[i] = v[i].real() * tb.pc[i] - v[i].imag() * tb.ps[i];
 }
 
 void chebyshev_coeffs(int kind, double D, double l, int n, bool derivative, double* a) {
+  const DctTables& tb = dct_tables((size_t)n);
   std::vector<double> f(n), y;
   for (int j = 0; j < n; ++j) {
-    const double s = std::cos(M_PI * (j + 0.5) / n);
-    const double r = D * std::fabs(s);
+    const double r = D * std::fabs(tb.node[j]);
     f[j] = derivative ? kernel_dl(kind, r, l) : kernel_value(kind, r, l);
   }
-  dct2(f, y);
+  dct2(f, y, tb);
   for (int i = 0; i < n; ++i) a[i] = (i % 2) ? 0.0 : y[i] * 2.0 / n;
   a[0] *= 0.5;
 }
@@ -139,7 +176,10 @@ static void gauss_legendre(int n, std::vector<ld>& x, std::vector<ld>& w) {
       dp = n * (z * p1 - p0) / (z * z - 1);
       ld dz = p1 / dp;
       z -= dz;
-      if (fabsl(dz) < 1e-21L * (1 + fabsl(z))) {
+      // quadratic convergence: a step within a few ulps means the node is
+      // exact to the working precision (a bound below the type's epsilon
+      // would never be met and run every iteration)
+      if (fabsl(dz) <= 4 * LDBL_EPSILON * (1 + fabsl(z))) {
         // refresh the derivative at the converged node
         p0 = 1; p1 = z;
         for (int k = 2; k <= n; ++k) {
