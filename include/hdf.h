@@ -95,6 +95,7 @@ typedef struct {
   double   t_mv_t_ms;        /* last hdf_matvec: pass 1 kernel (U^T V)       */
   double   t_mv_reduce_ms;   /* last hdf_matvec: split reduction + scaling   */
   double   t_mv_n_ms;        /* last hdf_matvec: pass 2 kernel (U (D W))     */
+  double   t_adjoint_ms;     /* last hdf_backward with dX: adjoint kernels   */
   int32_t  n_refined;        /* degrees refined by the second Gram pass      */
   int32_t  s_k[HDF_MAX_DEGREE / 2 + 1];   /* kept radial rank per degree   */
 } hdf_info_t;

@@ -278,14 +278,30 @@ def objective(st, X, Wm, Vm, C=None):
     return np.sum(gw * _apply_core(st, C, gv))
 
 
-def grad_l(st, Wm, Vm):
-    """dF/dl = sum_c g_w^T (dC/dl) g_v with dM/dl from the coefficients of dk/dl."""
-    U, _ = features(st, st["X"])
+def passes(st, M, chunk=16384):
+    """U^T M over all points of st["X"], point chunk by point chunk."""
+    X = st["X"]
+    M = np.asarray(M, dtype=np.float64).reshape(X.shape[0], -1)
+    out = None
+    for s in range(0, X.shape[0], chunk):
+        U, _ = features(st, X[s:s + chunk])
+        part = U.T @ M[s:s + chunk]
+        out = part if out is None else out + part
+    return out
+
+
+def grad_l_from_passes(st, gw, gv):
+    """dF/dl = sum_c g_w^T (dC/dl) g_v from g_w = U^T W, g_v = U^T V, with
+    dM/dl from the Chebyshev coefficients of dk/dl (structure frozen)."""
     da = chebyshev.cheb_coeffs_dl(st["kernel"], st["D"], st["l"])
     dC = core_blocks(st, da)
-    gw = U.T @ Wm
-    gv = U.T @ Vm
     return float(np.sum(gw * _apply_core(st, dC, gv)))
+
+
+def grad_l(st, Wm, Vm):
+    """dF/dl for F = sum_c w_c^T U C(l) U^T v_c (structure frozen)."""
+    U, _ = features(st, st["X"])
+    return grad_l_from_passes(st, U.T @ Wm, U.T @ Vm)
 
 
 def grad_x(st, Wm, Vm, h=1e-30):

@@ -74,7 +74,8 @@ struct hdf_factor {
   double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_build = -1;
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
   hipEvent_t ev_mv[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool mv_timed = false;
+  hipEvent_t ev_adj[2] = {nullptr, nullptr};
+  bool mv_timed = false, adj_timed = false;
   // device storage
   DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
       lam_row, moments;
@@ -89,6 +90,8 @@ struct hdf_factor {
     if (ev_b0) hipEventDestroy(ev_b0);
     if (ev_b1) hipEventDestroy(ev_b1);
     for (auto& e : ev_mv)
+      if (e) hipEventDestroy(e);
+    for (auto& e : ev_adj)
       if (e) hipEventDestroy(e);
   }
   size_t elem() const { return prec == HDF_MIXED ? 4 : 8; }
@@ -605,6 +608,9 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
     // radial rows staged in LDS per launch: at most 64 KiB (values + derivatives)
     const int max_rows = (int)(65536 / (2 * 64 * el));
     bool first = true;
+    if (!h->ev_adj[0])
+      for (auto& e : h->ev_adj) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(h->ev_adj[0], s));
     size_t di = 0;
     while (di < h->degs.size()) {
       const int row0 = h->degs[di].qoff;
@@ -623,6 +629,8 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
       }
       di = dj;
     }
+    HIPCHK(hipEventRecord(h->ev_adj[1], s));
+    h->adj_timed = true;
   }
   if (dlength) {
     // dF/dl = sum_{k,h,c} gw^T (E'_k^T dM_k/dl E'_k) gv, dM/dl from the Chebyshev
@@ -711,7 +719,11 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   }
   info->t_build_ms = h->t_build;
   info->n_refined = h->n_refined;
-  info->t_mv_t_ms = info->t_mv_reduce_ms = info->t_mv_n_ms = -1.0;
+  info->t_mv_t_ms = info->t_mv_reduce_ms = info->t_mv_n_ms = info->t_adjoint_ms = -1.0;
+  if (h->adj_timed && hipEventSynchronize(h->ev_adj[1]) == hipSuccess) {
+    float a = 0;
+    if (hipEventElapsedTime(&a, h->ev_adj[0], h->ev_adj[1]) == hipSuccess) info->t_adjoint_ms = a;
+  }
   if (h->mv_timed && hipEventSynchronize(h->ev_mv[3]) == hipSuccess) {
     float a = 0.f, b = 0.f, c2 = 0.f;
     if (hipEventElapsedTime(&a, h->ev_mv[0], h->ev_mv[1]) == hipSuccess) info->t_mv_t_ms = a;

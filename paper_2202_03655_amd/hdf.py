@@ -36,6 +36,7 @@ class HDFInfo(ctypes.Structure):
         ("t_gram_ms", ctypes.c_double), ("t_compress_ms", ctypes.c_double),
         ("t_build_ms", ctypes.c_double), ("t_mv_t_ms", ctypes.c_double),
         ("t_mv_reduce_ms", ctypes.c_double), ("t_mv_n_ms", ctypes.c_double),
+        ("t_adjoint_ms", ctypes.c_double),
         ("n_refined", ctypes.c_int32),
         ("s_k", ctypes.c_int32 * (HDF_MAX_DEGREE // 2 + 1)),
     ]
