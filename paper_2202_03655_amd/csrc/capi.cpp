@@ -84,7 +84,12 @@ struct hdf_factor {
   DevBuf items_dev, gitems_dev, gq_dev;
   int items_cpl = 0, n_groups = 0, max_nq = 0;
   // matvec / adjoint workspace
-  DevBuf ws_part, ws_W, ws_Wd, bw_GV, bw_GVd, bw_GW, bw_GWd, degs_by_k;
+  DevBuf ws_part, ws_W, ws_Wd, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
+  // adjoint tables: row of U^T V per harmonic row in the recursion's visiting
+  // order, per-degree (s_k, first radial row), coefficient stream scratch
+  std::vector<int32_t> adj_src_host;
+  std::vector<hdf::KInfo> adj_kinfo_host;
+  DevBuf adj_src, adj_kinfo, adj_stream;
   hdf::BuildTables tables{};
   ~hdf_factor() {
     if (ev_b0) hipEventDestroy(ev_b0);
@@ -359,13 +364,30 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
     // loop-order column table
     std::vector<int32_t> col_of;
     loop_order_columns(d, Kh, canon, col_of);
+    {
+      // adjoint visiting order: harmonic rows (k, h, l) as the recursion meets them
+      std::vector<int32_t> deg_of(f->H);
+      for (size_t di = 0; di < f->degs.size(); ++di)
+        for (int hh = 0; hh < f->degs[di].nh; ++hh) deg_of[f->degs[di].hoff + hh] = (int32_t)di;
+      f->adj_src_host.clear();
+      f->adj_src_host.reserve(f->r);
+      for (int32_t col : col_of) {
+        if (col < 0) continue;
+        const hdf::DegDev& dg = f->degs[deg_of[col]];
+        const int hh = col - dg.hoff;
+        for (int l = 0; l < dg.s; ++l) f->adj_src_host.push_back(dg.roff + hh * dg.s + l);
+      }
+      f->adj_kinfo_host.assign(Kh + 2, hdf::KInfo{0, 0});
+      for (size_t di = 0; di < f->degs.size(); ++di)
+        f->adj_kinfo_host[f->kept_k[di]] = hdf::KInfo{f->degs[di].s, f->degs[di].qoff};
+    }
     HIPCHK(f->col_of.ensure(col_of.size() * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(f->col_of.p, col_of.data(), col_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     // recurrence coefficients as (A, B) pairs in the storage type
     hdf::ChainCoeffs cc;
     hdf::chain_coeffs(d, Kh, cc);
     const size_t npair = cc.A.size();
-    std::vector<double> pd(2 * npair);
+    std::vector<double> pd(2 * npair + 2, 0.0);     // one pad pair: the adjoint reads one ahead
     for (size_t i = 0; i < npair; ++i) { pd[2 * i] = cc.A[i]; pd[2 * i + 1] = cc.B[i]; }
     std::vector<int32_t> ql, qo;
     std::vector<double> qc;
@@ -599,12 +621,47 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
     if (dX) HIPCHK(hipMemset2DAsync(dX, lddx * el, 0, h->d * el, h->N, s));
     return HDF_OK;
   }
-  const int m16 = (int)((m + 15) / 16 * 16);
-  hdf_status st = pass1(h, Vm, m, ld, m16, h->bw_GV, h->bw_GVd, s, false);
-  if (st != HDF_OK) return st;
-  st = pass1(h, Wm, m, ld, m16, h->bw_GW, h->bw_GWd, s, false);
-  if (st != HDF_OK) return st;
+  // U^T V and U^T W: one pass 1 over [V | W] (2m columns; a pass costs the
+  // same for any m up to 16), two passes when 2m exceeds the column limit
+  const bool joint = 2 * m <= HDF_MAX_RHS;
+  int m16;
+  const void *Gv_d, *Gw_d;
+  const DevBuf *gv_src, *gw_src;
+  int64_t gw_col = 0;
+  if (joint) {
+    const int64_t m2 = 2 * m;
+    m16 = (int)((m2 + 15) / 16 * 16);
+    HIPCHK(h->bw_VW.ensure((size_t)h->N * m2 * el));
+    HIPCHK(hipMemcpy2DAsync(h->bw_VW.p, m2 * el, Vm, ld * el, m * el, h->N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync((char*)h->bw_VW.p + m * el, m2 * el, Wm, ld * el, m * el, h->N,
+                            hipMemcpyDeviceToDevice, s));
+    hdf_status st = pass1(h, h->bw_VW.p, m2, m2, m16, h->bw_GV, h->bw_GVd, s, false);
+    if (st != HDF_OK) return st;
+    Gv_d = h->bw_GVd.p;
+    Gw_d = (const char*)h->bw_GVd.p + m * el;
+    gv_src = gw_src = &h->bw_GV;
+    gw_col = m;
+  } else {
+    m16 = (int)((m + 15) / 16 * 16);
+    hdf_status st = pass1(h, Vm, m, ld, m16, h->bw_GV, h->bw_GVd, s, false);
+    if (st != HDF_OK) return st;
+    st = pass1(h, Wm, m, ld, m16, h->bw_GW, h->bw_GWd, s, false);
+    if (st != HDF_OK) return st;
+    Gv_d = h->bw_GVd.p;
+    Gw_d = h->bw_GWd.p;
+    gv_src = &h->bw_GV;
+    gw_src = &h->bw_GW;
+  }
   if (dX) {
+    if (!h->adj_src.p) {
+      HIPCHK(h->adj_src.ensure(h->adj_src_host.size() * sizeof(int32_t)));
+      HIPCHK(h->adj_kinfo.ensure(h->adj_kinfo_host.size() * sizeof(hdf::KInfo)));
+      HIPCHK(hipMemcpyAsync(h->adj_src.p, h->adj_src_host.data(), h->adj_src_host.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->adj_kinfo.p, h->adj_kinfo_host.data(),
+                            h->adj_kinfo_host.size() * sizeof(hdf::KInfo), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(h->adj_stream.ensure(hdf::adjoint_stream_elems((int)h->r, (int)m) * el));
     // radial rows staged in LDS per launch: at most 64 KiB (values + derivatives)
     const int max_rows = (int)(65536 / (2 * 64 * el));
     bool first = true;
@@ -618,13 +675,14 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
       while (dj < h->degs.size() && h->degs[dj].qoff + h->degs[dj].s - row0 <= max_rows) ++dj;
       if (dj == di) return fail(HDF_E_INFEASIBLE, "radial rank of one degree exceeds the adjoint staging");
       const int row1 = h->degs[dj - 1].qoff + h->degs[dj - 1].s;
-      const int cstep = (m == 1) ? 1 : 4;
+      const int cstep = hdf::adjoint_cols_per_launch((int)m);
       for (int c0 = 0; c0 < m; c0 += cstep) {
         const int mc = (int)std::min<int64_t>(cstep, m - c0);
         HIPCHK(hdf::launch_adjoint(h->x_soa.p, h->dtype, h->ldN, h->N, h->d,
                                    (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, row0, row1,
-                                   (const hdf::DegDev*)h->degs_by_k.p, Wm, Vm, ld, c0, mc, m16,
-                                   h->bw_GVd.p, h->bw_GWd.p, dX, lddx, first ? 0 : 1, h->prec, s));
+                                   (const hdf::KInfo*)h->adj_kinfo.p, Gv_d, Gw_d, m16, (int)m,
+                                   (const int32_t*)h->adj_src.p, (int)h->r, h->adj_stream.p, Wm, Vm, ld,
+                                   c0, mc, dX, lddx, first ? 0 : 1, h->prec, s));
         first = false;
       }
       di = dj;
@@ -664,10 +722,14 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
           }
       }
     }
-    std::vector<double> gv((size_t)h->r * m16), gw((size_t)h->r * m16);
-    HIPCHK(hipMemcpyAsync(gv.data(), h->bw_GV.p, gv.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(gw.data(), h->bw_GW.p, gw.size() * 8, hipMemcpyDeviceToHost, s));
+    std::vector<double> gv((size_t)h->r * m16), gwbuf;
+    HIPCHK(hipMemcpyAsync(gv.data(), gv_src->p, gv.size() * 8, hipMemcpyDeviceToHost, s));
+    if (!joint) {
+      gwbuf.resize((size_t)h->r * m16);
+      HIPCHK(hipMemcpyAsync(gwbuf.data(), gw_src->p, gwbuf.size() * 8, hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
+    const double* gw = joint ? gv.data() + gw_col : gwbuf.data();
     double dl = 0.0;
     for (size_t dj = 0; dj < h->degs.size(); ++dj) {
       const hdf::DegDev& dg = h->degs[dj];

@@ -769,45 +769,98 @@ hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
 // where Gv = C U^T V, Gw = C U^T W and q' = dq/d(rho^2).  The harmonics and
 // their gradients are recomputed in the loop order of the factor kernel,
 // forward mode: every chain level carries (P, dP/dx_j, dP/dr_j^2) through its
-// recurrence, the running prefix product carries its full gradient.  One
-// wavefront per block; the per-point radial values and derivatives of the
-// rows [row0, row1) are staged in LDS, thread-major.
+// recurrence, the running prefix product carries its full gradient.
+//
+// Data access: the coefficients (Gv, Gw) are repacked beforehand into a
+// stream in the order the recursion visits the harmonics (k_adj_pack), so a
+// harmonic reads its s_k records at a running offset with no table lookup;
+// the per-degree record (s_k, first radial row) and the innermost level's
+// recurrence coefficients are fetched one iteration ahead.  The per-point
+// radial values and derivatives of the rows [row0, row1) are staged in LDS,
+// thread-major.  One wavefront per block.
 template <typename T, int D>
 struct AdjState {
   T xt[D], r2[D];
   T gacc[D];
   T sacc;
+  int ptr;                                        // offset into the stream
 };
 
 template <typename T, int D, int MB>
 struct AdjCtx {
-  const int32_t* col_of;
-  const typename Vec2<T>::type* chain;
-  const DegDev* degs_by_k;
-  const T* Gv;
-  const T* Gw;
-  int m16, mcols, K, row0, row1;
-  const T* qs;        // LDS: [2][nrows][64]
+  const typename Vec2<T>::type* chain;           // padded by one pair
+  const KInfo* kinfo;                             // per degree (s_k, qoff_k), padded by one
+  const T* stream;                                // padded by 4 records
+  int K, row0, row1, nrows;
+  const T* qs;                                    // LDS: [2][nrows][64]
   int lane;
   T wv[MB], vv[MB];
 };
+
+// One harmonic of degree k with value S and gradient gS (in xt).
+template <typename T, int D, int MB>
+__device__ __forceinline__ void adj_leaf(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, KInfo ki, T S,
+                                         const T* gS) {
+  const int s = ki.s;
+  if (s == 0) return;                             // dropped degree (uniform)
+  if (ki.qoff >= cx.row0 && ki.qoff + s <= cx.row1) {
+    const T* rec = cx.stream + st.ptr;
+    const int qr = ki.qoff - cx.row0;
+    T a = 0, bq = 0;
+    for (int l0 = 0; l0 < s; l0 += 4) {
+      T cv[4][2 * MB], q0[4], q1[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int e = 0; e < 2 * MB; ++e) cv[j][e] = rec[(l0 + j) * 2 * MB + e];
+        int rq = qr + l0 + j;
+        rq = rq < cx.nrows ? rq : cx.nrows - 1;  // in-bounds; unused past s
+        q0[j] = cx.qs[rq * 64 + cx.lane];
+        q1[j] = cx.qs[(cx.nrows + rq) * 64 + cx.lane];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (l0 + j < s) {                         // uniform
+          T alpha = 0;
+#pragma unroll
+          for (int c = 0; c < MB; ++c) alpha += cx.wv[c] * cv[j][2 * c] + cx.vv[c] * cv[j][2 * c + 1];
+          a += q0[j] * alpha;
+          bq += q1[j] * alpha;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) st.gacc[q] += a * gS[q];
+    st.sacc += bq * S;
+  }
+  st.ptr += s * 2 * MB;
+}
 
 template <typename T, int D, int MB, int LEVEL>
 struct AdjChain {
   typedef typename Vec2<T>::type T2;
   static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int b,
-                                             T pre, const T* gpre, int& t) {
+                                             T pre, const T* gpre) {
     const int cj = LEVEL - 1;                     // coordinate index of this level
     const T x = st.xt[cj], rr = st.r2[cj];
     const T2* cf = cx.chain + ((int64_t)(LEVEL - 1) * (cx.K + 1) + b) * (cx.K + 1);
     T pm1 = 0, pxm1 = 0, prm1 = 0;                // P_{n-1} and its partials
     T p = cf[0].x, px = 0, pr = 0;                // P_n
+    // next recurrence pair and (innermost level) next degree record, one
+    // iteration ahead; both tables carry one pad entry
+    // (index K + 1 - b of a row is the next row's first pair, or the pad)
+    T2 c_nxt = cf[0];
+    KInfo k_nxt = cx.kinfo[b];
     for (int nn = 0; nn <= cx.K - b; ++nn) {
+      const T2 c = c_nxt;
+      const KInfo ki = k_nxt;
+      c_nxt = cf[nn + 1];
+      if (LEVEL == 1) k_nxt = cx.kinfo[b + nn + 1];
       if (nn == 1) {
         pm1 = p; pxm1 = px; prm1 = pr;
-        p = cf[1].x * x; px = cf[1].x; pr = 0;
+        p = c.x * x; px = c.x; pr = 0;
       } else if (nn >= 2) {
-        const T A = cf[nn].x, B = cf[nn].y;
+        const T A = c.x, B = c.y;
         const T pn = A * x * p - B * rr * pm1;
         const T pxn = A * (p + x * px) - B * rr * pxm1;
         const T prn = A * x * pr - B * (pm1 + rr * prm1);
@@ -822,50 +875,23 @@ struct AdjChain {
         else if (q > cj) dP = 2 * st.xt[q] * pr;
         g[q] = gpre[q] * p + pre * dP;
       }
-      AdjChain<T, D, MB, LEVEL - 1>::run(st, cx, b + nn, pre * p, g, t);
+      if constexpr (LEVEL == 1) adj_leaf<T, D, MB>(st, cx, ki, pre * p, g);
+      else AdjChain<T, D, MB, LEVEL - 1>::run(st, cx, b + nn, pre * p, g);
     }
-  }
-};
-
-template <typename T, int D, int MB>
-struct AdjChain<T, D, MB, 0> {
-  static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int k,
-                                             T S, const T* gS, int& t) {
-    const int col = cx.col_of[t++];
-    if (col < 0) return;
-    const DegDev dg = cx.degs_by_k[k];
-    if (dg.qoff < cx.row0 || dg.qoff + dg.s > cx.row1) return;
-    const int h = col - dg.hoff;
-    T a = 0, bq = 0;
-    for (int l = 0; l < dg.s; ++l) {
-      const int64_t row = (int64_t)(dg.roff + h * dg.s + l) * cx.m16;
-      T alpha = 0;
-#pragma unroll
-      for (int c = 0; c < MB; ++c)
-        if (c < cx.mcols) alpha += cx.wv[c] * cx.Gv[row + c] + cx.vv[c] * cx.Gw[row + c];
-      const int qr = dg.qoff + l - cx.row0;
-      const int nrows = cx.row1 - cx.row0;
-      a += cx.qs[qr * 64 + cx.lane] * alpha;
-      bq += cx.qs[(nrows + qr) * 64 + cx.lane] * alpha;
-    }
-#pragma unroll
-    for (int q = 0; q < D; ++q) st.gacc[q] += a * gS[q];
-    st.sacc += bq * S;
   }
 };
 
 template <typename Tin, typename T, int D, int MB>
 __global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
                                                  const GeoDev* __restrict__ geo, double u0, double u1,
-                                                 const int32_t* __restrict__ col_of,
                                                  const typename Vec2<T>::type* __restrict__ chain,
                                                  const int32_t* __restrict__ q_len,
                                                  const int32_t* __restrict__ q_off,
                                                  const T* __restrict__ q_coef, int K, int row0, int row1,
-                                                 const DegDev* __restrict__ degs_by_k,
+                                                 const KInfo* __restrict__ kinfo,
+                                                 const T* __restrict__ stream,
                                                  const T* __restrict__ Wm, const T* __restrict__ Vm,
-                                                 int64_t ld, int c0, int mcols, int m16,
-                                                 const T* __restrict__ Gv, const T* __restrict__ Gw,
+                                                 int64_t ld, int c0, int mcols,
                                                  T* __restrict__ dX, int64_t lddx, int accumulate) {
   extern __shared__ unsigned char smem_raw[];
   T* qs = reinterpret_cast<T*>(smem_raw);
@@ -891,6 +917,7 @@ __global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, i
 #pragma unroll
   for (int q = 0; q < D; ++q) st.gacc[q] = 0;
   st.sacc = 0;
+  st.ptr = 0;
   // radial values and d/d(rho^2) for the rows of this launch (Clenshaw)
   const T tt = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
   const T dt_drho2 = (T)(2.0 / (u1 - u0));
@@ -909,15 +936,14 @@ __global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, i
     qs[(nrows + r) * 64 + lane] = (b1 + tt * d1 - d2) * dt_drho2;
   }
   AdjCtx<T, D, MB> cx;
-  cx.col_of = col_of; cx.chain = chain; cx.degs_by_k = degs_by_k; cx.Gv = Gv + c0; cx.Gw = Gw + c0;
-  cx.m16 = m16; cx.mcols = mcols; cx.K = K; cx.row0 = row0; cx.row1 = row1; cx.qs = qs; cx.lane = lane;
+  cx.chain = chain; cx.kinfo = kinfo; cx.stream = stream;
+  cx.K = K; cx.row0 = row0; cx.row1 = row1; cx.nrows = nrows; cx.qs = qs; cx.lane = lane;
 #pragma unroll
   for (int c = 0; c < MB; ++c) {
     cx.wv[c] = (valid && c < mcols) ? Wm[ii * ld + c0 + c] : (T)0;
     cx.vv[c] = (valid && c < mcols) ? Vm[ii * ld + c0 + c] : (T)0;
   }
   // azimuthal part outermost, exactly as the factor kernel
-  int t = 0;
   const T ax = st.xt[D - 2], ay = st.xt[D - 1];
   T cr = 1, ci = 0, pcr = 0, pci = 0;             // z^mm and z^(mm-1)
   const T inv_sqrt_2pi = (T)0.39894228040143267794, inv_sqrt_pi = (T)0.56418958354775628695;
@@ -935,12 +961,12 @@ __global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, i
     // Re z^m: d/dx = m Re z^{m-1}, d/dy = -m Im z^{m-1}
     g[D - 2] = cm * (T)mm * pcr;
     g[D - 1] = -cm * (T)mm * pci;
-    AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * cr, g, t);
+    AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * cr, g);
     if (mm > 0) {
       // Im z^m: d/dx = m Im z^{m-1}, d/dy = m Re z^{m-1}
       g[D - 2] = cm * (T)mm * pci;
       g[D - 1] = cm * (T)mm * pcr;
-      AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * ci, g, t);
+      AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * ci, g);
     }
   }
   if (valid) {
@@ -954,21 +980,54 @@ __global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, i
   }
 }
 
+// Coefficient stream of the adjoint: record j (a harmonic row (k,h,l) in the
+// visiting order, source row src_row[j] of Gv and Gw) holds, for c < MB,
+// (Gv[src][c0 + c], Gw[src][c0 + c]); columns c >= mcols and the 4 pad
+// records after the last are zero.
+template <typename T, int MB>
+__global__ void k_adj_pack(const T* __restrict__ Gv, const T* __restrict__ Gw, int m16,
+                           const int32_t* __restrict__ src_row, int nrec, int c0, int mcols,
+                           T* __restrict__ stream) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (nrec + 4) * MB) return;
+  const int j = e / MB, c = e - j * MB;
+  T gv = 0, gw = 0;
+  if (j < nrec && c < mcols) {
+    const int64_t row = (int64_t)src_row[j] * m16;
+    gv = Gv[row + c0 + c];
+    gw = Gw[row + c0 + c];
+  }
+  stream[(int64_t)j * 2 * MB + 2 * c] = gv;
+  stream[(int64_t)j * 2 * MB + 2 * c + 1] = gw;
+}
+
+int adjoint_cols_per_launch(int m) { return m <= 1 ? 1 : 4; }
+
+size_t adjoint_stream_elems(int nrec, int m) {
+  return (size_t)(nrec + 4) * 2 * adjoint_cols_per_launch(m);
+}
+
 template <typename Tin, typename T, int MB>
 static hipError_t launch_adjoint_t(const void* x_soa, int64_t ldx, int64_t n, int d, const GeoDev* geo,
                                    double u0, double u1, const BuildTables& tb, int row0, int row1,
-                                   const DegDev* degs_by_k, const void* Wm, const void* Vm, int64_t ld,
-                                   int c0, int mcols, int m16, const void* Gv, const void* Gw, void* dX,
-                                   int64_t lddx, int accumulate, hipStream_t s) {
+                                   const KInfo* kinfo, const void* Gv, const void* Gw, int m16,
+                                   const int32_t* src_row, int nrec, void* stream, const void* Wm,
+                                   const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
+                                   int accumulate, hipStream_t s) {
+  {
+    const int tot = (nrec + 4) * MB;
+    k_adj_pack<T, MB><<<(tot + 255) / 256, 256, 0, s>>>((const T*)Gv, (const T*)Gw, m16, src_row, nrec, c0,
+                                                         mcols, (T*)stream);
+  }
   const dim3 grid((unsigned)((n + 63) / 64));
   const size_t lds = (size_t)2 * (row1 - row0) * 64 * sizeof(T);
   typedef typename Vec2<T>::type T2;
-#define ADJ_CASE(DD)                                                                               \
-  case DD:                                                                                         \
-    k_adjoint<Tin, T, DD, MB><<<grid, 64, lds, s>>>(                                               \
-        (const Tin*)x_soa, ldx, n, geo, u0, u1, tb.col_of, (const T2*)tb.chain, tb.q_len, tb.q_off, \
-        (const T*)tb.q_coef, tb.K, row0, row1, degs_by_k, (const T*)Wm, (const T*)Vm, ld, c0, mcols, \
-        m16, (const T*)Gv, (const T*)Gw, (T*)dX, lddx, accumulate);                                \
+#define ADJ_CASE(DD)                                                                                \
+  case DD:                                                                                          \
+    k_adjoint<Tin, T, DD, MB><<<grid, 64, lds, s>>>(                                                \
+        (const Tin*)x_soa, ldx, n, geo, u0, u1, (const T2*)tb.chain, tb.q_len, tb.q_off,            \
+        (const T*)tb.q_coef, tb.K, row0, row1, kinfo, (const T*)stream, (const T*)Wm, (const T*)Vm, \
+        ld, c0, mcols, (T*)dX, lddx, accumulate);                                                    \
     break;
   switch (d) {
     ADJ_CASE(3)
@@ -985,20 +1044,21 @@ static hipError_t launch_adjoint_t(const void* x_soa, int64_t ldx, int64_t n, in
 
 hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                           const GeoDev* geo, double u0, double u1, const BuildTables& tb,
-                          int row0, int row1, const DegDev* degs_by_k, const void* Wm,
-                          const void* Vm, int64_t ld, int c0, int mcols, int m16, const void* Gv,
-                          const void* Gw, void* dX, int64_t lddx, int accumulate, int prec,
-                          hipStream_t s) {
+                          int row0, int row1, const KInfo* kinfo, const void* Gv, const void* Gw,
+                          int m16, int m, const int32_t* src_row, int nrec, void* stream, const void* Wm,
+                          const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
+                          int accumulate, int prec, hipStream_t s) {
+#define ADJ_ARGS x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, kinfo, Gv, Gw, m16, src_row, nrec, stream, \
+                 Wm, Vm, ld, c0, mcols, dX, lddx, accumulate, s
   if (prec == 1 && dtype == 0) {
-    if (mcols <= 1)
-      return launch_adjoint_t<float, float, 1>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
-    return launch_adjoint_t<float, float, 4>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
+    if (adjoint_cols_per_launch(m) == 1) return launch_adjoint_t<float, float, 1>(ADJ_ARGS);
+    return launch_adjoint_t<float, float, 4>(ADJ_ARGS);
   }
   if (prec == 0 && dtype == 1) {
-    if (mcols <= 1)
-      return launch_adjoint_t<double, double, 1>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
-    return launch_adjoint_t<double, double, 4>(x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, degs_by_k, Wm, Vm, ld, c0, mcols, m16, Gv, Gw, dX, lddx, accumulate, s);
+    if (adjoint_cols_per_launch(m) == 1) return launch_adjoint_t<double, double, 1>(ADJ_ARGS);
+    return launch_adjoint_t<double, double, 4>(ADJ_ARGS);
   }
+#undef ADJ_ARGS
   return hipErrorInvalidValue;
 }
 

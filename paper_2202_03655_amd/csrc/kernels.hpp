@@ -104,14 +104,25 @@ hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64
 
 // Adjoint: dX[i] (+)= dF/dx_i for F = sum_c w_c^T U C U^T v_c, restricted to
 // the radial rows [row0, row1) (degrees whose rows lie inside) and the
-// right-hand-side columns [c0, c0 + mcols), mcols <= 4.  Gv = C U^T V and
-// Gw = C U^T W (rank x m16, storage type).  degs_by_k: one DegDev per degree
-// 0..K (s = 0 for dropped degrees).  accumulate != 0 adds into dX.
+// right-hand-side columns [c0, c0 + mcols), mcols <= adjoint_cols_per_launch(m).
+// Gv = C U^T V and Gw = C U^T W (rank x m, row stride m16, storage type).
+// src_row[j], j < nrec = rank, is the row of Gv/Gw of the j-th harmonic row
+// (k, h, l) in the visiting order of the recursion; kinfo[k] = (s_k, first
+// radial row of degree k) for k <= K + 1 (s = 0 for dropped degrees and the
+// pad entry).  `stream` is scratch of adjoint_stream_elems(nrec, m) elements.
+// The chain table of `tb` must carry one pad pair.  accumulate != 0 adds
+// into dX.
+struct KInfo {
+  int32_t s;      // s_k (0: degree dropped)
+  int32_t qoff;   // first radial row of the degree
+};
+int adjoint_cols_per_launch(int m);
+size_t adjoint_stream_elems(int nrec, int m);
 hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
                           const GeoDev* geo, double u0, double u1, const BuildTables& tb,
-                          int row0, int row1, const DegDev* degs_by_k, const void* Wm,
-                          const void* Vm, int64_t ld, int c0, int mcols, int m16, const void* Gv,
-                          const void* Gw, void* dX, int64_t lddx, int accumulate, int prec,
-                          hipStream_t s);
+                          int row0, int row1, const KInfo* kinfo, const void* Gv, const void* Gw,
+                          int m16, int m, const int32_t* src_row, int nrec, void* stream, const void* Wm,
+                          const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
+                          int accumulate, int prec, hipStream_t s);
 
 }  // namespace hdf

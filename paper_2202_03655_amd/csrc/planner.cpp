@@ -375,7 +375,7 @@ void chain_coeffs(int d, int K, ChainCoeffs& out) {
       };
       const size_t base = out.idx(level, b, 0);
       out.A[base + 0] = (double)expl(-0.5L * logh(0));                 // c0
-      out.A[base + 1] = (double)(2 * lam * expl(-0.5L * logh(1)));     // c1
+      if (b < K) out.A[base + 1] = (double)(2 * lam * expl(-0.5L * logh(1)));   // c1 (rows of length >= 2)
       for (int n = 1; n + 1 <= K - b; ++n) {
         const ld an = 2 * (n + lam) / (n + 1) * expl(0.5L * (logh(n) - logh(n + 1)));
         const ld bn = (n + 2 * lam - 1) / (n + 1) * expl(0.5L * (logh(n - 1) - logh(n + 1)));
