@@ -797,45 +797,55 @@ struct AdjCtx {
   T wv[MB], vv[MB];
 };
 
-// One harmonic of degree k with value S and gradient gS (in xt).
+// Coefficients of one harmonic of degree k (record (s_k, first radial row)
+// ki): a = sum_l q_{k,l} alpha_l and bq = sum_l q'_{k,l} alpha_l over its s_k
+// stream records; advances the stream offset.  NS = s_k when known.
+template <typename T, int D, int MB, int NS>
+__device__ __forceinline__ void adj_coef_fixed(const AdjCtx<T, D, MB>& cx, const T* rec, int qr, T& a, T& bq) {
+  T cv[NS][2 * MB], q0[NS], q1[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+#pragma unroll
+    for (int e = 0; e < 2 * MB; ++e) cv[j][e] = rec[j * 2 * MB + e];
+    q0[j] = cx.qs[(qr + j) * 64 + cx.lane];
+    q1[j] = cx.qs[(cx.nrows + qr + j) * 64 + cx.lane];
+  }
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    T alpha = 0;
+#pragma unroll
+    for (int c = 0; c < MB; ++c) alpha += cx.wv[c] * cv[j][2 * c] + cx.vv[c] * cv[j][2 * c + 1];
+    a += q0[j] * alpha;
+    bq += q1[j] * alpha;
+  }
+}
+
 template <typename T, int D, int MB>
-__device__ __forceinline__ void adj_leaf(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, KInfo ki, T S,
-                                         const T* gS) {
+__device__ __forceinline__ void adj_coef(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, KInfo ki, T& a,
+                                         T& bq) {
+  a = 0;
+  bq = 0;
   const int s = ki.s;
   if (s == 0) return;                             // dropped degree (uniform)
   if (ki.qoff >= cx.row0 && ki.qoff + s <= cx.row1) {
     const T* rec = cx.stream + st.ptr;
     const int qr = ki.qoff - cx.row0;
-    T a = 0, bq = 0;
-    for (int l0 = 0; l0 < s; l0 += 4) {
-      T cv[4][2 * MB], q0[4], q1[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-#pragma unroll
-        for (int e = 0; e < 2 * MB; ++e) cv[j][e] = rec[(l0 + j) * 2 * MB + e];
-        int rq = qr + l0 + j;
-        rq = rq < cx.nrows ? rq : cx.nrows - 1;  // in-bounds; unused past s
-        q0[j] = cx.qs[rq * 64 + cx.lane];
-        q1[j] = cx.qs[(cx.nrows + rq) * 64 + cx.lane];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (l0 + j < s) {                         // uniform
-          T alpha = 0;
-#pragma unroll
-          for (int c = 0; c < MB; ++c) alpha += cx.wv[c] * cv[j][2 * c] + cx.vv[c] * cv[j][2 * c + 1];
-          a += q0[j] * alpha;
-          bq += q1[j] * alpha;
-        }
+    switch (s) {                                  // uniform
+      case 1: adj_coef_fixed<T, D, MB, 1>(cx, rec, qr, a, bq); break;
+      case 2: adj_coef_fixed<T, D, MB, 2>(cx, rec, qr, a, bq); break;
+      case 3: adj_coef_fixed<T, D, MB, 3>(cx, rec, qr, a, bq); break;
+      default: {
+        int l0 = 0;
+        for (; l0 + 4 <= s; l0 += 4) adj_coef_fixed<T, D, MB, 4>(cx, rec + l0 * 2 * MB, qr + l0, a, bq);
+        for (; l0 < s; ++l0) adj_coef_fixed<T, D, MB, 1>(cx, rec + l0 * 2 * MB, qr + l0, a, bq);
       }
     }
-#pragma unroll
-    for (int q = 0; q < D; ++q) st.gacc[q] += a * gS[q];
-    st.sacc += bq * S;
   }
   st.ptr += s * 2 * MB;
 }
 
+// Levels >= 2 of the polar chain: forward mode, the prefix and its gradient
+// passed down.
 template <typename T, int D, int MB, int LEVEL>
 struct AdjChain {
   typedef typename Vec2<T>::type T2;
@@ -846,21 +856,12 @@ struct AdjChain {
     const T2* cf = cx.chain + ((int64_t)(LEVEL - 1) * (cx.K + 1) + b) * (cx.K + 1);
     T pm1 = 0, pxm1 = 0, prm1 = 0;                // P_{n-1} and its partials
     T p = cf[0].x, px = 0, pr = 0;                // P_n
-    // next recurrence pair and (innermost level) next degree record, one
-    // iteration ahead; both tables carry one pad entry
-    // (index K + 1 - b of a row is the next row's first pair, or the pad)
-    T2 c_nxt = cf[0];
-    KInfo k_nxt = cx.kinfo[b];
     for (int nn = 0; nn <= cx.K - b; ++nn) {
-      const T2 c = c_nxt;
-      const KInfo ki = k_nxt;
-      c_nxt = cf[nn + 1];
-      if (LEVEL == 1) k_nxt = cx.kinfo[b + nn + 1];
       if (nn == 1) {
         pm1 = p; pxm1 = px; prm1 = pr;
-        p = c.x * x; px = c.x; pr = 0;
+        p = cf[1].x * x; px = cf[1].x; pr = 0;
       } else if (nn >= 2) {
-        const T A = c.x, B = c.y;
+        const T A = cf[nn].x, B = cf[nn].y;
         const T pn = A * x * p - B * rr * pm1;
         const T pxn = A * (p + x * px) - B * rr * pxm1;
         const T prn = A * x * pr - B * (pm1 + rr * prm1);
@@ -868,16 +869,69 @@ struct AdjChain {
         p = pn; px = pxn; pr = prn;
       }
       T g[D];
+      const T ppr = pre * pr;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        T dP = 0;
-        if (q == cj) dP = px + 2 * st.xt[q] * pr;
-        else if (q > cj) dP = 2 * st.xt[q] * pr;
-        g[q] = gpre[q] * p + pre * dP;
+        T gq = gpre[q] * p;
+        if (q == cj) gq += pre * px + 2 * st.xt[q] * ppr;
+        else if (q > cj) gq += 2 * st.xt[q] * ppr;
+        g[q] = gq;
       }
-      if constexpr (LEVEL == 1) adj_leaf<T, D, MB>(st, cx, ki, pre * p, g);
-      else AdjChain<T, D, MB, LEVEL - 1>::run(st, cx, b + nn, pre * p, g);
+      AdjChain<T, D, MB, LEVEL - 1>::run(st, cx, b + nn, pre * p, g);
     }
+  }
+};
+
+// Innermost level (coordinate 0, one harmonic per step, degree k = b + nn):
+// reverse mode.  With S = pre P, grad S = gpre P + pre (e_0 dP/dx + 2 xt dP/dr),
+// the harmonic's share a grad S + 2 xt bq S sums over the loop to
+//   gpre X1 + pre (e_0 X2 + 2 xt X3)  and  2 xt pre X4,
+// X1 = sum a P, X2 = sum a dP/dx, X3 = sum a dP/dr, X4 = sum bq P, so the
+// D-vector update happens once per loop.  The recurrence pair and the degree
+// record of the next step are fetched one step ahead (both tables padded).
+template <typename T, int D, int MB>
+struct AdjChain<T, D, MB, 1> {
+  typedef typename Vec2<T>::type T2;
+  static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int b,
+                                             T pre, const T* gpre) {
+    const T x = st.xt[0], rr = st.r2[0];
+    const T2* cf = cx.chain + (int64_t)b * (cx.K + 1);
+    T X1 = 0, X2 = 0, X3 = 0, X4 = 0, a, bq;
+    // step 0: P = c0
+    T p = cf[0].x, px = 0, pr = 0;
+    KInfo k_nxt = cx.kinfo[b + 1];
+    adj_coef<T, D, MB>(st, cx, cx.kinfo[b], a, bq);
+    X1 += a * p;
+    X4 += bq * p;
+    if (b < cx.K) {
+      // step 1: P = c1 x
+      T2 c_nxt = cf[2];                           // index K + 1 - b at most: next row or pad
+      const KInfo ki = k_nxt;
+      k_nxt = cx.kinfo[b + 2];
+      T pm1 = p, pxm1 = 0, prm1 = 0;
+      p = cf[1].x * x; px = cf[1].x; pr = 0;
+      adj_coef<T, D, MB>(st, cx, ki, a, bq);
+      X1 += a * p; X2 += a * px; X4 += bq * p;
+      for (int nn = 2; nn <= cx.K - b; ++nn) {
+        const T2 c = c_nxt;
+        const KInfo kc = k_nxt;
+        c_nxt = cf[nn + 1];
+        k_nxt = cx.kinfo[b + nn + 1];
+        const T Ax = c.x * x, Brr = c.y * rr;
+        const T pn = Ax * p - Brr * pm1;
+        const T pxn = c.x * p + Ax * px - Brr * pxm1;
+        const T prn = Ax * pr - c.y * pm1 - Brr * prm1;
+        pm1 = p; pxm1 = px; prm1 = pr;
+        p = pn; px = pxn; pr = prn;
+        adj_coef<T, D, MB>(st, cx, kc, a, bq);
+        X1 += a * p; X2 += a * px; X3 += a * pr; X4 += bq * p;
+      }
+    }
+    const T pX3 = 2 * pre * X3;
+#pragma unroll
+    for (int q = 0; q < D; ++q) st.gacc[q] += gpre[q] * X1 + st.xt[q] * pX3;
+    st.gacc[0] += pre * X2;
+    st.sacc += pre * X4;
   }
 };
 
