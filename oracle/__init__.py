@@ -28,6 +28,8 @@ Hyperspherical Harmonics" (Ryan & Damle, ICML 2022) step by step:
                    truncated eigendecomposition (Eq. svd, Eq. rapprox), factor
                    assembly and the O(Nr) matvec (Sec. 3.6), plus the
                    frozen-structure derivatives,
+* cross.py      -- Algorithm 1 in the general case X != Y (QR of both radial
+                   matrices, SVD of R_x M_k R_y^T, K(X, Y) ~ U V^T),
 * dense.py      -- the dense kernel matrix and its truncated eigendecomposition
                    (the optimal-rank reference of Sec. 4.1, Fig. 3).
 

@@ -18,6 +18,20 @@ def dense_K(X, name, l):
     return kappa(name, cdist(X, X), l)
 
 
+def dense_K_cross(X, Y, name, l):
+    """K(X, Y)_ij = k(||x_i - y_j||)."""
+    return kappa(name, cdist(np.asarray(X, dtype=np.float64), np.asarray(Y, dtype=np.float64)), l)
+
+
+def optimal_rank_cross(K, eps):
+    """Smallest r with ||K - K_r||_F <= eps ||K||_F (Eckart-Young, SVD)."""
+    sv = np.sort(np.linalg.svd(K, compute_uv=False))      # ascending
+    tail = np.sqrt(np.cumsum(sv ** 2))
+    budget = eps * np.linalg.norm(sv)
+    dropped = int(np.searchsorted(tail, budget, side="right"))
+    return len(sv) - dropped
+
+
 def rel_fro_error(K, Kt):
     return float(np.linalg.norm(K - Kt) / np.linalg.norm(K))
 

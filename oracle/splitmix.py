@@ -31,13 +31,15 @@ class SplitMix64:
         return z ^ (z >> 31)
 
 
-def sample_pairs(N, M=NU_PAIRS, seed=NU_SEED):
+def sample_pairs(N, M=NU_PAIRS, seed=NU_SEED, Nb=None):
+    """M index pairs (a_t, b_t), a_t < N, b_t < Nb (default N), two outputs per pair."""
+    Nb = N if Nb is None else Nb
     g = SplitMix64(seed)
     a = np.empty(M, dtype=np.int64)
     b = np.empty(M, dtype=np.int64)
     for t in range(M):
         a[t] = (g.next() >> 11) % N
-        b[t] = (g.next() >> 11) % N
+        b[t] = (g.next() >> 11) % Nb
     return a, b
 
 
@@ -49,6 +51,23 @@ def norm_scale(X, name, l, M=NU_PAIRS, seed=NU_SEED):
     s = np.zeros(M)
     for j in range(d):
         t = X[a, j] - X[b, j]
+        s = s + t * t
+    kv = kappa(name, np.sqrt(s), l)
+    acc = 0.0
+    for t in range(M):
+        acc += kv[t] * kv[t]
+    return float(np.sqrt(acc / M))
+
+
+def norm_scale_cross(X, Y, name, l, M=NU_PAIRS, seed=NU_SEED):
+    """nu = sqrt(mean_t k(||x_a - y_b||)^2), a < N_x, b < N_y: estimates
+    ||K(X, Y)||_F / sqrt(N_x N_y)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    a, b = sample_pairs(X.shape[0], M, seed, Nb=Y.shape[0])
+    s = np.zeros(M)
+    for j in range(X.shape[1]):
+        t = X[a, j] - Y[b, j]
         s = s + t * t
     kv = kappa(name, np.sqrt(s), l)
     acc = 0.0

@@ -12,7 +12,7 @@ import pytest
 import scipy.special as ss
 from numpy.polynomial import chebyshev as npcheb
 
-from oracle import chebyshev, dense, expansion, geometry, harmonics, hdf, kernels, splitmix
+from oracle import chebyshev, cross, dense, expansion, geometry, harmonics, hdf, kernels, splitmix
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -468,3 +468,72 @@ def test_gradients_vs_dense_closed_form():
     G = hdf.grad_x(st, w[:, None], v[:, None])
     Gd = dense.dense_grad_x(X, "gaussian", l, w, v)
     assert np.linalg.norm(G - Gd) <= 1e-3 * np.linalg.norm(Gd)
+
+
+# ----------------------------------------------- Q17 general case X != Y
+@pytest.mark.parametrize("d,name,l,tol", [(3, "gaussian", 1.0, 1e-6), (4, "cauchy", 1.0, 1e-4),
+                                          (5, "matern52", 2.0, 1e-5)])
+def test_cross_with_y_equal_x_is_the_symmetric_factor(d, name, l, tol):
+    # R_x M R_y^T is then symmetric, its singular values are |lambda| and
+    # U V^T = U D U^T: same degree, threshold, ranks and approximation
+    rng = np.random.default_rng(40 + d)
+    X = unit_ball(rng, 300, d)
+    st = hdf.build(X, name, l, tol)
+    sc = cross.build_cross(X, X, name, l, tol)
+    assert sc["p"] == st["p"] and sc["nu"] == st["nu"]
+    assert abs(sc["tau"] / st["tau"] - 1) < 1e-15
+    for dc, ds in zip(sc["deg"], st["deg"]):
+        np.testing.assert_allclose(dc["sig_all"], np.sort(np.abs(ds["lam_all"]))[::-1],
+                                   atol=1e-12 * np.max(np.abs(ds["lam_all"])))
+        assert dc["s"] == ds["s"]
+    U, Dv = hdf.factor(st)
+    Ux, Vy = cross.factor_cross(sc)
+    Ks = (U * Dv) @ U.T
+    assert np.max(np.abs(Ux @ Vy.T - Ks)) <= 1e-12 * np.max(np.abs(Ks))
+
+
+@pytest.mark.parametrize("d,name", [(3, "gaussian"), (4, "matern32"), (6, "cauchy")])
+def test_cross_uncompressed_reproduces_chebyshev_kernel(d, name):
+    # tau = 0 keeps every singular value: U V^T is the degree-p Chebyshev
+    # kernel between the two sets (different sizes and distributions)
+    rng = np.random.default_rng(50 + d)
+    X = unit_ball(rng, 90, d) * 1.3 + 0.2
+    Y = rng.uniform(-1.0, 1.0, size=(70, d))
+    p = 10
+    sc = cross.build_cross(X, Y, name, 1.0, 1e-6, p=p, tau=0.0)
+    Ux, Vy = cross.factor_cross(sc)
+    from scipy.spatial.distance import cdist
+    Kp = npcheb.chebval(cdist(X, Y) / sc["D"], sc["a"][: p + 1])
+    assert np.max(np.abs(Ux @ Vy.T - Kp)) < 1e-12
+    assert sc["r"] == sum(harmonics.count(d, k) * (p // 2 - k + 1) for k in range(p // 2 + 1))
+
+
+@pytest.mark.parametrize("d,name,l,tol,nx,ny", [
+    (3, "gaussian", 1.0, 1e-6, 900, 500),
+    (4, "cauchy", 1.0, 1e-5, 700, 400),
+    (5, "matern52", 1.0, 1e-3, 500, 600),
+])
+def test_cross_guarantee_against_dense(d, name, l, tol, nx, ny, capsys):
+    rng = np.random.default_rng(60 + d)
+    X = unit_ball(rng, nx, d)                               # training-like set
+    Y = unit_ball(rng, ny, d) * 0.8 + 0.1                   # shifted query set
+    sc = cross.build_cross(X, Y, name, l, tol)
+    Ux, Vy = cross.factor_cross(sc)
+    K = dense.dense_K_cross(X, Y, name, l)
+    assert dense.rel_fro_error(K, Ux @ Vy.T) <= tol
+    # nu estimates ||K(X, Y)||_F / sqrt(N_x N_y)
+    assert abs(sc["nu"] * np.sqrt(nx * ny) / np.linalg.norm(K) - 1) < 0.05
+    W = rng.normal(size=(ny, 2))
+    np.testing.assert_allclose(cross.matvec_cross(sc, W, Ux, Vy), (Ux @ Vy.T) @ W, rtol=1e-11, atol=1e-11)
+    # every kept singular value is above tau, every dropped one at or below
+    for dd in sc["deg"]:
+        assert np.all(dd["sig"] > sc["tau"]) and np.all(dd["sig_all"][dd["s"]:] <= sc["tau"])
+    ropt = dense.optimal_rank_cross(K, tol)
+    print(f"cross rank {sc['r']} vs optimal {ropt}")
+    assert sc["r"] >= ropt
+
+
+def test_norm_scale_cross_reduces_to_symmetric():
+    rng = np.random.default_rng(70)
+    X = rng.normal(size=(250, 4))
+    assert splitmix.norm_scale_cross(X, X, "cauchy", 1.3) == splitmix.norm_scale(X, "cauchy", 1.3)
