@@ -75,6 +75,7 @@ typedef struct {
   int32_t  n_dim;          /* d                                            */
   int32_t  precision;      /* hdf_precision                                */
   int64_t  n_points;       /* N                                            */
+  int64_t  n_points_y;     /* general factor K(X, Y): N_y (0: symmetric)     */
   int32_t  degree_p;       /* Chebyshev degree p (even)                    */
   int32_t  n_degrees;      /* p/2 + 1 harmonic degrees k = 0..p/2          */
   int64_t  n_harmonics;    /* H, harmonics of kept degrees (s_k > 0)       */
@@ -107,16 +108,36 @@ typedef struct {
  *           in Frobenius form).
  *   prec    HDF_MIXED (dtype must be 0) or HDF_FP64 (dtype must be 1).
  *   out     receives the handle; untouched on error.
- * The handle keeps its own copy of the points.  Two blocking device-to-host
- * synchronisations happen on `hip_stream` (after the geometry pass and after
- * the radial Gram pass) because the degree and the ranks depend on the data.
+ * The handle keeps its own copy of the points.  Blocking device-to-host
+ * synchronisations happen on `hip_stream` after the geometry pass and after
+ * the radial Gram pass (the degree and the ranks depend on the data), and
+ * after a second, binary64 Gram pass when a degree's first-pass Gram is too
+ * ill-conditioned for the target accuracy.
  * HDF_E_INFEASIBLE when p > HDF_MAX_DEGREE or the factor would need more than
  * max(1 GiB, 60% of the free device memory). */
 hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld,
                      hdf_kernel kernel, double lengthscale, double tol,
                      hdf_precision prec, void* hip_stream, hdf_handle* out);
 
-/* KV = U D U^T V (Sec. 3.6, two passes over the factor, no host sync).
+/* General case X != Y (Algorithm 1 with two point sets): K(X, Y) ~ U V^T.
+ *   x       device, nx x d (leading dimension ldx >= d); y device, ny x d
+ *           (ldy >= d); both of the dtype matching prec, as for hdf_build.
+ * One normalisation (centre, radius, radial interval) covers X u Y; ||K||_F
+ * is estimated over sampled pairs (x_a, y_b), and the threshold uses
+ * sqrt(nx ny) in place of N (Sec. 3.5 budget).  Per degree the two radial
+ * matrices are factorised from their Gram blocks and the core R_x M R_y^T is
+ * truncated by its singular values (Sec. 3.4, Eq. svd / Eq. rapprox).  The
+ * handle then serves hdf_matvec (KV = K(X, Y) V, V of ny rows, KV of nx rows),
+ * hdf_info (n_points = nx, n_points_y = ny, lambda = singular values),
+ * hdf_get_plan (radial coefficients of the X side), hdf_copy_factor (X side)
+ * and hdf_copy_factor_y (Y side); hdf_backward returns HDF_E_ARG.  Errors and
+ * synchronisations as hdf_build. */
+hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y, int64_t ny,
+                           int64_t ldy, int dtype, int d, hdf_kernel kernel, double lengthscale,
+                           double tol, hdf_precision prec, void* hip_stream, hdf_handle* out);
+
+/* KV = U D U^T V (Sec. 3.6, two passes over the factor, no host sync); for a
+ * handle from hdf_build_cross, KV = U (V_y^T V) with V of ny rows.
  *   V   device, n x m (ldv >= m), KV device, n x m (ldkv >= m); same dtype as
  *       the points; 1 <= m <= HDF_MAX_RHS.  V and KV must not overlap. */
 hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv,
@@ -153,6 +174,11 @@ hdf_status hdf_get_plan(hdf_handle h, int32_t* index_table, double* lambda,
  * (Algorithm 1: Xbar^(k)[:, l] times the harmonic). */
 hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_out, int64_t ld_q,
                            void* hip_stream);
+/* As hdf_copy_factor for the Y side of a handle from hdf_build_cross
+ * (harmonics and radial functions at the ny points y; ld >= ny).
+ * HDF_E_ARG for a symmetric handle. */
+hdf_status hdf_copy_factor_y(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_out, int64_t ld_q,
+                             void* hip_stream);
 
 void        hdf_free(hdf_handle h);
 const char* hdf_status_string(hdf_status s);
@@ -185,6 +211,15 @@ hdf_status hdf_plan_cores(const double* a, int p, int d, double u0, double u1, d
 /* Index set H_k (Sec. 3.3) in the enumeration order: count = |H_k|
  * (App. B); table (may be NULL) receives count x (d-2) int32. */
 hdf_status hdf_plan_index_set(int d, int k, int32_t* table, int64_t* count);
+
+/* Cross compression of one degree from its two radial Gram blocks (single
+ * pass): Gx, Gy, M are L x L row-major (1 <= L <= 32); the eigenvalues of Gx,
+ * Gy at or below null_rel times their largest are treated as null.  Writes
+ * s = the number of singular values of R_x M R_y^T above tau, sig (s values,
+ * descending) and the radial coefficients Ex, Ey (L x s, column-major by
+ * column: Ex[l * L + a]).  Sec. 3.4 (Eq. svd, Eq. rapprox); host only. */
+hdf_status hdf_plan_compress_cross(int L, const double* Gx, const double* Gy, const double* M, double tau,
+                                   double null_rel, int32_t* s, double* sig, double* Ex, double* Ey);
 
 #ifdef __cplusplus
 }

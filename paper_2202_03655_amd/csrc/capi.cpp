@@ -65,6 +65,14 @@ struct hdf_factor {
   std::vector<std::vector<double>> cores;
   std::vector<hdf::DegreeFactor> deg;             // k = 0..K
   std::vector<std::vector<double>> dC;            // per kept degree: E'^T (dM/dl) E' (s x s), lazily
+  // general factor K(X, Y) ~ U V^T: the X side is the fields above (N, ldN,
+  // x_soa, phi, q, tables, deg[].E = Ex, deg[].lam = singular values), the Y
+  // side these
+  bool cross = false;
+  int64_t N2 = 0, ldN2 = 0;
+  std::vector<hdf::DegreeFactor> degy;            // deg[].E = Ey
+  DevBuf x_soa2, phi2, q2, q_coef2;
+  hdf::BuildTables tables2{};
   std::vector<hdf::DegDev> degs;                  // kept degrees
   std::vector<int> kept_k;
   std::vector<int32_t> index_table;               // H x (d-1)
@@ -146,6 +154,175 @@ void loop_order_columns(int d, int K, const std::map<std::vector<int>, int>& can
 
 
 }  // namespace
+
+// Kept degrees, harmonic tables, memory budget and the factor evaluation,
+// common to the symmetric and the general (X != Y) build.  A general factor
+// evaluates its Y side too, with the Y-side radial coefficients; its diagonal
+// is the identity (sqrt of the singular values is folded into both sides).
+static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
+  const int K = f->K, d = f->d, dtype = f->dtype;
+  const int prec = f->prec;
+  const int64_t n = f->N;
+  // kept degrees, offsets, tables
+  int64_t hoff = 0, qoff = 0, roff = 0;
+  std::map<std::vector<int>, int> canon;
+  for (int k = 0; k <= K; ++k) {
+    const hdf::DegreeFactor& df = f->deg[k];
+    if (df.s == 0) continue;
+    const int64_t nh = hdf::index_count(d, k);
+    hdf::DegDev dd{};
+    dd.hoff = (int32_t)hoff; dd.nh = (int32_t)nh; dd.qoff = (int32_t)qoff; dd.s = df.s; dd.roff = (int32_t)roff;
+    f->degs.push_back(dd);
+    f->kept_k.push_back(k);
+    std::vector<int32_t> tab;
+    hdf::index_set(d, k, tab);
+    for (int64_t h = 0; h < nh; ++h) {
+      std::vector<int> key(1, k);
+      f->index_table.push_back(k);
+      for (int j = 0; j < d - 2; ++j) {
+        key.push_back(tab[(size_t)h * (d - 2) + j]);
+        f->index_table.push_back(tab[(size_t)h * (d - 2) + j]);
+      }
+      canon[key] = (int)(hoff + h);
+    }
+    hoff += nh;
+    qoff += df.s;
+    roff += nh * df.s;
+    f->max_s = std::max(f->max_s, df.s);
+  }
+  f->H = hoff; f->S = qoff; f->r = roff;
+  f->t_compress = now_ms() - t0;
+
+  // 5. memory budget, then the factor evaluation
+  const size_t fbytes = (size_t)(f->H + f->S) * (f->ldN + (f->cross ? f->ldN2 : 0)) * f->elem();
+  size_t freeb = 0, totb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totb));
+  const size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)(0.6 * (double)freeb));
+  if (fbytes > budget) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "factor needs %.3g GB (H=%lld, S=%lld), budget %.3g GB",
+             fbytes / 1e9, (long long)f->H, (long long)f->S, budget / 1e9);
+    return fail(HDF_E_INFEASIBLE, buf);
+  }
+  if (f->H > 0) {
+    HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
+    HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
+    if (f->cross) {
+      HIPCHK(f->phi2.ensure((size_t)f->H * f->ldN2 * f->elem()));
+      HIPCHK(f->q2.ensure((size_t)f->S * f->ldN2 * f->elem()));
+    }
+    // The harmonic recurrences run up to the largest kept degree only:
+    // dropped top degrees would be evaluated and discarded by both the factor
+    // kernel and the adjoint.
+    const int Kh = f->kept_k.back();
+    // loop-order column table
+    std::vector<int32_t> col_of;
+    loop_order_columns(d, Kh, canon, col_of);
+    {
+      // adjoint visiting order: harmonic rows (k, h, l) as the recursion meets them
+      std::vector<int32_t> deg_of(f->H);
+      for (size_t di = 0; di < f->degs.size(); ++di)
+        for (int hh = 0; hh < f->degs[di].nh; ++hh) deg_of[f->degs[di].hoff + hh] = (int32_t)di;
+      f->adj_src_host.clear();
+      f->adj_src_host.reserve(f->r);
+      for (int32_t col : col_of) {
+        if (col < 0) continue;
+        const hdf::DegDev& dg = f->degs[deg_of[col]];
+        const int hh = col - dg.hoff;
+        for (int l = 0; l < dg.s; ++l) f->adj_src_host.push_back(dg.roff + hh * dg.s + l);
+      }
+      f->adj_kinfo_host.assign(Kh + 2, hdf::KInfo{0, 0});
+      for (size_t di = 0; di < f->degs.size(); ++di)
+        f->adj_kinfo_host[f->kept_k[di]] = hdf::KInfo{f->degs[di].s, f->degs[di].qoff};
+    }
+    HIPCHK(f->col_of.ensure(col_of.size() * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(f->col_of.p, col_of.data(), col_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // recurrence coefficients as (A, B) pairs in the storage type
+    hdf::ChainCoeffs cc;
+    hdf::chain_coeffs(d, Kh, cc);
+    const size_t npair = cc.A.size();
+    std::vector<double> pd(2 * npair + 2, 0.0);     // one pad pair: the adjoint reads one ahead
+    for (size_t i = 0; i < npair; ++i) { pd[2 * i] = cc.A[i]; pd[2 * i + 1] = cc.B[i]; }
+    std::vector<int32_t> ql, qo;
+    std::vector<double> qc, qc2;
+    for (size_t di = 0; di < f->kept_k.size(); ++di) {
+      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
+      for (int l = 0; l < df.s; ++l) {
+        ql.push_back(df.L);
+        qo.push_back((int32_t)qc.size());
+        qc.insert(qc.end(), df.E.begin() + (size_t)l * df.L, df.E.begin() + (size_t)(l + 1) * df.L);
+        if (f->cross) {
+          const hdf::DegreeFactor& dy = f->degy[f->kept_k[di]];
+          qc2.insert(qc2.end(), dy.E.begin() + (size_t)l * dy.L, dy.E.begin() + (size_t)(l + 1) * dy.L);
+        }
+      }
+    }
+    auto upload_typed = [&](DevBuf& b, const std::vector<double>& v) -> hipError_t {
+      if (f->prec == HDF_MIXED) {
+        std::vector<float> tmp(v.begin(), v.end());
+        hipError_t e = b.ensure(tmp.size() * 4);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(b.p, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);      // tmp goes out of scope
+      }
+      hipError_t e = b.ensure(v.size() * 8);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return e;
+      return hipStreamSynchronize(s);
+    };
+    HIPCHK(upload_typed(f->chain, pd));
+    HIPCHK(upload_typed(f->q_coef, qc));
+    if (f->cross) HIPCHK(upload_typed(f->q_coef2, qc2));
+    HIPCHK(f->q_len.ensure(ql.size() * 4));
+    HIPCHK(f->q_off.ensure(qo.size() * 4));
+    HIPCHK(hipMemcpyAsync(f->q_len.p, ql.data(), ql.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(f->q_off.p, qo.data(), qo.size() * 4, hipMemcpyHostToDevice, s));
+    // contraction tables
+    HIPCHK(f->degs_dev.ensure(f->degs.size() * sizeof(hdf::DegDev)));
+    HIPCHK(hipMemcpyAsync(f->degs_dev.p, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
+    std::vector<double> lr;
+    lr.reserve(f->r);
+    for (size_t di = 0; di < f->degs.size(); ++di) {
+      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
+      for (int h = 0; h < f->degs[di].nh; ++h)
+        for (int l = 0; l < df.s; ++l) lr.push_back(f->cross ? 1.0 : df.lam[l]);
+    }
+    HIPCHK(f->lam_row.ensure(lr.size() * 8));
+    HIPCHK(hipMemcpyAsync(f->lam_row.p, lr.data(), lr.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
+
+    hdf::BuildTables tb{};
+    tb.col_of = (const int32_t*)f->col_of.p;
+    tb.chain = f->chain.p;
+    tb.q_len = (const int32_t*)f->q_len.p;
+    tb.q_off = (const int32_t*)f->q_off.p;
+    tb.q_coef = f->q_coef.p;
+    tb.K = Kh;
+    tb.S = (int)f->S;
+    f->tables = tb;
+    std::vector<hdf::DegDev> dbk(K + 1);
+    for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
+    for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
+    HIPCHK(f->degs_by_k.ensure(dbk.size() * sizeof(hdf::DegDev)));
+    HIPCHK(hipMemcpyAsync(f->degs_by_k.p, dbk.data(), dbk.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipEventCreate(&f->ev_b0));
+    HIPCHK(hipEventCreate(&f->ev_b1));
+    HIPCHK(hipEventRecord(f->ev_b0, s));
+    HIPCHK(hdf::launch_build(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p,
+                             f->u0, f->u1, tb, prec, f->phi.p, f->ldN, f->q.p, f->ldN, s));
+    if (f->cross) {
+      f->tables2 = tb;
+      f->tables2.q_coef = f->q_coef2.p;
+      HIPCHK(hdf::launch_build(f->x_soa2.p, dtype, f->ldN2, f->N2, d, (const hdf::GeoDev*)f->geo_dev.p,
+                               f->u0, f->u1, f->tables2, prec, f->phi2.p, f->ldN2, f->q2.p, f->ldN2, s));
+    }
+    HIPCHK(hipEventRecord(f->ev_b1, s));
+  }
+  return HDF_OK;
+}
 
 extern "C" {
 
@@ -313,148 +490,195 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
       hdf::compress_degree_refined(k, L, G2.data(), pcs[k], f->cores[k].data(), f->tau, 1e-14, f->deg[k]);
     }
   }
-  // kept degrees, offsets, tables
-  int64_t hoff = 0, qoff = 0, roff = 0;
-  std::map<std::vector<int>, int> canon;
-  for (int k = 0; k <= K; ++k) {
-    const hdf::DegreeFactor& df = f->deg[k];
-    if (df.s == 0) continue;
-    const int64_t nh = hdf::index_count(d, k);
-    hdf::DegDev dd{};
-    dd.hoff = (int32_t)hoff; dd.nh = (int32_t)nh; dd.qoff = (int32_t)qoff; dd.s = df.s; dd.roff = (int32_t)roff;
-    f->degs.push_back(dd);
-    f->kept_k.push_back(k);
-    std::vector<int32_t> tab;
-    hdf::index_set(d, k, tab);
-    for (int64_t h = 0; h < nh; ++h) {
-      std::vector<int> key(1, k);
-      f->index_table.push_back(k);
-      for (int j = 0; j < d - 2; ++j) {
-        key.push_back(tab[(size_t)h * (d - 2) + j]);
-        f->index_table.push_back(tab[(size_t)h * (d - 2) + j]);
-      }
-      canon[key] = (int)(hoff + h);
-    }
-    hoff += nh;
-    qoff += df.s;
-    roff += nh * df.s;
-    f->max_s = std::max(f->max_s, df.s);
+  {
+    const hdf_status st = finish_build(f.get(), t0, s);
+    if (st != HDF_OK) return st;
   }
-  f->H = hoff; f->S = qoff; f->r = roff;
-  f->t_compress = now_ms() - t0;
+  *out = f.release();
+  return HDF_OK;
+}
 
-  // 5. memory budget, then the factor evaluation
-  const size_t fbytes = (size_t)(f->H + f->S) * f->ldN * f->elem();
-  size_t freeb = 0, totb = 0;
-  HIPCHK(hipMemGetInfo(&freeb, &totb));
-  const size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)(0.6 * (double)freeb));
-  if (fbytes > budget) {
-    char buf[200];
-    snprintf(buf, sizeof buf, "factor needs %.3g GB (H=%lld, S=%lld), budget %.3g GB",
-             fbytes / 1e9, (long long)f->H, (long long)f->S, budget / 1e9);
+// ------------------------------------------------------------------ general build
+hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y, int64_t ny, int64_t ldy,
+                           int dtype, int d, hdf_kernel kernel, double lengthscale, double tol,
+                           hdf_precision prec, void* hip_stream, hdf_handle* out) {
+  g_err.clear();
+  if (!out) return fail(HDF_E_ARG, "out is NULL");
+  if (!x || !y) return fail(HDF_E_ARG, "x or y is NULL");
+  if (d < 3 || d > HDF_MAX_DIM) return fail(HDF_E_DIM, "d must be in [3, 8]");
+  if (nx < 1 || ny < 1) return fail(HDF_E_ARG, "nx and ny must be >= 1");
+  if (ldx < d || ldy < d) return fail(HDF_E_ARG, "leading dimensions must be >= d");
+  if (dtype != 0 && dtype != 1) return fail(HDF_E_ARG, "dtype must be 0 (f32) or 1 (f64)");
+  if (prec != HDF_FP64 && prec != HDF_MIXED) return fail(HDF_E_ARG, "unknown precision");
+  if ((prec == HDF_MIXED) != (dtype == 0))
+    return fail(HDF_E_ARG, "HDF_MIXED needs float32 points, HDF_FP64 needs float64 points");
+  if ((int)kernel < 0 || (int)kernel > 3) return fail(HDF_E_ARG, "unknown kernel");
+  if (!(lengthscale > 0) || !std::isfinite(lengthscale)) return fail(HDF_E_ARG, "lengthscale must be > 0");
+  if (!(tol > 0 && tol < 1)) return fail(HDF_E_ARG, "tol must be in (0, 1)");
+  hipStream_t s = (hipStream_t)hip_stream;
+
+  std::unique_ptr<hdf_factor> f(new hdf_factor());
+  f->cross = true;
+  f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
+  f->N = nx; f->N2 = ny; f->l = lengthscale; f->tol = tol;
+  f->ldN = (nx + 63) / 64 * 64 + 64;
+  f->ldN2 = (ny + 63) / 64 * 64 + 64;
+  const size_t in_elem = dtype == 0 ? 4 : 8;
+
+  // 1. geometry of X u Y and the cross-pair norm sample, one sync
+  double t0 = now_ms();
+  HIPCHK(f->x_soa.ensure((size_t)d * f->ldN * in_elem));
+  HIPCHK(f->x_soa2.ensure((size_t)d * f->ldN2 * in_elem));
+  HIPCHK(f->geo_dev.ensure(sizeof(hdf::GeoDev)));
+  HIPCHK(f->part.ensure((size_t)hdf::kPrepBlocks * 64 * sizeof(double)));
+  HIPCHK(hdf::launch_prep_cross(x, nx, ldx, y, ny, ldy, dtype, d, f->x_soa.p, f->ldN, f->x_soa2.p, f->ldN2,
+                                kernel, lengthscale, (double*)f->part.p, (hdf::GeoDev*)f->geo_dev.p, s));
+  HIPCHK(hipMemcpyAsync(&f->geo, f->geo_dev.p, sizeof(hdf::GeoDev), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  f->t_prep = now_ms() - t0;
+  if (f->geo.nonfinite > 0) return fail(HDF_E_NONFINITE, "points contain NaN or Inf");
+
+  // 2. host planner (degree rule as in the symmetric case)
+  t0 = now_ms();
+  f->nu = std::sqrt(f->geo.nu2_sum / (double)hdf::kNuPairs);
+  const double D = 2.0 * f->geo.R;
+  std::vector<double> afull(hdf::kChebNodes);
+  hdf::chebyshev_coeffs(kernel, D, lengthscale, hdf::kChebNodes, false, afull.data());
+  f->p = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, HDF_MAX_DEGREE, &f->tail);
+  if (f->p < 0) {
+    int pp = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, hdf::kChebNodes - 2, nullptr);
+    char buf[160];
+    snprintf(buf, sizeof buf, "Chebyshev degree %d needed (> %d): diameter/lengthscale too large for tol",
+             pp, HDF_MAX_DEGREE);
     return fail(HDF_E_INFEASIBLE, buf);
   }
-  if (f->H > 0) {
-    HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
-    HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
-    // The harmonic recurrences run up to the largest kept degree only:
-    // dropped top degrees would be evaluated and discarded by both the factor
-    // kernel and the adjoint.
-    const int Kh = f->kept_k.back();
-    // loop-order column table
-    std::vector<int32_t> col_of;
-    loop_order_columns(d, Kh, canon, col_of);
-    {
-      // adjoint visiting order: harmonic rows (k, h, l) as the recursion meets them
-      std::vector<int32_t> deg_of(f->H);
-      for (size_t di = 0; di < f->degs.size(); ++di)
-        for (int hh = 0; hh < f->degs[di].nh; ++hh) deg_of[f->degs[di].hoff + hh] = (int32_t)di;
-      f->adj_src_host.clear();
-      f->adj_src_host.reserve(f->r);
-      for (int32_t col : col_of) {
-        if (col < 0) continue;
-        const hdf::DegDev& dg = f->degs[deg_of[col]];
-        const int hh = col - dg.hoff;
-        for (int l = 0; l < dg.s; ++l) f->adj_src_host.push_back(dg.roff + hh * dg.s + l);
-      }
-      f->adj_kinfo_host.assign(Kh + 2, hdf::KInfo{0, 0});
-      for (size_t di = 0; di < f->degs.size(); ++di)
-        f->adj_kinfo_host[f->kept_k[di]] = hdf::KInfo{f->degs[di].s, f->degs[di].qoff};
-    }
-    HIPCHK(f->col_of.ensure(col_of.size() * sizeof(int32_t)));
-    HIPCHK(hipMemcpyAsync(f->col_of.p, col_of.data(), col_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    // recurrence coefficients as (A, B) pairs in the storage type
-    hdf::ChainCoeffs cc;
-    hdf::chain_coeffs(d, Kh, cc);
-    const size_t npair = cc.A.size();
-    std::vector<double> pd(2 * npair + 2, 0.0);     // one pad pair: the adjoint reads one ahead
-    for (size_t i = 0; i < npair; ++i) { pd[2 * i] = cc.A[i]; pd[2 * i + 1] = cc.B[i]; }
-    std::vector<int32_t> ql, qo;
-    std::vector<double> qc;
-    for (size_t di = 0; di < f->kept_k.size(); ++di) {
-      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
-      for (int l = 0; l < df.s; ++l) {
-        ql.push_back(df.L);
-        qo.push_back((int32_t)qc.size());
-        qc.insert(qc.end(), df.E.begin() + (size_t)l * df.L, df.E.begin() + (size_t)(l + 1) * df.L);
-      }
-    }
-    auto upload_typed = [&](DevBuf& b, const std::vector<double>& v) -> hipError_t {
-      if (f->prec == HDF_MIXED) {
-        std::vector<float> tmp(v.begin(), v.end());
-        hipError_t e = b.ensure(tmp.size() * 4);
-        if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(b.p, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return e;
-        return hipStreamSynchronize(s);      // tmp goes out of scope
-      }
-      hipError_t e = b.ensure(v.size() * 8);
-      if (e != hipSuccess) return e;
-      e = hipMemcpyAsync(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s);
-      if (e != hipSuccess) return e;
-      return hipStreamSynchronize(s);
-    };
-    HIPCHK(upload_typed(f->chain, pd));
-    HIPCHK(upload_typed(f->q_coef, qc));
-    HIPCHK(f->q_len.ensure(ql.size() * 4));
-    HIPCHK(f->q_off.ensure(qo.size() * 4));
-    HIPCHK(hipMemcpyAsync(f->q_len.p, ql.data(), ql.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(f->q_off.p, qo.data(), qo.size() * 4, hipMemcpyHostToDevice, s));
-    // contraction tables
-    HIPCHK(f->degs_dev.ensure(f->degs.size() * sizeof(hdf::DegDev)));
-    HIPCHK(hipMemcpyAsync(f->degs_dev.p, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
-    std::vector<double> lr;
-    lr.reserve(f->r);
-    for (size_t di = 0; di < f->degs.size(); ++di) {
-      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
-      for (int h = 0; h < f->degs[di].nh; ++h)
-        for (int l = 0; l < df.s; ++l) lr.push_back(df.lam[l]);
-    }
-    HIPCHK(f->lam_row.ensure(lr.size() * 8));
-    HIPCHK(hipMemcpyAsync(f->lam_row.p, lr.data(), lr.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
+  f->K = f->p / 2;
+  f->a.assign(afull.begin(), afull.begin() + f->p + 1);
+  hdf::radial_interval(f->geo.rho2_min, f->geo.rho2_max, &f->u0, &f->u1);
+  f->t_plan = now_ms() - t0;
 
-    hdf::BuildTables tb{};
-    tb.col_of = (const int32_t*)f->col_of.p;
-    tb.chain = f->chain.p;
-    tb.q_len = (const int32_t*)f->q_len.p;
-    tb.q_off = (const int32_t*)f->q_off.p;
-    tb.q_coef = f->q_coef.p;
-    tb.K = Kh;
-    tb.S = (int)f->S;
-    f->tables = tb;
-    std::vector<hdf::DegDev> dbk(K + 1);
-    for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
-    for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
-    HIPCHK(f->degs_by_k.ensure(dbk.size() * sizeof(hdf::DegDev)));
-    HIPCHK(hipMemcpyAsync(f->degs_by_k.p, dbk.data(), dbk.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
+  // 3. radial Gram moments of both sets, one sync; cores and tau meanwhile
+  t0 = now_ms();
+  const int K = f->K;
+  const int nrt = (K + 1 + 15) / 16, nct = (2 * K + 1 + 15) / 16;
+  const int gram_mode = (prec == HDF_FP64) ? 0 : 2;
+  const int gb = std::max(hdf::gram_blocks(nx), hdf::gram_blocks(ny));
+  const size_t mom_n = (size_t)nrt * 16 * nct * 16;
+  HIPCHK(f->part.ensure(std::max((size_t)gb * mom_n * sizeof(double) + 4096,
+                                 (size_t)hdf::kPrepBlocks * 64 * sizeof(double))));
+  HIPCHK(f->moments.ensure(2 * mom_n * sizeof(double)));
+  HIPCHK(hdf::launch_gram(f->x_soa.p, dtype, f->ldN, nx, d, (const hdf::GeoDev*)f->geo_dev.p, f->u0, f->u1,
+                          K, gram_mode, (double*)f->part.p, (double*)f->moments.p, s));
+  HIPCHK(hdf::launch_gram(f->x_soa2.p, dtype, f->ldN2, ny, d, (const hdf::GeoDev*)f->geo_dev.p, f->u0, f->u1,
+                          K, gram_mode, (double*)f->part.p, (double*)f->moments.p + mom_n, s));
+  const int mcols = nct * 16;
+  std::vector<double> mom(2 * mom_n);
+  HIPCHK(hipMemcpyAsync(mom.data(), f->moments.p, mom.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  const double t_overlap = now_ms();
+  hdf::radial_cores(f->a.data(), f->p, d, f->u0, f->u1, f->cores);
+  f->tau = hdf::tau_threshold(tol, f->nu, std::sqrt((double)nx * (double)ny), d, f->p);
+  const double t_cores = now_ms() - t_overlap;
+  HIPCHK(hipStreamSynchronize(s));
+  f->t_plan += t_cores;
+  f->t_gram = now_ms() - t0 - t_cores;
+
+  // 4. compression per degree (SVD of R_x M R_y^T); a degree whose first-pass
+  // Gram error on either side exceeds the target is refined by a second,
+  // binary64 Gram pass of both sets
+  t0 = now_ms();
+  const double eta1 = (gram_mode == 0) ? 1e-16 : 1e-9;
+  const double target = (prec == HDF_FP64) ? 1e-14 : 1e-3 * tol;
+  const double floor_rel = (gram_mode == 0) ? 1e-15 : 1e-10;
+  f->deg.resize(K + 1);
+  f->degy.resize(K + 1);
+  std::vector<hdf::DegreeFactorCross> dc(K + 1);
+  std::vector<hdf::Precond> pcx(K + 1), pcy(K + 1);
+  std::vector<double> t1x, t1y;
+  std::vector<int32_t> t1_off(K + 1, 0);
+  std::vector<int> refine;
+  auto gram_of = [&](const double* mm, int k, int L, std::vector<double>& G) {
+    G.assign((size_t)L * L, 0.0);
+    for (int aa = 0; aa < L; ++aa)
+      for (int bb = 0; bb < L; ++bb)
+        G[(size_t)aa * L + bb] = 0.5 * (mm[(size_t)k * mcols + aa + bb] + mm[(size_t)k * mcols + std::abs(aa - bb)]);
+  };
+  auto cond_of = [](const hdf::Precond& pc) {
+    double gmax = 0.0, gmin = INFINITY;
+    for (double v : pc.lam1c) { gmax = std::max(gmax, v); gmin = std::min(gmin, v); }
+    return gmax / gmin;
+  };
+  for (int k = 0; k <= K; ++k) {
+    const int L = K - k + 1;
+    std::vector<double> Gx, Gy;
+    gram_of(mom.data(), k, L, Gx);
+    gram_of(mom.data() + mom_n, k, L, Gy);
+    hdf::gram_precondition(L, Gx.data(), floor_rel, pcx[k]);
+    hdf::gram_precondition(L, Gy.data(), floor_rel, pcy[k]);
+    hdf::SqrtFactor fx, fy;
+    hdf::sqrt_factor_single(L, Gx.data(), floor_rel, fx);
+    hdf::sqrt_factor_single(L, Gy.data(), floor_rel, fy);
+    hdf::compress_degree_cross(k, L, fx, fy, f->cores[k].data(), f->tau, dc[k]);
+    double smax = 0.0;
+    for (double v : dc[k].sig) smax = std::max(smax, v);
+    const double est = eta1 * std::max(cond_of(pcx[k]), cond_of(pcy[k])) * (smax > 0 ? f->tau / smax : 1.0);
+    if (est > target) refine.push_back(k);
+    t1_off[k] = (int32_t)t1x.size();
+    t1x.insert(t1x.end(), pcx[k].T1.begin(), pcx[k].T1.end());
+    t1y.insert(t1y.end(), pcy[k].T1.begin(), pcy[k].T1.end());
+  }
+  f->n_refined = (int)refine.size();
+  if (!refine.empty()) {
+    DevBuf t1dx, t1dy, t1o, g2, g2part, selk;
+    const int nsel = (int)refine.size();
+    const int gb2 = std::max(hdf::gram2_blocks(nx, nsel), hdf::gram2_blocks(ny, nsel));
+    HIPCHK(t1dx.ensure(t1x.size() * 8));
+    HIPCHK(t1dy.ensure(t1y.size() * 8));
+    HIPCHK(t1o.ensure(t1_off.size() * 4));
+    HIPCHK(selk.ensure(refine.size() * 4));
+    HIPCHK(g2.ensure(2 * refine.size() * 1024 * 8));
+    HIPCHK(g2part.ensure((size_t)gb2 * refine.size() * 1024 * 8));
+    std::vector<int32_t> sel(refine.begin(), refine.end());
+    HIPCHK(hipMemcpyAsync(t1dx.p, t1x.data(), t1x.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(t1dy.p, t1y.data(), t1y.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(t1o.p, t1_off.data(), t1_off.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(selk.p, sel.data(), sel.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hdf::launch_gram2(f->x_soa.p, dtype, f->ldN, nx, d, (const hdf::GeoDev*)f->geo_dev.p, f->u0, f->u1,
+                             K, (const double*)t1dx.p, (const int32_t*)t1o.p, (const int32_t*)selk.p, nsel,
+                             (double*)g2part.p, (double*)g2.p, s));
+    HIPCHK(hdf::launch_gram2(f->x_soa2.p, dtype, f->ldN2, ny, d, (const hdf::GeoDev*)f->geo_dev.p, f->u0,
+                             f->u1, K, (const double*)t1dy.p, (const int32_t*)t1o.p, (const int32_t*)selk.p,
+                             nsel, (double*)g2part.p, (double*)g2.p + refine.size() * 1024, s));
+    std::vector<double> g2h(2 * refine.size() * 1024);
+    HIPCHK(hipMemcpyAsync(g2h.data(), g2.p, g2h.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipEventCreate(&f->ev_b0));
-    HIPCHK(hipEventCreate(&f->ev_b1));
-    HIPCHK(hipEventRecord(f->ev_b0, s));
-    HIPCHK(hdf::launch_build(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p,
-                             f->u0, f->u1, tb, prec, f->phi.p, f->ldN, f->q.p, f->ldN, s));
-    HIPCHK(hipEventRecord(f->ev_b1, s));
+    for (size_t ri = 0; ri < refine.size(); ++ri) {
+      const int k = refine[ri];
+      const int L = K - k + 1;
+      std::vector<double> G2x((size_t)L * L), G2y((size_t)L * L);
+      for (int aa = 0; aa < L; ++aa)
+        for (int bb = 0; bb < L; ++bb) {
+          G2x[(size_t)aa * L + bb] = g2h[ri * 1024 + aa * 32 + bb];
+          G2y[(size_t)aa * L + bb] = g2h[(refine.size() + ri) * 1024 + aa * 32 + bb];
+        }
+      hdf::SqrtFactor fx, fy;
+      hdf::sqrt_factor_refined(L, G2x.data(), pcx[k], 1e-14, fx);
+      hdf::sqrt_factor_refined(L, G2y.data(), pcy[k], 1e-14, fy);
+      hdf::compress_degree_cross(k, L, fx, fy, f->cores[k].data(), f->tau, dc[k]);
+    }
+  }
+  for (int k = 0; k <= K; ++k) {
+    hdf::DegreeFactor& dx = f->deg[k];
+    hdf::DegreeFactor& dy = f->degy[k];
+    dx.k = dy.k = k;
+    dx.L = dy.L = K - k + 1;
+    dx.s = dy.s = dc[k].s;
+    dx.lam = dy.lam = dc[k].sig;
+    dx.E = dc[k].Ex;
+    dy.E = dc[k].Ey;
+  }
+  {
+    const hdf_status st = finish_build(f.get(), t0, s);
+    if (st != HDF_OK) return st;
   }
   *out = f.release();
   return HDF_OK;
@@ -462,9 +686,13 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
 
 // ------------------------------------------------------------------ matvec
 // Pass 1 (W = U^T V, binary64) and the scaled copy Wd = D W for pass 2.
-static hdf_status pass1(hdf_handle h, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
+// side 0: the factor's (X) rows; side 1: the Y rows of a general factor.
+static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
                         DevBuf& Wd, hipStream_t s, bool timed) {
-  const int64_t n = h->N;
+  const int64_t n = side ? h->N2 : h->N;
+  const void* phi = side ? h->phi2.p : h->phi.p;
+  const void* qv = side ? h->q2.p : h->q.p;
+  const int64_t ldn = side ? h->ldN2 : h->ldN;
   const size_t el = h->elem();
   const int cpl = m16 / 16;
   const int max_nct = h->max_s * cpl;
@@ -531,7 +759,7 @@ static hdf_status pass1(hdf_handle h, const void* V, int64_t m, int64_t ldv, int
           for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
         HIPCHK(hipEventRecord(h->ev_mv[0], s));
       }
-      HIPCHK(hdf::launch_matvec_t_lds(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+      HIPCHK(hdf::launch_matvec_t_lds(phi, ldn, qv, ldn, (const hdf::DegDev*)h->degs_dev.p,
                                       (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
                                       (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, V, ldv, n,
                                       (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
@@ -559,7 +787,7 @@ static hdf_status pass1(hdf_handle h, const void* V, int64_t m, int64_t ldv, int
       for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(h->ev_mv[0], s));
   }
-  HIPCHK(hdf::launch_matvec_t(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+  HIPCHK(hdf::launch_matvec_t(phi, ldn, qv, ldn, (const hdf::DegDev*)h->degs_dev.p,
                               (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, max_nct, V, ldv, n,
                               (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
                               h->prec, s));
@@ -579,7 +807,7 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
     return HDF_OK;
   }
   const int m16 = (int)((m + 15) / 16 * 16);
-  hdf_status st = pass1(h, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
+  hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
   if (st != HDF_OK) return st;
   HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
                               (int)h->degs.size(), h->max_s, h->ws_Wd.p, m16, KV, ldkv, n, (int)m,
@@ -598,7 +826,7 @@ hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv, void*
   if (ldv < m || ldkv < m) return fail(HDF_E_ARG, "leading dimensions must be >= m");
   const size_t el = h->elem();
   const char* v0 = (const char*)V;
-  const char* v1 = v0 + ((h->N - 1) * ldv + m) * el;
+  const char* v1 = v0 + (((h->cross ? h->N2 : h->N) - 1) * ldv + m) * el;
   const char* k0 = (const char*)KV;
   const char* k1 = k0 + ((h->N - 1) * ldkv + m) * el;
   if (v0 < k1 && k0 < v1) return fail(HDF_E_ARG, "V and KV overlap");
@@ -613,6 +841,7 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
   if (m < 1 || m > HDF_MAX_RHS) return fail(HDF_E_ARG, "m must be in [1, 256]");
   if (ld < m) return fail(HDF_E_ARG, "ld must be >= m");
   if (dX && lddx < h->d) return fail(HDF_E_ARG, "lddx must be >= d");
+  if (h->cross) return fail(HDF_E_ARG, "hdf_backward needs a symmetric factor (hdf_build)");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t el = h->elem();
   if (!dlength && !dX) return HDF_OK;
@@ -635,7 +864,7 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
     HIPCHK(hipMemcpy2DAsync(h->bw_VW.p, m2 * el, Vm, ld * el, m * el, h->N, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpy2DAsync((char*)h->bw_VW.p + m * el, m2 * el, Wm, ld * el, m * el, h->N,
                             hipMemcpyDeviceToDevice, s));
-    hdf_status st = pass1(h, h->bw_VW.p, m2, m2, m16, h->bw_GV, h->bw_GVd, s, false);
+    hdf_status st = pass1(h, 0, h->bw_VW.p, m2, m2, m16, h->bw_GV, h->bw_GVd, s, false);
     if (st != HDF_OK) return st;
     Gv_d = h->bw_GVd.p;
     Gw_d = (const char*)h->bw_GVd.p + m * el;
@@ -643,9 +872,9 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
     gw_col = m;
   } else {
     m16 = (int)((m + 15) / 16 * 16);
-    hdf_status st = pass1(h, Vm, m, ld, m16, h->bw_GV, h->bw_GVd, s, false);
+    hdf_status st = pass1(h, 0, Vm, m, ld, m16, h->bw_GV, h->bw_GVd, s, false);
     if (st != HDF_OK) return st;
-    st = pass1(h, Wm, m, ld, m16, h->bw_GW, h->bw_GWd, s, false);
+    st = pass1(h, 0, Wm, m, ld, m16, h->bw_GW, h->bw_GWd, s, false);
     if (st != HDF_OK) return st;
     Gv_d = h->bw_GVd.p;
     Gw_d = h->bw_GWd.p;
@@ -758,6 +987,7 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   info->n_dim = h->d;
   info->precision = h->prec;
   info->n_points = h->N;
+  info->n_points_y = h->cross ? h->N2 : 0;
   info->degree_p = h->p;
   info->n_degrees = h->K + 1;
   info->n_harmonics = h->H;
@@ -769,7 +999,7 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   info->center_radius = h->geo.R;
   info->rho2_min = h->u0;
   info->rho2_max = h->u1;
-  info->factor_bytes = (int64_t)((h->H + h->S) * h->ldN * h->elem());
+  info->factor_bytes = (int64_t)((h->H + h->S) * (h->ldN + (h->cross ? h->ldN2 : 0)) * h->elem());
   info->t_prep_ms = h->t_prep;
   info->t_plan_ms = h->t_plan;
   info->t_gram_ms = h->t_gram;
@@ -833,7 +1063,41 @@ hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_
   return HDF_OK;
 }
 
+hdf_status hdf_copy_factor_y(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_out, int64_t ld_q,
+                             void* hip_stream) {
+  g_err.clear();
+  if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  if (!h->cross) return fail(HDF_E_ARG, "the handle is a symmetric factor (no Y side)");
+  if ((phi_out && ld_phi < h->N2) || (q_out && ld_q < h->N2)) return fail(HDF_E_ARG, "leading dimension < n_y");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t el = h->elem();
+  if (phi_out && h->H > 0)
+    HIPCHK(hipMemcpy2DAsync(phi_out, ld_phi * el, h->phi2.p, h->ldN2 * el, h->N2 * el, h->H,
+                            hipMemcpyDeviceToDevice, s));
+  if (q_out && h->S > 0)
+    HIPCHK(hipMemcpy2DAsync(q_out, ld_q * el, h->q2.p, h->ldN2 * el, h->N2 * el, h->S,
+                            hipMemcpyDeviceToDevice, s));
+  return HDF_OK;
+}
+
 // ------------------------------------------------------------------ host planner
+hdf_status hdf_plan_compress_cross(int L, const double* Gx, const double* Gy, const double* M, double tau,
+                                   double null_rel, int32_t* s, double* sig, double* Ex, double* Ey) {
+  g_err.clear();
+  if (!Gx || !Gy || !M || !s) return fail(HDF_E_ARG, "NULL argument");
+  if (L < 1 || L > 32) return fail(HDF_E_ARG, "L must be in [1, 32]");
+  hdf::SqrtFactor fx, fy;
+  hdf::sqrt_factor_single(L, Gx, null_rel, fx);
+  hdf::sqrt_factor_single(L, Gy, null_rel, fy);
+  hdf::DegreeFactorCross out;
+  hdf::compress_degree_cross(0, L, fx, fy, M, tau, out);
+  *s = out.s;
+  if (sig) std::copy(out.sig.begin(), out.sig.end(), sig);
+  if (Ex) std::copy(out.Ex.begin(), out.Ex.end(), Ex);
+  if (Ey) std::copy(out.Ey.begin(), out.Ey.end(), Ey);
+  return HDF_OK;
+}
+
 hdf_status hdf_plan_chebyshev(hdf_kernel kernel, double D, double lengthscale, int n_nodes,
                               int derivative, double* a) {
   g_err.clear();

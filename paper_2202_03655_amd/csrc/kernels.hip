@@ -250,6 +250,71 @@ hipError_t launch_prep(const void* pts, int dtype, int64_t n, int d, int64_t ld,
   return hipGetLastError();
 }
 
+// Geometry of two point sets (general case X != Y): the existing passes run
+// over both sets into adjacent halves of the partial records, so the centre,
+// radius and rho^2 interval are those of X u Y.  nu is then replaced by the
+// cross-pair estimate: pair t draws generator outputs 2t+1 and 2t+2, a < nx,
+// b < ny (the per-set estimates of the min/max pass are discarded).
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_nu_cross(const Tin* __restrict__ px, int64_t nx, int64_t ldx,
+                                                   const Tin* __restrict__ py, int64_t ny, int64_t ldy,
+                                                   int d, int kind, double l, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double nu = 0.0;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  {
+#pragma clang fp contract(off)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < kNuPairs; t += gsz) {
+      const uint64_t ia = (splitmix_at(kNuSeed, 2 * (uint64_t)t + 1) >> 11) % (uint64_t)nx;
+      const uint64_t ib = (splitmix_at(kNuSeed, 2 * (uint64_t)t + 2) >> 11) % (uint64_t)ny;
+      double s = 0.0;
+      for (int j = 0; j < d; ++j) {
+        const double df = (double)px[(int64_t)ia * ldx + j] - (double)py[(int64_t)ib * ldy + j];
+        s = s + df * df;
+      }
+      const double kv = kernel_value_dev(kind, sqrt(s), l);
+      nu = nu + kv * kv;
+    }
+  }
+  const double r = block_reduce(nu, sh, OpAdd());
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) k_nu_fin(const double* __restrict__ part, int nblk, GeoDev* geo) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) v += part[b];
+  const double r = block_reduce(v, sh, OpAdd());
+  if (threadIdx.x == 0) geo->nu2_sum = r;
+}
+
+hipError_t launch_prep_cross(const void* ptsx, int64_t nx, int64_t ldx, const void* ptsy, int64_t ny,
+                             int64_t ldy, int dtype, int d, void* soax, int64_t ldsx, void* soay,
+                             int64_t ldsy, int kernel, double l, double* partials, GeoDev* geo,
+                             hipStream_t s) {
+  const int nb = kPrepBlocks;
+  double* p1 = partials + (int64_t)nb * kPrepRec;
+#define PREP_CROSS(T)                                                                                   \
+  k_prep_minmax<T><<<nb, 256, 0, s>>>((const T*)ptsx, nx, d, ldx, (T*)soax, ldsx, kernel, l, partials); \
+  k_prep_minmax<T><<<nb, 256, 0, s>>>((const T*)ptsy, ny, d, ldy, (T*)soay, ldsy, kernel, l, p1);       \
+  k_prep_fin1<<<1, 256, 0, s>>>(partials, 2 * nb, geo);                                                 \
+  k_prep_radius<T><<<nb, 256, 0, s>>>((const T*)soax, ldsx, nx, d, geo, partials);                      \
+  k_prep_radius<T><<<nb, 256, 0, s>>>((const T*)soay, ldsy, ny, d, geo, partials + nb);                 \
+  k_prep_fin2<<<1, 256, 0, s>>>(partials, 2 * nb, geo);                                                 \
+  k_prep_rho<T><<<nb, 256, 0, s>>>((const T*)soax, ldsx, nx, d, geo, partials);                         \
+  k_prep_rho<T><<<nb, 256, 0, s>>>((const T*)soay, ldsy, ny, d, geo, partials + 2 * nb);                \
+  k_prep_fin3<<<1, 256, 0, s>>>(partials, 2 * nb, geo);                                                 \
+  k_nu_cross<T><<<nb, 256, 0, s>>>((const T*)ptsx, nx, ldx, (const T*)ptsy, ny, ldy, d, kernel, l, partials); \
+  k_nu_fin<<<1, 256, 0, s>>>(partials, nb, geo);
+  if (dtype == 0) {
+    PREP_CROSS(float)
+  } else {
+    PREP_CROSS(double)
+  }
+#undef PREP_CROSS
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Gram
 // Moments mu[k][c] = sum_i rho_i^{2k} T_c(t_i) as a tall-skinny product
 // A^T B on MFMA (A[i][k] = rho_i^{2k}, B[i][c] = T_c(t_i)).  The per-degree

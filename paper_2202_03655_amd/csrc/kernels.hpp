@@ -24,6 +24,13 @@ hipError_t launch_prep(const void* pts, int dtype, int64_t n, int d, int64_t ld,
                        int64_t ldx, int kernel, double l, double* partials, GeoDev* geo,
                        hipStream_t s);
 
+// Geometry of two sets (X u Y) with the cross-pair ||K(X, Y)||_F sample.
+// partials: at least 2 * kPrepBlocks * 18 doubles.
+hipError_t launch_prep_cross(const void* ptsx, int64_t nx, int64_t ldx, const void* ptsy, int64_t ny,
+                             int64_t ldy, int dtype, int d, void* soax, int64_t ldsx, void* soay,
+                             int64_t ldsy, int kernel, double l, double* partials, GeoDev* geo,
+                             hipStream_t s);
+
 // Weighted Chebyshev moments mu[k][c] = sum_i rho_i^{2k} T_c(t_i), k <= K,
 // c <= 2K, written to `moments` (rows 16*nrt x cols 16*nct, binary64).
 // mode 0: binary64 MFMA; 1: binary32 MFMA; 2: binary32 hi/lo split MFMA.

@@ -350,12 +350,12 @@ double sphere_area(int d) {
   return (double)(2 * powl(kPiL, (ld)d / 2) / tgammal((ld)d / 2));
 }
 
-double tau_threshold(double tol, double nu, int64_t N, int d, int p) {
+double tau_threshold(double tol, double nu, double N, int d, int p) {
   const int K = p / 2;
   const double area = sphere_area(d);
   double denom = 0.0;
   for (int k = 0; k <= K; ++k) denom += (double)index_count(d, k) / area * std::sqrt((double)(K - k + 1));
-  return (tol * nu * (double)N / 2.0) / denom;
+  return (tol * nu * N / 2.0) / denom;
 }
 
 void chain_coeffs(int d, int K, ChainCoeffs& out) {
@@ -500,6 +500,165 @@ void compress_degree(int k, int L, const double* G, const double* M, double tau,
     out.lam.push_back(mu[i]);
     out.E.insert(out.E.end(), e.begin(), e.end());
     out.Ep.insert(out.Ep.end(), ep.begin(), ep.end());
+    out.s++;
+  }
+}
+
+// ------------------------------------------------------------ SVD
+// One-sided Jacobi (Hestenes): plane rotations orthogonalise the columns of
+// A (m x n, row-major), accumulated in V (n x n); the singular values are the
+// final column norms and U holds the normalised columns (zero where the norm
+// is zero).  Works on the matrix itself, not on A^T A, so small singular
+// values keep their relative accuracy.
+void jacobi_svd(int m, int n, const double* A, double* U, double* S, double* V) {
+  std::vector<double> W(A, A + (size_t)m * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double worst = 0.0;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double alpha = 0.0, beta = 0.0, gamma = 0.0;
+        for (int i = 0; i < m; ++i) {
+          const double wp = W[(size_t)i * n + p], wq = W[(size_t)i * n + q];
+          alpha += wp * wp;
+          beta += wq * wq;
+          gamma += wp * wq;
+        }
+        if (gamma == 0.0) continue;
+        const double rel = std::fabs(gamma) / std::sqrt(alpha * beta);
+        worst = std::max(worst, rel);
+        if (rel <= 1e-15) continue;
+        const double zeta = (beta - alpha) / (2.0 * gamma);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < m; ++i) {
+          const double wp = W[(size_t)i * n + p], wq = W[(size_t)i * n + q];
+          W[(size_t)i * n + p] = c * wp - sn * wq;
+          W[(size_t)i * n + q] = sn * wp + c * wq;
+        }
+        for (int i = 0; i < n; ++i) {
+          const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
+          V[(size_t)i * n + p] = c * vp - sn * vq;
+          V[(size_t)i * n + q] = sn * vp + c * vq;
+        }
+      }
+    if (worst <= 1e-15) break;
+  }
+  for (int j = 0; j < n; ++j) {
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm += W[(size_t)i * n + j] * W[(size_t)i * n + j];
+    nrm = std::sqrt(nrm);
+    S[j] = nrm;
+    for (int i = 0; i < m; ++i) U[(size_t)i * n + j] = nrm > 0.0 ? W[(size_t)i * n + j] / nrm : 0.0;
+  }
+}
+
+void sqrt_factor_single(int L, const double* G, double null_rel, SqrtFactor& f) {
+  f.L = L;
+  f.r = 0;
+  f.R.clear();
+  f.T.clear();
+  std::vector<double> Gc(G, G + (size_t)L * L), w(L), Vg((size_t)L * L);
+  jacobi_eigh(L, Gc.data(), w.data(), Vg.data());
+  double gmax = 0.0;
+  for (int i = 0; i < L; ++i) gmax = std::max(gmax, w[i]);
+  if (!(gmax > 0.0)) return;
+  std::vector<int> kept;
+  for (int i = 0; i < L; ++i)
+    if (w[i] > null_rel * gmax) kept.push_back(i);
+  f.r = (int)kept.size();
+  f.R.assign((size_t)f.r * L, 0.0);
+  f.T.assign((size_t)L * f.r, 0.0);
+  for (int i = 0; i < f.r; ++i) {
+    const double sw = std::sqrt(w[kept[i]]);
+    for (int a = 0; a < L; ++a) {
+      f.R[(size_t)i * L + a] = sw * Vg[(size_t)a * L + kept[i]];
+      f.T[(size_t)a * f.r + i] = Vg[(size_t)a * L + kept[i]] / sw;
+    }
+  }
+}
+
+void sqrt_factor_refined(int L, const double* G2, const Precond& pc, double null_rel, SqrtFactor& f) {
+  f.L = L;
+  f.r = 0;
+  f.R.clear();
+  f.T.clear();
+  std::vector<double> Gc(G2, G2 + (size_t)L * L), w2(L), V2((size_t)L * L);
+  jacobi_eigh(L, Gc.data(), w2.data(), V2.data());
+  double gmax = 0.0;
+  for (int i = 0; i < L; ++i) gmax = std::max(gmax, w2[i]);
+  if (!(gmax > 0.0)) return;
+  std::vector<int> kept;
+  for (int i = 0; i < L; ++i)
+    if (w2[i] > null_rel * gmax) kept.push_back(i);
+  f.r = (int)kept.size();
+  f.R.assign((size_t)f.r * L, 0.0);
+  f.T.assign((size_t)L * f.r, 0.0);
+  for (int i = 0; i < f.r; ++i) {
+    const int ki = kept[i];
+    const double s2 = std::sqrt(w2[ki]);
+    for (int a = 0; a < L; ++a) {
+      double acc = 0.0, acc2 = 0.0;
+      for (int j = 0; j < L; ++j) {
+        acc += V2[(size_t)j * L + ki] * std::sqrt(pc.lam1c[j]) * pc.V1[(size_t)a * L + j];
+        acc2 += pc.V1[(size_t)a * L + j] / std::sqrt(pc.lam1c[j]) * V2[(size_t)j * L + ki];
+      }
+      f.R[(size_t)i * L + a] = s2 * acc;
+      f.T[(size_t)a * f.r + i] = acc2 / s2;
+    }
+  }
+}
+
+void compress_degree_cross(int k, int L, const SqrtFactor& fx, const SqrtFactor& fy, const double* M,
+                           double tau, DegreeFactorCross& out) {
+  out.k = k;
+  out.L = L;
+  out.s = 0;
+  out.sig.clear();
+  out.Ex.clear();
+  out.Ey.clear();
+  const int rx = fx.r, ry = fy.r;
+  if (rx == 0 || ry == 0) return;
+  // A = R_x M R_y^T (rx x ry)
+  std::vector<double> RM((size_t)rx * L, 0.0), A((size_t)rx * ry, 0.0);
+  for (int i = 0; i < rx; ++i)
+    for (int b = 0; b < L; ++b) {
+      double acc = 0.0;
+      for (int a = 0; a < L; ++a) acc += fx.R[(size_t)i * L + a] * M[(size_t)a * L + b];
+      RM[(size_t)i * L + b] = acc;
+    }
+  for (int i = 0; i < rx; ++i)
+    for (int j = 0; j < ry; ++j) {
+      double acc = 0.0;
+      for (int b = 0; b < L; ++b) acc += RM[(size_t)i * L + b] * fy.R[(size_t)j * L + b];
+      A[(size_t)i * ry + j] = acc;
+    }
+  std::vector<double> U((size_t)rx * ry), S(ry), V((size_t)ry * ry);
+  jacobi_svd(rx, ry, A.data(), U.data(), S.data(), V.data());
+  std::vector<int> ord(ry);
+  for (int i = 0; i < ry; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return S[x] > S[y]; });
+  for (int c = 0; c < ry; ++c) {
+    const int j = ord[c];
+    if (!(S[j] > tau)) break;
+    const double rs = std::sqrt(S[j]);
+    std::vector<double> ex(L, 0.0), ey(L, 0.0);
+    for (int a = 0; a < L; ++a) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int i = 0; i < rx; ++i) s1 += fx.T[(size_t)a * rx + i] * U[(size_t)i * ry + j];
+      for (int i = 0; i < ry; ++i) s2 += fy.T[(size_t)a * ry + i] * V[(size_t)i * ry + j];
+      ex[a] = s1 * rs;
+      ey[a] = s2 * rs;
+    }
+    int piv = 0;
+    for (int a = 1; a < L; ++a)
+      if (std::fabs(ex[a]) > std::fabs(ex[piv])) piv = a;
+    if (ex[piv] < 0)
+      for (int a = 0; a < L; ++a) { ex[a] = -ex[a]; ey[a] = -ey[a]; }
+    out.sig.push_back(S[j]);
+    out.Ex.insert(out.Ex.end(), ex.begin(), ex.end());
+    out.Ey.insert(out.Ey.end(), ey.begin(), ey.end());
     out.s++;
   }
 }

@@ -63,8 +63,32 @@ void gram_precondition(int L, const double* G1, double floor_rel, Precond& pc);
 void compress_degree_refined(int k, int L, const double* G2, const Precond& pc, const double* M,
                              double tau, double null_rel, DegreeFactor& out);
 
-// The kernel-matrix threshold tau of the Frobenius-form error budget.
-double tau_threshold(double tol, double nu, int64_t N, int d, int p);
+// General case X != Y (Algorithm 1): square-root factors of the two radial
+// Grams, Y = Q R with Q orthonormal, R (r x L) and T (L x r) with R T = I
+// (row-major); from the single-pass Gram or the refined pair (G2, pc).
+struct SqrtFactor {
+  int L = 0, r = 0;
+  std::vector<double> R, T;
+};
+void sqrt_factor_single(int L, const double* G, double null_rel, SqrtFactor& f);
+void sqrt_factor_refined(int L, const double* G2, const Precond& pc, double null_rel, SqrtFactor& f);
+// One-sided Jacobi SVD of A (m x n, row-major): A = U diag(S) V^T, U m x n,
+// V n x n (row-major), S unsorted.
+void jacobi_svd(int m, int n, const double* A, double* U, double* S, double* V);
+// Per-degree compression of the cross radial core: SVD of R_x M R_y^T, the
+// singular values above tau kept in descending order; radial coefficients
+// Ex = T_x U sqrt(S), Ey = T_y V sqrt(S) (L x s, column-major by l), signed so
+// that the largest-magnitude entry of each Ex column is positive.
+struct DegreeFactorCross {
+  int k = 0, L = 0, s = 0;
+  std::vector<double> sig, Ex, Ey;
+};
+void compress_degree_cross(int k, int L, const SqrtFactor& fx, const SqrtFactor& fy, const double* M,
+                           double tau, DegreeFactorCross& out);
+
+// The kernel-matrix threshold tau of the Frobenius-form error budget; N is
+// the side of the kernel matrix (sqrt(N_x N_y) for a rectangular one).
+double tau_threshold(double tol, double nu, double N, int d, int p);
 
 // Normalised Gegenbauer chain recurrences of the solid harmonics.
 //   level j = 1..d-2 (coordinate x_j, partial radius r_j^2), lower index b:

@@ -19,14 +19,16 @@ HDF_MAX_DEGREE = 60
 STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
           -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP"}
 
-EXPORTS = ["hdf_build", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
-           "hdf_copy_factor", "hdf_free", "hdf_status_string", "hdf_last_error",
-           "hdf_plan_chebyshev", "hdf_plan_degree", "hdf_plan_cores", "hdf_plan_index_set"]
+EXPORTS = ["hdf_build", "hdf_build_cross", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
+           "hdf_copy_factor", "hdf_copy_factor_y", "hdf_free", "hdf_status_string", "hdf_last_error",
+           "hdf_plan_chebyshev", "hdf_plan_degree", "hdf_plan_cores", "hdf_plan_index_set",
+           "hdf_plan_compress_cross"]
 
 
 class HDFInfo(ctypes.Structure):
     _fields_ = [
         ("n_dim", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_points", ctypes.c_int64),
+        ("n_points_y", ctypes.c_int64),
         ("degree_p", ctypes.c_int32), ("n_degrees", ctypes.c_int32),
         ("n_harmonics", ctypes.c_int64), ("n_radial", ctypes.c_int64), ("rank", ctypes.c_int64),
         ("tau", ctypes.c_double), ("nu", ctypes.c_double), ("cheb_tail", ctypes.c_double),
@@ -60,6 +62,10 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.hdf_build.argtypes = [vp, i32, i64, i32, i64, i32, dbl, dbl, i32, vp, ctypes.POINTER(vp)]
+    L.hdf_build_cross.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, dbl, dbl, i32, vp,
+                                  ctypes.POINTER(vp)]
+    L.hdf_copy_factor_y.argtypes = [vp, vp, i64, vp, i64, vp]
+    L.hdf_plan_compress_cross.argtypes = [i32, vp, vp, vp, dbl, dbl, ctypes.POINTER(ctypes.c_int32), vp, vp, vp]
     L.hdf_matvec.argtypes = [vp, vp, i64, i64, vp, i64, vp]
     L.hdf_backward.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl), vp, i64, vp]
     L.hdf_info.argtypes = [vp, ctypes.POINTER(HDFInfo)]
@@ -194,6 +200,62 @@ class Factor:
         return phi, q
 
 
+class CrossFactor(Factor):
+    """Handle of a general factor K(X, Y) ~ U V^T (hdf_build_cross).
+
+    matvec(W) applies K(X, Y) to W (n_y rows) and returns n_x rows; backward
+    is not defined for it."""
+
+    def __init__(self, X, Y, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None):
+        L = lib()
+        if precision is None:
+            precision = HDF_FP64 if X.dtype == torch.float64 else HDF_MIXED
+        dtype = torch.float64 if precision == HDF_FP64 else torch.float32
+        X = _dev2d(X, dtype, "X")
+        Y = _dev2d(Y, dtype, "Y")
+        if X.shape[1] != Y.shape[1]:
+            raise ValueError("X and Y must have the same number of columns")
+        self.n, self.d = X.shape
+        self.n_y = Y.shape[0]
+        self.dtype = dtype
+        self.precision = precision
+        self.kernel = kernel
+        self.lengthscale = float(lengthscale)
+        self.tol = float(tol)
+        self.device = X.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(X.device):
+            _check(L.hdf_build_cross(X.data_ptr(), self.n, X.stride(0), Y.data_ptr(), self.n_y, Y.stride(0),
+                                     0 if dtype == torch.float32 else 1, self.d, KERNELS[kernel],
+                                     self.lengthscale, self.tol, precision, _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def matvec(self, W, out=None):
+        """K(X, Y) W for W of shape (n_y,) or (n_y, m)."""
+        squeeze = W.dim() == 1
+        W2 = _dev2d(W, self.dtype, "W")
+        if W2.shape[0] != self.n_y:
+            raise ValueError("W must have n_y rows")
+        m = W2.shape[1]
+        if out is None:
+            out = torch.empty((self.n, m), dtype=self.dtype, device=W2.device)
+        _check(lib().hdf_matvec(self._h, W2.data_ptr(), m, W2.stride(0), out.data_ptr(),
+                                out.stride(0), _stream()))
+        return out[:, 0] if squeeze else out
+
+    def backward(self, W, V, need_l=True, need_x=True):
+        raise HDFError(-1, "backward is defined for the symmetric factor only")
+
+    def factor_parts_y(self):
+        """(phi, q) copies at the Y points: H x n_y and S x n_y."""
+        inf = self.info()
+        phi = torch.empty((inf["n_harmonics"], self.n_y), dtype=self.dtype, device=self.device)
+        q = torch.empty((inf["n_radial"], self.n_y), dtype=self.dtype, device=self.device)
+        _check(lib().hdf_copy_factor_y(self._h, phi.data_ptr() if phi.numel() else None, self.n_y,
+                                       q.data_ptr() if q.numel() else None, self.n_y, _stream()))
+        return phi, q
+
+
 def build(X, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None):
     return Factor(X, kernel, lengthscale, tol, precision)
 
@@ -256,6 +318,22 @@ def plan_cores(a, p, d, u0, u1):
         cores.append(out[o:o + L * L].reshape(L, L))
         o += L * L
     return cores
+
+
+def plan_compress_cross(Gx, Gy, M, tau, null_rel=1e-15):
+    """Cross compression of one degree (single pass): (sig, Ex, Ey)."""
+    import numpy as np
+    L = M.shape[0]
+    Gx, Gy, M = (np.ascontiguousarray(a, dtype=np.float64) for a in (Gx, Gy, M))
+    s = ctypes.c_int32(0)
+    sig = np.zeros(L)
+    Ex = np.zeros(L * L)
+    Ey = np.zeros(L * L)
+    _check(lib().hdf_plan_compress_cross(L, Gx.ctypes.data, Gy.ctypes.data, M.ctypes.data, float(tau),
+                                         float(null_rel), ctypes.byref(s), sig.ctypes.data, Ex.ctypes.data,
+                                         Ey.ctypes.data))
+    n = s.value
+    return sig[:n], Ex[:n * L].reshape(n, L).T, Ey[:n * L].reshape(n, L).T
 
 
 def plan_index_set(d, k):

@@ -115,3 +115,36 @@ def test_host_entry_point_errors():
         hdf.plan_chebyshev("gaussian", 1.0, -1.0)
     with pytest.raises(hdf.HDFError):
         hdf.plan_chebyshev("gaussian", 1.0, 1.0, n_nodes=1000)
+
+
+def test_planner_cross_compression_matches_oracle():
+    """Gram + SVD route of the library vs the oracle's QR + SVD (Algorithm 1,
+    general case) on well-conditioned degrees: singular values and radial
+    functions Y_x E_x, Y_y E_y agree."""
+    import numpy as np
+    from oracle import cross, hdf as ohdf
+    hdf = _lib()
+    rng = np.random.default_rng(12)
+    X = rng.uniform(-1, 1, size=(600, 4))
+    Y = rng.normal(size=(500, 4)) * 0.5
+    sc = cross.build_cross(X, Y, "cauchy", 1.0, 1e-5)
+    rx2, ry2 = sc["geo"]["rho2"][:600], sc["geo"]["rho2"][600:]
+    for dd in sc["deg"]:
+        k, L = dd["k"], dd["L"]
+        if L > 6 or dd["s"] == 0:
+            continue
+        Yx = (np.sqrt(rx2) ** k)[:, None] * ohdf.cheb_basis(ohdf.cheb_arg(rx2, sc["u0"], sc["u1"]), L)
+        Yy = (np.sqrt(ry2) ** k)[:, None] * ohdf.cheb_basis(ohdf.cheb_arg(ry2, sc["u0"], sc["u1"]), L)
+        cond = max(np.linalg.cond(Yx.T @ Yx), np.linalg.cond(Yy.T @ Yy))
+        sig, Ex, Ey = hdf.plan_compress_cross(Yx.T @ Yx, Yy.T @ Yy, np.array(sc["cores"][k]), sc["tau"])
+        assert len(sig) == dd["s"]
+        np.testing.assert_allclose(sig, dd["sig"], rtol=0, atol=1e-13 * cond * dd["sig_all"][0])
+        gaps = np.abs(np.diff(dd["sig_all"]))
+        for c in range(dd["s"]):
+            gap = min(gaps[c - 1] if c > 0 else np.inf, gaps[c] if c < len(gaps) else np.inf)
+            bound = 1e-13 * cond * (1 + dd["sig_all"][0] / gap)
+            if bound < 1e-6:
+                qx, qxo = Yx @ Ex[:, c], Yx @ dd["Ex"][:, c]
+                qy, qyo = Yy @ Ey[:, c], Yy @ dd["Ey"][:, c]
+                assert np.linalg.norm(qx - qxo) <= bound * np.linalg.norm(qxo), (k, c)
+                assert np.linalg.norm(qy - qyo) <= bound * np.linalg.norm(qyo), (k, c)
