@@ -126,6 +126,45 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
                 k_mv_reduce_ms=avg["k_mv_red"], k_adjoint_ms=avg["k_adj"], info=info)
 
 
+def run_cross(wname, X, nq, m, precision, steps, warmup):
+    """General factor K(X*, X) on the workload's cloud X and nq query points
+    drawn from the same family (shifted, seed 9): one step = hdf_build_cross +
+    hdf_matvec (m RHS of the training side)."""
+    import numpy as np
+    import torch
+    from paper_2202_03655_amd import hdf, workloads
+    cfg = hdf_cfg(wname)
+    rng = np.random.default_rng(9)
+    Q = X[rng.choice(len(X), nq, replace=False)] * 0.95 + 0.01
+    dt = torch.float32 if precision == "mixed" else torch.float64
+    prec = hdf.HDF_MIXED if precision == "mixed" else hdf.HDF_FP64
+    Xd = torch.tensor(X, dtype=dt, device="cuda")
+    Qd = torch.tensor(Q, dtype=dt, device="cuda")
+    W = torch.tensor(workloads.rhs(len(X), m, 12), dtype=dt, device="cuda")
+    out = torch.empty((nq, m), dtype=dt, device="cuda")
+
+    def step():
+        f = hdf.CrossFactor(Qd, Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec)
+        f.matvec(W, out=out)
+        return f
+
+    for _ in range(warmup):
+        step().info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = None
+    for _ in range(steps):
+        info = step().info()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"n_query": nq, "n_train": len(X), "rhs": m, "ms_per_step": round(ms, 3),
+            "value": round((nq + len(X)) / (ms * 1e-3) / 1e6, 3), "unit": "Mpoints/s",
+            "rank": info["rank"], "degree_p": info["degree_p"],
+            "kernel_ms": {"build_both_sides": round(info["t_build_ms"], 4), "matvec_pass1": round(info["t_mv_t_ms"], 4),
+                          "matvec_pass2": round(info["t_mv_n_ms"], 4)},
+            "step": "hdf_build_cross + hdf_matvec"}
+
+
 def hdf_cfg(wname):
     from paper_2202_03655_amd import workloads
     return workloads.CONFIGS[wname]
@@ -181,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--cross", type=int, default=0, metavar="NQ",
+                    help="also time the general factor K(X*, X) (X* = NQ query points) and its product")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -215,10 +256,10 @@ def main():
     mvn_bytes = N * (H + S + m) * el
     kernels = {"k_build": (res["k_build_ms"], build_bytes), "k_mv_t": (res["k_mv_t_ms"], mvt_bytes),
                "k_mv_n": (res["k_mv_n_ms"], mvn_bytes)}
-    # launches per step: pass 1 runs once in hdf_matvec and twice in
-    # hdf_backward (U^T V and U^T W); the dominant kernel has the largest
-    # device time per step
-    per_step = {"k_build": res["k_build_ms"], "k_mv_t": res["k_mv_t_ms"] * (3 if with_backward else 1),
+    # launches per step: pass 1 runs once in hdf_matvec and once in
+    # hdf_backward (U^T [V | W] in one pass); the dominant kernel has the
+    # largest device time per step
+    per_step = {"k_build": res["k_build_ms"], "k_mv_t": res["k_mv_t_ms"] * (2 if with_backward else 1),
                 "k_mv_n": res["k_mv_n_ms"]}
     dom = max(per_step, key=lambda k: per_step[k])
     t_ms, nbytes = kernels[dom]
@@ -262,6 +303,8 @@ def main():
                        "matvec_gflops": round(4.0 * N * r64["info"]["rank"] * m / (r64["matvec_ms"] * 1e-3) / 1e9, 1),
                        "rank": r64["info"]["rank"]}
         out["speedup_vs_fp64"] = round(r64["ms_per_step"] / res["ms_per_step"], 3)
+    if args.cross:
+        out["cross"] = run_cross(args.workload, X, args.cross, m, args.precision, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, X, V, min(args.cpu_sample, N))
     print(json.dumps(out), flush=True)
