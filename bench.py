@@ -88,7 +88,7 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
         del f
     torch.cuda.synchronize()
     rec = dict(build_s=[], bw_s=[], k_build=[], k_mv_t=[], k_mv_n=[], k_mv_red=[], k_adj=[], h_prep=[],
-               h_plan=[], h_gram=[], h_compress=[])
+               h_plan=[], h_gram=[], h_compress=[], h_finish=[])
     t_start = time.perf_counter()
     info = None
     for _ in range(steps):
@@ -96,7 +96,7 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
         info = f.info()                      # waits for the step's last kernel
         rec["build_s"].append(tb)
         rec["bw_s"].append(tbw)
-        for key in ("prep", "plan", "gram", "compress"):
+        for key in ("prep", "plan", "gram", "compress", "finish"):
             rec["h_" + key].append(info[f"t_{key}_ms"])
         rec["k_build"].append(info["t_build_ms"])
         rec["k_mv_t"].append(info["t_mv_t_ms"])
@@ -121,7 +121,8 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
     avg = {k: sum(v) / len(v) for k, v in rec.items()}
     return dict(ms_per_step=1e3 * t_total / steps, build_ms=1e3 * avg["build_s"], matvec_ms=1e3 * mv_s,
                 backward_ms=1e3 * avg["bw_s"],
-                build_phases_ms={k[2:]: round(avg[k], 3) for k in ("h_prep", "h_plan", "h_gram", "h_compress")},
+                build_phases_ms={k[2:]: round(avg[k], 3) for k in ("h_prep", "h_plan", "h_gram", "h_compress",
+                                                                   "h_finish")},
                 k_build_ms=avg["k_build"], k_mv_t_ms=avg["k_mv_t"], k_mv_n_ms=avg["k_mv_n"],
                 k_mv_reduce_ms=avg["k_mv_red"], k_adjoint_ms=avg["k_adj"], info=info)
 

@@ -92,6 +92,7 @@ typedef struct {
   double   t_gram_ms;        /* host wall waiting on the Gram pass beyond the
                                 planner work that overlaps it                */
   double   t_compress_ms;    /* host wall: compression incl. refinement pass */
+  double   t_finish_ms;      /* host wall: tables, allocation, factor launch  */
   double   t_build_ms;       /* factor-evaluation kernel (HIP events)        */
   double   t_mv_t_ms;        /* last hdf_matvec: pass 1 kernel (U^T V)       */
   double   t_mv_reduce_ms;   /* last hdf_matvec: split reduction + scaling   */

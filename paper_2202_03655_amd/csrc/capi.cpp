@@ -79,7 +79,7 @@ struct hdf_factor {
   int64_t H = 0, S = 0, r = 0;
   int max_s = 0;
   int n_refined = 0;                              // degrees refined by the second Gram pass
-  double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_build = -1;
+  double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_finish = 0, t_build = -1;
   hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;
   hipEvent_t ev_mv[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_adj[2] = {nullptr, nullptr};
@@ -160,6 +160,11 @@ void loop_order_columns(int d, int K, const std::map<std::vector<int>, int>& can
 // evaluates its Y side too, with the Y-side radial coefficients; its diagonal
 // is the identity (sqrt of the singular values is folded into both sides).
 static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
+  struct FinishTimer {
+    hdf_factor* f;
+    double t;
+    ~FinishTimer() { f->t_finish = now_ms() - t; }
+  } timer{f, 0.0};
   const int K = f->K, d = f->d, dtype = f->dtype;
   const int prec = f->prec;
   const int64_t n = f->N;
@@ -192,6 +197,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   }
   f->H = hoff; f->S = qoff; f->r = roff;
   f->t_compress = now_ms() - t0;
+  timer.t = now_ms();
 
   // 5. memory budget, then the factor evaluation
   const size_t fbytes = (size_t)(f->H + f->S) * (f->ldN + (f->cross ? f->ldN2 : 0)) * f->elem();
@@ -1004,6 +1010,7 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   info->t_plan_ms = h->t_plan;
   info->t_gram_ms = h->t_gram;
   info->t_compress_ms = h->t_compress;
+  info->t_finish_ms = h->t_finish;
   if (h->ev_b0 && h->ev_b1 && h->t_build < 0) {
     float ms = 0.f;
     if (hipEventSynchronize(h->ev_b1) == hipSuccess && hipEventElapsedTime(&ms, h->ev_b0, h->ev_b1) == hipSuccess)

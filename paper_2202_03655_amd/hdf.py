@@ -35,7 +35,7 @@ class HDFInfo(ctypes.Structure):
         ("center_radius", ctypes.c_double), ("rho2_min", ctypes.c_double),
         ("rho2_max", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
         ("t_prep_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double),
-        ("t_gram_ms", ctypes.c_double), ("t_compress_ms", ctypes.c_double),
+        ("t_gram_ms", ctypes.c_double), ("t_compress_ms", ctypes.c_double), ("t_finish_ms", ctypes.c_double),
         ("t_build_ms", ctypes.c_double), ("t_mv_t_ms", ctypes.c_double),
         ("t_mv_reduce_ms", ctypes.c_double), ("t_mv_n_ms", ctypes.c_double),
         ("t_adjoint_ms", ctypes.c_double),
