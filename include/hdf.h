@@ -61,7 +61,9 @@ typedef enum {
   HDF_E_INFEASIBLE = -4,  /* degree above HDF_MAX_DEGREE, or the factor would
                              exceed the memory budget (see hdf_build)        */
   HDF_E_OOM        = -5,  /* device allocation failed                        */
-  HDF_E_HIP        = -6   /* a HIP runtime call failed                       */
+  HDF_E_HIP        = -6,  /* a HIP runtime call failed                       */
+  HDF_E_DISABLED   = -7   /* the requested operation is switched off in this
+                             library (see hdf_backward)                      */
 } hdf_status;
 
 #define HDF_MAX_DIM     8
@@ -150,7 +152,12 @@ hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv,
  *   dlength  host, receives dF/dl (NULL: not computed).
  *   dX       device, n x d with leading dimension lddx (>= d), receives dF/dX
  *            (NULL: not computed); same dtype as the points.
- * One blocking synchronisation when dlength != NULL. */
+ * One blocking synchronisation when dlength != NULL.
+ * dF/dX is switched off unless the library is compiled with
+ * -DHDF_ADJOINT_KERNEL=1: a request with dX != NULL returns HDF_E_DISABLED
+ * before any device work.  The adjoint kernels are withdrawn until a device
+ * memory fault seen in runs that called them is explained; dF/dl (pass 1 and
+ * host arithmetic) is unaffected. */
 hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
                         double* dlength, void* dX, int64_t lddx, void* hip_stream);
 

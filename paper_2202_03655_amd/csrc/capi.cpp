@@ -110,6 +110,12 @@ struct hdf_factor {
   size_t elem() const { return prec == HDF_MIXED ? 4 : 8; }
 };
 
+// dF/dX (k_adj_pack + k_adjoint) is compiled but not dispatched unless enabled.
+#ifndef HDF_ADJOINT_KERNEL
+#define HDF_ADJOINT_KERNEL 0
+#endif
+constexpr bool kAdjointKernel = HDF_ADJOINT_KERNEL != 0;
+
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
@@ -341,6 +347,7 @@ const char* hdf_status_string(hdf_status s) {
     case HDF_E_INFEASIBLE: return "infeasible: degree or factor size above the limits";
     case HDF_E_OOM: return "device out of memory";
     case HDF_E_HIP: return "HIP runtime error";
+    case HDF_E_DISABLED: return "operation switched off in this library";
   }
   return "unknown status";
 }
@@ -848,6 +855,9 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
   if (ld < m) return fail(HDF_E_ARG, "ld must be >= m");
   if (dX && lddx < h->d) return fail(HDF_E_ARG, "lddx must be >= d");
   if (h->cross) return fail(HDF_E_ARG, "hdf_backward needs a symmetric factor (hdf_build)");
+  if (dX && !kAdjointKernel)
+    return fail(HDF_E_DISABLED, "dF/dX is switched off (compile with -DHDF_ADJOINT_KERNEL=1): the adjoint "
+                                "kernels are withdrawn until a device memory fault seen with them is explained");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t el = h->elem();
   if (!dlength && !dX) return HDF_OK;

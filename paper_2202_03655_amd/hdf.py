@@ -17,7 +17,7 @@ KERNELS = {"gaussian": 0, "cauchy": 1, "matern32": 2, "matern52": 3}
 HDF_FP64, HDF_MIXED = 0, 1
 HDF_MAX_DEGREE = 60
 STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
-          -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP"}
+          -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP", -7: "HDF_E_DISABLED"}
 
 EXPORTS = ["hdf_build", "hdf_build_cross", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
            "hdf_copy_factor", "hdf_copy_factor_y", "hdf_free", "hdf_status_string", "hdf_last_error",

@@ -188,3 +188,8 @@ def test_error_paths():
         f.matvec(torch.zeros((63, 1), dtype=torch.float64, device="cuda"))
     with pytest.raises(hdf.HDFError):
         f.matvec(torch.zeros((64, 300), dtype=torch.float64, device="cuda"))
+    # dF/dX is switched off: refused before any device work
+    Z = torch.zeros((64, 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(hdf.HDFError) as e:
+        f.backward(Z, Z, need_l=False, need_x=True)
+    assert e.value.status == -7
