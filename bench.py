@@ -222,7 +222,7 @@ def main():
     ap.add_argument("--with-backward", action="store_true",
                     help="add hdf_backward (dF/dl only; dF/dX is switched off in the library) to the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--cross", type=int, default=0, metavar="NQ",
                     help="also time the general factor K(X*, X) (X* = NQ query points) and its product")
