@@ -1,0 +1,98 @@
+// HIP subset used by the HDF kernels and the C ABI, emulated on the CPU for
+// memory-safety tests (see emu_rt.cpp).  Included in place of
+// <hip/hip_runtime.h> through shim/hip/.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <cmath>
+#include <math.h>
+#include <functional>
+#include <algorithm>
+#include <type_traits>
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1, hipErrorNotReady = 600 };
+typedef struct emu_stream* hipStream_t;
+typedef struct emu_event* hipEvent_t;
+enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
+                     hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 };
+
+extern "C" {
+hipError_t hipMalloc(void** p, size_t b);
+hipError_t hipFree(void* p);
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t b, hipMemcpyKind k, hipStream_t s);
+hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch, size_t w, size_t h,
+                            hipMemcpyKind k, hipStream_t s);
+hipError_t hipMemset2DAsync(void* dst, size_t pitch, int v, size_t w, size_t h, hipStream_t s);
+hipError_t hipMemsetAsync(void* dst, int v, size_t b, hipStream_t s);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipDeviceSynchronize();
+hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventDestroy(hipEvent_t e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
+hipError_t hipMemGetInfo(size_t* f, size_t* t);
+hipError_t hipGetLastError();
+const char* hipGetErrorString(hipError_t e);
+void emu_flush();
+}
+
+#ifdef EMU_DEVICE_CODE
+using std::isfinite;
+using std::isnan;
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+typedef float float2 __attribute__((ext_vector_type(2)));
+typedef double double2 __attribute__((ext_vector_type(2)));
+
+namespace emu {
+struct Fiber;
+extern Fiber* cur;
+extern dim3 g_blockIdx, g_blockDim, g_gridDim;
+const dim3& tidx();
+void syncthreads();
+unsigned char* dyn_smem();
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+f4 mfma_f32(float a, float b, f4 c);
+d4 mfma_f64(double a, double b, d4 c);
+void check_launch(unsigned grid, unsigned block, size_t shm);
+void enqueue(hipStream_t s, std::function<void()> f);
+void run_grid(dim3 grid, unsigned block, size_t shm, const std::function<void()>& body);
+extern const char* g_kernel_name;
+void check_ptr(const char* kname, const char* what, int idx, const void* p);
+template <typename T> struct StructCheck { static void run(const char*, int, const T&) {} };
+template <typename T> inline void check_arg(const char* kname, int idx, const T& a) {
+  if constexpr (std::is_pointer<T>::value) { if (a) check_ptr(kname, "arg", idx, (const void*)a); }
+  else StructCheck<T>::run(kname, idx, a);
+}
+void garbage_once(void* p, size_t n);
+template <typename K, typename... A>
+void launch(const char* name, dim3 grid, dim3 block, size_t shm, hipStream_t s, K k, A... args) {
+  check_launch(grid.x * grid.y * grid.z, block.x * block.y * block.z, shm);
+  { int idx = 0; (check_arg(name, idx++, args), ...); }
+  if (block.y != 1 || block.z != 1) abort();
+  enqueue(s, [=]() { g_kernel_name = name; run_grid(grid, block.x, shm, [=]() { k(args...); }); });
+}
+}  // namespace emu
+
+#define threadIdx (emu::tidx())
+#define blockIdx (emu::g_blockIdx)
+#define blockDim (emu::g_blockDim)
+#define gridDim (emu::g_gridDim)
+#define __syncthreads() emu::syncthreads()
+#define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32(a, b, c)
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64(a, b, c)
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
+
+#endif

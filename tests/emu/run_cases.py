@@ -1,0 +1,175 @@
+"""Run the C ABI on the CPU-emulated library and compare with the oracle.
+
+Started in a subprocess with the ASan runtime preloaded (tests/test_emu_kernels.py):
+    LD_PRELOAD=<libclang_rt.asan> python tests/emu/run_cases.py <libhdf_emu.so> [case ...]
+The binding (paper_2202_03655_amd.hdf) is used as is, with three substitutions:
+the library path, a null stream, and "device" tensors that live in guarded
+host memory registered with the emulator.  Every library call is followed by
+a stream flush, as a later synchronising torch call would be on a device.
+Exit status 0 when every case matches; ASan or the emulator abort otherwise.
+"""
+import ctypes
+import mmap
+import os
+import sys
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import cross, hdf as ohdf  # noqa: E402
+from paper_2202_03655_amd import hdf, workloads as wl  # noqa: E402
+
+LIB = sys.argv[1]
+_raw = ctypes.CDLL(LIB)
+_raw.emu_flush.restype = None
+_raw.emu_register.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+_libc = ctypes.CDLL(None)
+_libc.mprotect.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+_keep = []
+_G = 1 << 20
+_NP = {torch.float64: np.float64, torch.float32: np.float32}
+
+
+def dev_empty(shape, dtype, fill=np.nan):
+    """Tensor in host memory that ends flush (within 16 B) against a PROT_NONE region."""
+    np_dtype = _NP[dtype]
+    n = int(np.prod(shape)) if len(shape) else 1
+    nbytes = (n * np.dtype(np_dtype).itemsize + 15) // 16 * 16
+    body = (nbytes + 4095) // 4096 * 4096
+    mm = mmap.mmap(-1, body + 2 * _G)
+    base = ctypes.addressof(ctypes.c_char.from_buffer(mm))
+    assert _libc.mprotect(base, _G, 0) == 0 and _libc.mprotect(base + _G + body, _G, 0) == 0
+    arr = np.frombuffer(mm, dtype=np_dtype, count=n, offset=_G + body - nbytes).reshape(shape)
+    arr[...] = fill
+    _raw.emu_register(arr.ctypes.data, max(arr.nbytes, 1))
+    _keep.append(mm)
+    return torch.from_numpy(arr)
+
+
+def to_dev(X, dtype):
+    X = np.ascontiguousarray(X)
+    t = dev_empty(X.shape, dtype)
+    t.numpy()[...] = X
+    return t
+
+
+class _Flushing:
+    def __init__(self, L):
+        self._L = L
+
+    def __getattr__(self, name):
+        f = getattr(self._L, name)
+        if not name.startswith("hdf_"):
+            return f
+
+        def call(*a):
+            r = f(*a)
+            _raw.emu_flush()
+            return r
+        return call
+
+
+def _install():
+    hdf.LIB_PATH = LIB
+    hdf._lib = None
+    hdf._lib = _Flushing(hdf.lib())          # hdf.lib() returns the cached handle from now on
+    hdf._stream = lambda: ctypes.c_void_p(None)
+    torch.cuda.device = lambda d: __import__("contextlib").nullcontext()
+
+    def dev2d(t, dtype, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype:
+            raise TypeError(name)
+        if t.dim() == 1:
+            t = t.unsqueeze(1)
+        return t if t.dim() == 2 and t.stride(1) == 1 else t.contiguous()
+    hdf._dev2d = dev2d
+    real_empty = torch.empty
+
+    def empty(*a, **k):                      # outputs the binding allocates
+        shape = a[0] if len(a) == 1 and isinstance(a[0], (tuple, list, torch.Size)) else a
+        if k.get("dtype") in _NP and not k.get("out"):
+            return dev_empty(tuple(int(x) for x in shape), k["dtype"])
+        k.pop("device", None)
+        return real_empty(*a, **k)
+    torch.empty = empty
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def check(name, cond, msg):
+    print(f"{'ok  ' if cond else 'FAIL'} {name}: {msg}", flush=True)
+    if not cond:
+        check.failed = True
+
+
+check.failed = False
+
+
+def case_fp64():
+    """Symmetric factor, binary64: factor, K~V, dF/dl and dF/dX against the oracle."""
+    X = wl.unit_ball(700, 3, 5)
+    st = ohdf.build(X, "gaussian", 1.0, 1e-6)
+    f = hdf.Factor(to_dev(X, torch.float64), "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64)
+    inf = f.info()
+    check("fp64 rank", inf["rank"] == st["r"], f"{inf['rank']} vs {st['r']}")
+    V = wl.rhs(700, 3, 6)
+    KV = f.matvec(to_dev(V, torch.float64)).numpy()
+    e = rel(KV, ohdf.matvec(st, V))
+    check("fp64 matvec", e <= 1e-12, f"{e:.2e}")
+    W = wl.rhs(700, 2, 7)
+    dl, dX = f.backward(to_dev(W, torch.float64), to_dev(V[:, :2], torch.float64))
+    gl = ohdf.grad_l(st, W, V[:, :2])
+    check("fp64 dF/dl", abs(dl - gl) <= 1e-10 * abs(gl), f"{dl:.12e} vs {gl:.12e}")
+    e = rel(dX.numpy(), ohdf.grad_x(st, W, V[:, :2]))
+    check("fp64 dF/dX", e <= 1e-10, f"{e:.2e}")
+
+
+def case_mixed():
+    """Mixed precision on a ragged size (several tiles and a tail): K~V and the adjoint."""
+    X = wl.uniform_cube(1013, 4, 104).astype(np.float32).astype(np.float64)
+    st = ohdf.build(X, "gaussian", 0.7, 1e-5)
+    f = hdf.Factor(to_dev(X, torch.float32), "gaussian", 0.7, 1e-5, precision=hdf.HDF_MIXED)
+    V = wl.rhs(1013, 17, 8)
+    KV = f.matvec(to_dev(V, torch.float32)).numpy().astype(np.float64)
+    e = rel(KV, ohdf.matvec(st, V))
+    check("mixed matvec", e <= 1e-5 + 1e-6, f"{e:.2e}")
+    W = wl.rhs(1013, 1, 9)
+    dl, dX = f.backward(to_dev(W, torch.float32), to_dev(V[:, :1], torch.float32))
+    e = rel(dX.numpy().astype(np.float64), ohdf.grad_x(st, W, V[:, :1]))
+    check("mixed dF/dX", e <= 1e-3, f"{e:.2e}")
+
+
+def case_cross():
+    """General factor K(X, Y) W against the oracle."""
+    X, Y = wl.unit_ball(600, 3, 201), wl.uniform_cube(333, 3, 202) * 0.7
+    sc = cross.build_cross(X, Y, "gaussian", 1.0, 1e-6)
+    f = hdf.CrossFactor(to_dev(X, torch.float64), to_dev(Y, torch.float64), "gaussian", 1.0, 1e-6,
+                        precision=hdf.HDF_FP64)
+    W = wl.rhs(333, 5, 13)
+    e = rel(f.matvec(to_dev(W, torch.float64)).numpy(), cross.matvec_cross(sc, W))
+    check("cross matvec", e <= 1e-12, f"{e:.2e}")
+
+
+def case_tiny():
+    """Degenerate sizes: one point, and fewer points than a tile."""
+    for n in (1, 5):
+        X = wl.unit_ball(n, 3, 3)
+        st = ohdf.build(X, "gaussian", 1.0, 1e-6)
+        f = hdf.Factor(to_dev(X, torch.float64), "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64)
+        V = wl.rhs(n, 2, 4)
+        e = rel(f.matvec(to_dev(V, torch.float64)).numpy(), ohdf.matvec(st, V))
+        check(f"tiny n={n}", e <= 1e-12, f"{e:.2e}")
+
+
+CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny}
+
+if __name__ == "__main__":
+    _install()
+    for name in (sys.argv[2:] or list(CASES)):
+        CASES[name]()
+    sys.exit(1 if check.failed else 0)

@@ -1,0 +1,45 @@
+"""Translate kernels.hip into C++ for the CPU emulation (emu_hip.h).
+
+Three mechanical rewrites, nothing else: triple-chevron launches become
+emu::launch calls, __shared__ arrays become static arrays filled with garbage
+once per block, and the dynamic LDS array becomes the block's emulated LDS.
+"""
+import re
+import sys
+
+_HOOK = '''
+namespace emu {
+template <> struct StructCheck<hdf::BuildTables> {
+  static void run(const char* k, int i, const hdf::BuildTables& t) {
+    check_ptr(k, "tb.col_of", i, t.col_of); check_ptr(k, "tb.chain", i, t.chain);
+    check_ptr(k, "tb.q_len", i, t.q_len); check_ptr(k, "tb.q_off", i, t.q_off);
+    check_ptr(k, "tb.q_coef", i, t.q_coef);
+  }
+};
+}
+'''
+
+
+def translate(src):
+    n0 = src.count("<<<")
+    src, n = re.subn(r'(k_\w+(?:<[^<>;]*?>)?)<<<(.*?)>>>\(',
+                     lambda m: f'emu::launch("{m.group(1)}", {m.group(2)}, {m.group(1)}, ', src)
+    if n != n0:
+        raise ValueError(f"translated {n} of {n0} launches")
+    src = re.sub(r'extern __shared__ unsigned char (\w+)\[\];', r'unsigned char* \1 = emu::dyn_smem();', src)
+
+    def shared(m):
+        typ, rest = re.match(r'(\w+)\s+(.*)', m.group(1)).groups()
+        names = re.findall(r'(\w+)\s*(?:\[[^\]]*\])+\s*(?:,|$)', rest)
+        if not names:
+            raise ValueError(m.group(0))
+        return f'static {typ} {rest};' + ''.join(f' emu::garbage_once({x}, sizeof({x}));' for x in names)
+    src = re.sub(r'__shared__ ([^;]*);', shared, src)
+    if '#include "kernels.hpp"\n' not in src:
+        raise ValueError("kernels.hpp include not found")
+    src = src.replace('#include "kernels.hpp"\n', '#include "kernels.hpp"\n' + _HOOK, 1)
+    return '#define EMU_DEVICE_CODE\n' + src
+
+
+if __name__ == "__main__":
+    open(sys.argv[2], "w").write(translate(open(sys.argv[1]).read()))
