@@ -30,6 +30,9 @@ Hyperspherical Harmonics" (Ryan & Damle, ICML 2022) step by step:
                    frozen-structure derivatives,
 * cross.py      -- Algorithm 1 in the general case X != Y (QR of both radial
                    matrices, SVD of R_x M_k R_y^T, K(X, Y) ~ U V^T),
+* adaptive.py   -- the tighter degree and rank selection of the remark after
+                   Eq. bound (sampled Frobenius error, tau raised while the
+                   estimate stays within the tolerance),
 * dense.py      -- the dense kernel matrix and its truncated eigendecomposition
                    (the optimal-rank reference of Sec. 4.1, Fig. 3).
 
