@@ -62,7 +62,7 @@ def read_traffic(kernel, workload):
     return None
 
 
-def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
+def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule="bound"):
     import torch
     from paper_2202_03655_amd import hdf
     cfg = hdf_cfg(wname)
@@ -75,7 +75,7 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
 
     def step():
         t0 = time.perf_counter()
-        f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec)
+        f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule)
         t1 = time.perf_counter()
         f.matvec(Vd, out=out)
         t2 = time.perf_counter()
@@ -108,7 +108,7 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     # separate matvec timing on a resident factor (wall clock of the call)
-    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec)
+    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule)
     for _ in range(2):
         f.matvec(Vd, out=out)
     torch.cuda.synchronize()
@@ -219,6 +219,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--rhs", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 comparison path")
+    ap.add_argument("--no-sampled", action="store_true", help="skip the run with the sampled degree/rank rule")
     ap.add_argument("--with-backward", action="store_true",
                     help="add hdf_backward (dF/dl only; dF/dX is switched off in the library) to the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -310,6 +311,16 @@ def main():
                        "matvec_gflops": round(4.0 * N * r64["info"]["rank"] * m / (r64["matvec_ms"] * 1e-3) / 1e9, 1),
                        "rank": r64["info"]["rank"]}
         out["speedup_vs_fp64"] = round(r64["ms_per_step"] / res["ms_per_step"], 3)
+    if not args.no_sampled:
+        # the tighter degree / rank rule (remark after Eq. bound) on the same inputs
+        rs = run_gpu(args.workload, X, V, Wm, args.precision, args.steps, args.warmup, False, "sampled")
+        si = rs["info"]
+        out["sampled_rule"] = {"ms_per_step": round(rs["ms_per_step"], 3),
+                               "value": round(N / (rs["ms_per_step"] * 1e-3) / 1e6, 3),
+                               "build_ms": round(rs["build_ms"], 3), "matvec_ms": round(rs["matvec_ms"], 3),
+                               "p": si["degree_p"], "p_bound": si["degree_bound"], "rank": si["rank"],
+                               "tau": si["tau"], "tau_bound": si["tau_bound"],
+                               "est_error": si["est_error"]}
     if args.cross:
         out["cross"] = run_cross(args.workload, X, args.cross, m, args.precision, args.steps, args.warmup)
     if not args.no_cpu_baseline:

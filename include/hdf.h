@@ -102,6 +102,13 @@ typedef struct {
   double   t_adjoint_ms;     /* last hdf_backward with dX: adjoint kernels   */
   int32_t  n_refined;        /* degrees refined by the second Gram pass      */
   int32_t  s_k[HDF_MAX_DEGREE / 2 + 1];   /* kept radial rank per degree   */
+  int32_t  rank_rule;        /* hdf_rank_rule the factor was built with      */
+  double   tau_bound;        /* threshold of the error budget at degree_p    */
+  double   est_error;        /* HDF_RULE_SAMPLED: sampled relative Frobenius
+                                error of the factor; -1 otherwise           */
+  int32_t  degree_bound;     /* degree the budget rule picks (may differ from
+                                degree_p under HDF_RULE_SAMPLED; -1 if above
+                                HDF_MAX_DEGREE)                             */
 } hdf_info_t;
 
 /* Build the factor (Algorithm 1, symmetric case, Remark 1).
@@ -121,6 +128,36 @@ typedef struct {
 hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld,
                      hdf_kernel kernel, double lengthscale, double tol,
                      hdf_precision prec, void* hip_stream, hdf_handle* out);
+
+/* How p and tau are chosen. */
+typedef enum {
+  HDF_RULE_BOUND   = 0,  /* a-priori: Chebyshev tail <= tol nu / 2 and the
+                            Frobenius budget threshold (Sec. 3.5, Eq. bound) */
+  HDF_RULE_SAMPLED = 1   /* tighter (remark after Eq. bound): smallest even p
+                            whose sampled Chebyshev truncation error is
+                            <= tol / 2, then tau raised from the budget value,
+                            dropping eigenpairs in increasing |lambda| while
+                            the sampled error of U D U^T stays <= margin tol */
+} hdf_rank_rule;
+
+/* Options of hdf_build_ex; zero-initialised fields take the defaults. */
+typedef struct {
+  int32_t rank_rule;     /* hdf_rank_rule (default HDF_RULE_BOUND)          */
+  int32_t n_pairs;       /* sampled pairs, 1 .. 1048576 (default 16384)      */
+  double  margin;        /* share of tol the sampled error may use, (0, 1]
+                            (default 0.8)                                    */
+} hdf_build_options;
+
+/* hdf_build with options (NULL: defaults, identical to hdf_build).  Under
+ * HDF_RULE_SAMPLED the relative Frobenius error is estimated from n_pairs
+ * SplitMix64 pairs (seed 0x48444601, outputs 2t+1 and 2t+2 of pair t),
+ * stratified into the off-diagonal pairs and the diagonal at the pairs'
+ * first points, ||E||^2 ~ N(N-1) mean_off e^2 + N mean_diag e^2 (likewise
+ * ||K||^2).  The estimate is not a bound: the result meets tol up to the
+ * sampling error that the margin absorbs.  No additional synchronisation. */
+hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t ld,
+                        hdf_kernel kernel, double lengthscale, double tol, hdf_precision prec,
+                        const hdf_build_options* opts, void* hip_stream, hdf_handle* out);
 
 /* General case X != Y (Algorithm 1 with two point sets): K(X, Y) ~ U V^T.
  *   x       device, nx x d (leading dimension ldx >= d); y device, ny x d

@@ -61,6 +61,8 @@ struct hdf_factor {
   hdf::GeoDev geo{};
   double u0 = 0, u1 = 1, nu = 0, tail = 0, tau = 0;
   int p = 0, K = 0;
+  int rank_rule = HDF_RULE_BOUND, p_bound = -1;
+  double tau0 = 0, est_error = -1.0;             // budget threshold, sampled estimate
   std::vector<double> a;                          // p+1 coefficients
   std::vector<std::vector<double>> cores;
   std::vector<hdf::DegreeFactor> deg;             // k = 0..K
@@ -165,6 +167,12 @@ void loop_order_columns(int d, int K, const std::map<std::vector<int>, int>& can
 // common to the symmetric and the general (X != Y) build.  A general factor
 // evaluates its Y side too, with the Y-side radial coefficients; its diagonal
 // is the identity (sqrt of the singular values is folded into both sides).
+// Zero columns [n, ld) of a rows x ld matrix (the padding of the factor rows).
+static hipError_t clear_padding(void* base, int64_t rows, int64_t n, int64_t ld, size_t el, hipStream_t s) {
+  if (rows <= 0 || ld <= n) return hipSuccess;
+  return hipMemset2DAsync((char*)base + n * el, ld * el, 0, (ld - n) * el, rows, s);
+}
+
 static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   struct FinishTimer {
     hdf_factor* f;
@@ -325,11 +333,17 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     HIPCHK(hipEventRecord(f->ev_b0, s));
     HIPCHK(hdf::launch_build(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p,
                              f->u0, f->u1, tb, prec, f->phi.p, f->ldN, f->q.p, f->ldN, s));
+    // rows are padded past N: clear the padding so contraction kernels may
+    // read whole 8-point groups without masking
+    HIPCHK(clear_padding(f->phi.p, f->H, n, f->ldN, f->elem(), s));
+    HIPCHK(clear_padding(f->q.p, f->S, n, f->ldN, f->elem(), s));
     if (f->cross) {
       f->tables2 = tb;
       f->tables2.q_coef = f->q_coef2.p;
       HIPCHK(hdf::launch_build(f->x_soa2.p, dtype, f->ldN2, f->N2, d, (const hdf::GeoDev*)f->geo_dev.p,
                                f->u0, f->u1, f->tables2, prec, f->phi2.p, f->ldN2, f->q2.p, f->ldN2, s));
+      HIPCHK(clear_padding(f->phi2.p, f->H, f->N2, f->ldN2, f->elem(), s));
+      HIPCHK(clear_padding(f->q2.p, f->S, f->N2, f->ldN2, f->elem(), s));
     }
     HIPCHK(hipEventRecord(f->ev_b1, s));
   }
@@ -360,6 +374,12 @@ void hdf_free(hdf_handle h) { delete h; }
 hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld,
                      hdf_kernel kernel, double lengthscale, double tol, hdf_precision prec,
                      void* hip_stream, hdf_handle* out) {
+  return hdf_build_ex(points, dtype, n, d, ld, kernel, lengthscale, tol, prec, nullptr, hip_stream, out);
+}
+
+hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t ld,
+                        hdf_kernel kernel, double lengthscale, double tol, hdf_precision prec,
+                        const hdf_build_options* opts, void* hip_stream, hdf_handle* out) {
   g_err.clear();
   if (!out) return fail(HDF_E_ARG, "out is NULL");
   if (!points) return fail(HDF_E_ARG, "points is NULL");
@@ -373,9 +393,16 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   if ((int)kernel < 0 || (int)kernel > 3) return fail(HDF_E_ARG, "unknown kernel");
   if (!(lengthscale > 0) || !std::isfinite(lengthscale)) return fail(HDF_E_ARG, "lengthscale must be > 0");
   if (!(tol > 0 && tol < 1)) return fail(HDF_E_ARG, "tol must be in (0, 1)");
+  const int rule = opts ? opts->rank_rule : HDF_RULE_BOUND;
+  if (rule != HDF_RULE_BOUND && rule != HDF_RULE_SAMPLED) return fail(HDF_E_ARG, "unknown rank_rule");
+  const int n_pairs = (opts && opts->n_pairs) ? opts->n_pairs : 16384;
+  const double margin = (opts && opts->margin != 0.0) ? opts->margin : 0.8;
+  if (n_pairs < 1 || n_pairs > (1 << 20)) return fail(HDF_E_ARG, "n_pairs must be in [1, 1048576]");
+  if (!(margin > 0.0 && margin <= 1.0)) return fail(HDF_E_ARG, "margin must be in (0, 1]");
   hipStream_t s = (hipStream_t)hip_stream;
 
   std::unique_ptr<hdf_factor> f(new hdf_factor());
+  f->rank_rule = rule;
   f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
   f->N = n; f->l = lengthscale; f->tol = tol;
   // rows of the factor are padded by at least 64 points: the streaming kernels
@@ -391,7 +418,31 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   HIPCHK(hdf::launch_prep(points, dtype, n, d, ld, f->x_soa.p, f->ldN, kernel, lengthscale,
                           (double*)f->part.p, (hdf::GeoDev*)f->geo_dev.p, s));
   HIPCHK(hipMemcpyAsync(&f->geo, f->geo_dev.p, sizeof(hdf::GeoDev), hipMemcpyDeviceToHost, s));
+  hdf::PairSample ps;
+  DevBuf pairs_dev;
+  std::vector<double> pair_vals;
+  std::vector<int32_t> pair_idx;
+  if (rule == HDF_RULE_SAMPLED) {
+    HIPCHK(pairs_dev.ensure((size_t)n_pairs * (4 * sizeof(double) + 2 * sizeof(int32_t))));
+    double* pv = (double*)pairs_dev.p;
+    int32_t* pi = (int32_t*)(pv + 4 * (size_t)n_pairs);
+    HIPCHK(hdf::launch_pairs(f->x_soa.p, dtype, f->ldN, n, d, (const hdf::GeoDev*)f->geo_dev.p, hdf::kPairSeed,
+                             n_pairs, pv, pi, s));
+    pair_vals.resize(4 * (size_t)n_pairs);
+    pair_idx.resize(2 * (size_t)n_pairs);
+    HIPCHK(hipMemcpyAsync(pair_vals.data(), pv, pair_vals.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pair_idx.data(), pi, pair_idx.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
+  if (rule == HDF_RULE_SAMPLED) {
+    const size_t M = (size_t)n_pairs;
+    ps.r.assign(pair_vals.begin(), pair_vals.begin() + M);
+    ps.ra2.assign(pair_vals.begin() + M, pair_vals.begin() + 2 * M);
+    ps.rb2.assign(pair_vals.begin() + 2 * M, pair_vals.begin() + 3 * M);
+    ps.dot.assign(pair_vals.begin() + 3 * M, pair_vals.end());
+    ps.a.assign(pair_idx.begin(), pair_idx.begin() + M);
+    ps.b.assign(pair_idx.begin() + M, pair_idx.end());
+  }
   f->t_prep = now_ms() - t0;
   if (f->geo.nonfinite > 0) return fail(HDF_E_NONFINITE, "points contain NaN or Inf");
 
@@ -402,6 +453,12 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
   std::vector<double> afull(hdf::kChebNodes);
   hdf::chebyshev_coeffs(kernel, D, lengthscale, hdf::kChebNodes, false, afull.data());
   f->p = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, HDF_MAX_DEGREE, &f->tail);
+  f->p_bound = f->p;
+  if (rule == HDF_RULE_SAMPLED) {
+    f->p = hdf::choose_degree_sampled(kernel, lengthscale, afull.data(), hdf::kChebNodes, D, (double)n, ps, tol,
+                                      HDF_MAX_DEGREE, f->p_bound);
+    f->tail = -1.0;
+  }
   if (f->p < 0) {
     int pp = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, hdf::kChebNodes - 2, nullptr);
     char buf[160];
@@ -503,6 +560,22 @@ hdf_status hdf_build(const void* points, int dtype, int64_t n, int d, int64_t ld
       hdf::compress_degree_refined(k, L, G2.data(), pcs[k], f->cores[k].data(), f->tau, 1e-14, f->deg[k]);
     }
   }
+  f->tau0 = f->tau;
+  if (rule == HDF_RULE_SAMPLED) {
+    // raise tau from the budget value while the sampled error allows; the
+    // kept eigenpairs of every degree are a prefix in |lambda| order
+    f->tau = hdf::tune_threshold(kernel, lengthscale, d, (double)n, f->u0, f->u1, f->deg, ps, tol, margin, f->tau0,
+                                 &f->est_error);
+    for (int k = 0; k <= K; ++k) {
+      hdf::DegreeFactor& df = f->deg[k];
+      int sk = 0;
+      while (sk < df.s && std::fabs(df.lam[sk]) > f->tau) ++sk;
+      df.s = sk;
+      df.lam.resize(sk);
+      df.E.resize((size_t)sk * df.L);
+      df.Ep.resize((size_t)sk * df.L);
+    }
+  }
   {
     const hdf_status st = finish_build(f.get(), t0, s);
     if (st != HDF_OK) return st;
@@ -558,6 +631,7 @@ hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y
   std::vector<double> afull(hdf::kChebNodes);
   hdf::chebyshev_coeffs(kernel, D, lengthscale, hdf::kChebNodes, false, afull.data());
   f->p = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, HDF_MAX_DEGREE, &f->tail);
+  f->p_bound = f->p;
   if (f->p < 0) {
     int pp = hdf::choose_degree(afull.data(), hdf::kChebNodes, tol * f->nu / 2.0, hdf::kChebNodes - 2, nullptr);
     char buf[160];
@@ -590,6 +664,7 @@ hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y
   const double t_overlap = now_ms();
   hdf::radial_cores(f->a.data(), f->p, d, f->u0, f->u1, f->cores);
   f->tau = hdf::tau_threshold(tol, f->nu, std::sqrt((double)nx * (double)ny), d, f->p);
+  f->tau0 = f->tau;
   const double t_cores = now_ms() - t_overlap;
   HIPCHK(hipStreamSynchronize(s));
   f->t_plan += t_cores;
@@ -1028,6 +1103,10 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   }
   info->t_build_ms = h->t_build;
   info->n_refined = h->n_refined;
+  info->rank_rule = h->rank_rule;
+  info->tau_bound = h->tau0;
+  info->est_error = h->est_error;
+  info->degree_bound = h->p_bound;
   info->t_mv_t_ms = info->t_mv_reduce_ms = info->t_mv_n_ms = info->t_adjoint_ms = -1.0;
   if (h->adj_timed && hipEventSynchronize(h->ev_adj[1]) == hipSuccess) {
     float a = 0;

@@ -315,6 +315,43 @@ hipError_t launch_prep_cross(const void* ptsx, int64_t nx, int64_t ldx, const vo
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ sampled pairs
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_pairs(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n, int d,
+                                                const GeoDev* __restrict__ geo, uint64_t seed, int M,
+                                                double* __restrict__ out, int32_t* __restrict__ idx) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= M) return;
+  const int64_t a = (int64_t)((splitmix_at(seed, 2 * (uint64_t)t + 1) >> 11) % (uint64_t)n);
+  const int64_t b = (int64_t)((splitmix_at(seed, 2 * (uint64_t)t + 2) >> 11) % (uint64_t)n);
+  const double Reff = geo->Reff;
+  double r2 = 0.0, ra2 = 0.0, rb2 = 0.0, dot = 0.0;
+  for (int j = 0; j < d; ++j) {
+    const double xa = (double)x_soa[(int64_t)j * ldx + a], xb = (double)x_soa[(int64_t)j * ldx + b];
+    const double df = xa - xb;
+    const double ua = (xa - geo->c[j]) / Reff, ub = (xb - geo->c[j]) / Reff;
+    r2 += df * df;
+    ra2 += ua * ua;
+    rb2 += ub * ub;
+    dot += ua * ub;
+  }
+  out[t] = sqrt(r2);
+  out[M + t] = ra2;
+  out[2 * M + t] = rb2;
+  out[3 * M + t] = dot;
+  idx[t] = (int32_t)a;
+  idx[M + t] = (int32_t)b;
+}
+
+hipError_t launch_pairs(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                        uint64_t seed, int M, double* out, int32_t* idx, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((M + 255) / 256);
+  if (dtype == 0) k_pairs<float><<<nb, 256, 0, s>>>((const float*)x_soa, ldx, n, d, geo, seed, M, out, idx);
+  else k_pairs<double><<<nb, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, seed, M, out, idx);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Gram
 // Moments mu[k][c] = sum_i rho_i^{2k} T_c(t_i) as a tall-skinny product
 // A^T B on MFMA (A[i][k] = rho_i^{2k}, B[i][c] = T_c(t_i)).  The per-degree
@@ -472,13 +509,25 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
 }
 
 // Fixed-order sum over block partial records: out[e] = sum_b part[b][e].
-__global__ void k_gram_fin(const double* __restrict__ part, int nblk, int total,
-                           double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * total + e];
-  out[e] = s;
+// Fixed-order sum of the per-block partial records, out[e] = sum_b part[b][e].
+// A block owns 64 consecutive entries; wavefront w takes the records
+// b = w, w + 4, ... with eight independent running sums (loads in flight),
+// and the four wavefront sums are combined in a fixed order through LDS.
+__global__ void __launch_bounds__(256) k_gram_fin(const double* __restrict__ part, int nblk, int total,
+                                                   double* __restrict__ out) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int ee = e < total ? e : 0;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = w;
+  for (; b + 28 < nblk; b += 32)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += part[(int64_t)(b + 4 * u) * total + ee];
+  for (; b < nblk; b += 4) acc[0] += part[(int64_t)b * total + ee];
+  red[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (w == 0 && e < total) out[e] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 int gram_blocks(int64_t n) {
@@ -509,7 +558,7 @@ hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int
   }
 #undef GRAM_LAUNCH
   const int total = nrt * 16 * nct * 16;
-  k_gram_fin<<<(total + 255) / 256, 256, 0, s>>>(partials, nb, total, moments);
+  k_gram_fin<<<(total + 63) / 64, 256, 0, s>>>(partials, nb, total, moments);
   return hipGetLastError();
 }
 
@@ -631,7 +680,7 @@ hipError_t launch_gram2(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
     k_gram2<double><<<grid, 256, 0, s>>>((const double*)x_soa, ldx, n, d, geo, u0, u1, K, T1, t1_off, sel,
                                          n_sel, partials);
   const int total = n_sel * 1024;
-  k_gram_fin<<<(total + 255) / 256, 256, 0, s>>>(partials, nb, total, out);
+  k_gram_fin<<<(total + 63) / 64, 256, 0, s>>>(partials, nb, total, out);
   return hipGetLastError();
 }
 
@@ -1573,15 +1622,8 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
           }
         }
       };
-      load_batch(0, v_nxt);
-      for (int hb = 0; hb < dg.nh; hb += 4 * KB) {
-        T v[KB][4];
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) v[kb][u] = v_nxt[kb][u];
-        if (hb + 4 * KB < dg.nh) load_batch(hb + 4 * KB, v_nxt);
-        T bw[KB][NCT];
+      // B operands (rows of D W) of a batch, fetched together with its Phi rows
+      auto load_w = [&](int hb, T (&bb)[KB][NCT]) {
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           const int hh = hb + 4 * kb + g;
@@ -1590,8 +1632,25 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             const int l = l0 + ct;
-            bw[kb][ct] = (l < dg.s) ? wrow[(int64_t)l * m16] * hmask : (T)0;
+            bb[kb][ct] = (l < dg.s) ? wrow[(int64_t)(l < dg.s ? l : 0) * m16] * hmask : (T)0;
           }
+        }
+      };
+      T w_nxt[KB][NCT];
+      load_batch(0, v_nxt);
+      load_w(0, w_nxt);
+      for (int hb = 0; hb < dg.nh; hb += 4 * KB) {
+        T v[KB][4], bw[KB][NCT];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[kb][u] = v_nxt[kb][u];
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) bw[kb][ct] = w_nxt[kb][ct];
+        }
+        if (hb + 4 * KB < dg.nh) {
+          load_batch(hb + 4 * KB, v_nxt);
+          load_w(hb + 4 * KB, w_nxt);
         }
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {

@@ -31,6 +31,15 @@ hipError_t launch_prep_cross(const void* ptsx, int64_t nx, int64_t ldx, const vo
                              int64_t ldsy, int kernel, double l, double* partials, GeoDev* geo,
                              hipStream_t s);
 
+// Sampled pairs of the tighter degree and rank rules: pair t uses SplitMix64
+// outputs 2t+1 and 2t+2 of the stream `seed` (a = out >> 11 mod n, likewise
+// b).  out[0..M) = ||x_a - x_b||, out[M..2M) = rho_a^2, out[2M..3M) = rho_b^2,
+// out[3M..4M) = dot of the normalised points (x - c) / Reff; idx[0..M) = a,
+// idx[M..2M) = b.  Needs the geometry of launch_prep.
+constexpr uint64_t kPairSeed = 0x48444601ull;
+hipError_t launch_pairs(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                        uint64_t seed, int M, double* out, int32_t* idx, hipStream_t s);
+
 // Weighted Chebyshev moments mu[k][c] = sum_i rho_i^{2k} T_c(t_i), k <= K,
 // c <= 2K, written to `moments` (rows 16*nrt x cols 16*nct, binary64).
 // mode 0: binary64 MFMA; 1: binary32 MFMA; 2: binary32 hi/lo split MFMA.

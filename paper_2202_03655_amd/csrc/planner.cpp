@@ -32,6 +32,7 @@
 #include <mutex>
 #include <cstring>
 #include <stdexcept>
+#include <thread>
 
 namespace hdf {
 
@@ -766,4 +767,210 @@ void compress_degree_refined(int k, int L, const double* G2, const Precond& pc, 
   }
 }
 
+}  // namespace hdf
+
+namespace hdf {
+
+// ------------------------------------------------------------------ sampled rules
+namespace {
+
+// Stratified relative Frobenius error from the off-diagonal sums of squares
+// (errors and values over n_off pairs) and the diagonal ones (over n_d points).
+double stratified(double N, double e_off, double k_off, int n_off, double e_d, double k_d, int n_d) {
+  const double w_off = N * (N - 1.0), w_d = N;
+  double num = w_d * e_d / n_d, den = w_d * k_d / n_d;
+  if (n_off > 0) {
+    num += w_off * e_off / n_off;
+    den += w_off * k_off / n_off;
+  }
+  return std::sqrt(num / den);
+}
+
+}  // namespace
+
+int choose_degree_sampled(int kind, double l, const double* a, int n_coef, double D, double N,
+                          const PairSample& ps, double eps, int p_max, int p_hint) {
+  // the budget rule's degree bounds the answer in exact arithmetic (a max-norm
+  // tail <= eps nu / 2 gives a Frobenius truncation error <= eps / 2): scan up
+  // to it first, and on to p_max only if no degree qualifies there
+  if (p_hint >= 0 && p_hint < p_max) {
+    const int p = choose_degree_sampled(kind, l, a, n_coef, D, N, ps, eps, p_hint, -1);
+    if (p >= 0) return p;
+  }
+  const int M = (int)ps.r.size();
+  const int top = std::min(p_max, n_coef - 1);
+  // e_off[p] = sum over off-diagonal pairs of (k - S_p)^2 for every p <= top
+  std::vector<double> e_off(top + 1, 0.0);
+  double k_off = 0.0;
+  int n_off = 0;
+  for (int t = 0; t < M; ++t) {
+    if (ps.a[t] == ps.b[t]) continue;
+    ++n_off;
+    const double kv = kernel_value(kind, ps.r[t], l), s = ps.r[t] / D;
+    k_off += kv * kv;
+    double Tm = 1.0, T = s, S = a[0];
+    e_off[0] += (kv - S) * (kv - S);
+    for (int p = 1; p <= top; ++p) {
+      if (p >= 2) {
+        const double Tn = 2.0 * s * T - Tm;
+        Tm = T;
+        T = Tn;
+      }
+      S += a[p] * T;
+      e_off[p] += (kv - S) * (kv - S);
+    }
+  }
+  // diagonal: s = 0, T_i(0) = 1, 0, -1, 0, 1, ...
+  const double k0 = kernel_value(kind, 0.0, l);
+  double S0 = 0.0;
+  for (int p = 0; p <= top; ++p) {
+    S0 += a[p] * ((p % 2) ? 0.0 : ((p / 2) % 2 ? -1.0 : 1.0));
+    if (p % 2) continue;
+    const double e_d = (k0 - S0) * (k0 - S0) * M, k_d = k0 * k0 * M;
+    if (stratified(N, e_off[p], k_off, n_off, e_d, k_d, M) <= eps / 2.0) return p;
+  }
+  return -1;
+}
+
+double tune_threshold(int kind, double l, int d, double N, double u0, double u1,
+                      const std::vector<DegreeFactor>& deg, const PairSample& ps, double eps,
+                      double margin, double tau0, double* err) {
+  const int M = (int)ps.r.size();
+  const int K = (int)deg.size() - 1;
+  const double alpha = 0.5 * d - 1.0;
+  const double area = sphere_area(d);
+  // eigenpairs kept at tau0, in (k, l) order
+  std::vector<int> pk, pl;
+  std::vector<double> plam;
+  for (int k = 0; k <= K; ++k)
+    for (int li = 0; li < deg[k].s; ++li) { pk.push_back(k); pl.push_back(li); plam.push_back(deg[k].lam[li]); }
+  const int J = (int)pk.size();
+  std::vector<double> c1(K + 1, 1.0), hk(K + 1);      // C_k^alpha(1), |H_k| / |S^{d-1}|
+  for (int k = 1; k <= K; ++k) c1[k] = c1[k - 1] * (k + 2.0 * alpha - 1.0) / k;
+  for (int k = 0; k <= K; ++k) hk[k] = (double)index_count(d, k) / area;
+  std::vector<int> off;
+  for (int t = 0; t < M; ++t)
+    if (ps.a[t] != ps.b[t]) off.push_back(t);
+  const int n_off = (int)off.size();
+  const int rows = n_off + M;                          // off-diagonal pairs, then diagonal points
+  const double k0 = kernel_value(kind, 0.0, l);
+  // Dropping a set S of eigenpairs turns the residual r0 = k - K~ of a row
+  // into r0 + sum_{j in S} c_j, so per stratum the squared error is
+  //   sum r0^2 + 2 sum_{j in S} b_j + sum_{j, j' in S} G_jj',
+  // b_j = sum r0 c_j, G = C^T C: one pass over the rows accumulates them.
+  struct Acc {
+    std::vector<double> G[2], b[2];
+    double r2[2] = {0, 0}, k2[2] = {0, 0};
+  };
+  auto accumulate = [&](int r0, int r1, Acc& A) {
+    for (int st = 0; st < 2; ++st) { A.G[st].assign((size_t)J * J, 0.0); A.b[st].assign(J, 0.0); }
+    const int Lmax = K + 1;
+    std::vector<double> Ta(Lmax), Tb(Lmax), G(K + 1), cj(J);
+    for (int row = r0; row < r1; ++row) {
+      double ra2, rb2, dot, kv;
+      int st;
+      if (row < n_off) {
+        const int t = off[row];
+        ra2 = ps.ra2[t]; rb2 = ps.rb2[t]; dot = ps.dot[t];
+        kv = kernel_value(kind, ps.r[t], l);
+        st = 0;
+      } else {
+        ra2 = rb2 = dot = ps.ra2[row - n_off];
+        kv = k0;
+        st = 1;
+      }
+      const double ta = (2.0 * ra2 - u0 - u1) / (u1 - u0), tb = (2.0 * rb2 - u0 - u1) / (u1 - u0);
+      Ta[0] = Tb[0] = 1.0;
+      if (Lmax > 1) { Ta[1] = ta; Tb[1] = tb; }
+      for (int q = 2; q < Lmax; ++q) { Ta[q] = 2.0 * ta * Ta[q - 1] - Ta[q - 2]; Tb[q] = 2.0 * tb * Tb[q - 1] - Tb[q - 2]; }
+      // (rho_a rho_b)^k C_k^alpha(cos): solid Gegenbauer recurrence in dot and rho_a^2 rho_b^2
+      const double rr = ra2 * rb2;
+      G[0] = 1.0;
+      if (K >= 1) G[1] = 2.0 * alpha * dot;
+      for (int k = 2; k <= K; ++k)
+        G[k] = (2.0 * (k + alpha - 1.0) * dot * G[k - 1] - (k + 2.0 * alpha - 2.0) * rr * G[k - 2]) / k;
+      double kt = 0.0;
+      for (int j = 0; j < J; ++j) {
+        const DegreeFactor& df = deg[pk[j]];
+        const double* e = df.E.data() + (size_t)pl[j] * df.L;
+        double qa = 0.0, qb = 0.0;
+        for (int q = 0; q < df.L; ++q) { qa += Ta[q] * e[q]; qb += Tb[q] * e[q]; }
+        cj[j] = plam[j] * hk[pk[j]] * G[pk[j]] / c1[pk[j]] * qa * qb;
+        kt += cj[j];
+      }
+      const double r = kv - kt;
+      A.r2[st] += r * r;
+      A.k2[st] += kv * kv;
+      double* Gs = A.G[st].data();
+      double* bs = A.b[st].data();
+      for (int j = 0; j < J; ++j) {
+        bs[j] += r * cj[j];
+        const double v = cj[j];
+        for (int jj = 0; jj <= j; ++jj) Gs[(size_t)j * J + jj] += v * cj[jj];
+      }
+    }
+  };
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<Acc> acc(nth);
+  {
+    const int per = (rows + nth - 1) / nth;
+    std::vector<std::thread> th;
+    for (int i = 0; i < nth; ++i) {
+      const int r0 = std::min(rows, i * per), r1 = std::min(rows, r0 + per);
+      th.emplace_back(accumulate, r0, r1, std::ref(acc[i]));
+    }
+    for (auto& x : th) x.join();
+  }
+  // fixed-order combination of the thread partials; G symmetric from its lower triangle
+  Acc tot;
+  for (int st = 0; st < 2; ++st) { tot.G[st].assign((size_t)J * J, 0.0); tot.b[st].assign(J, 0.0); }
+  for (const Acc& A : acc)
+    for (int st = 0; st < 2; ++st) {
+      tot.r2[st] += A.r2[st];
+      tot.k2[st] += A.k2[st];
+      for (size_t i = 0; i < tot.G[st].size(); ++i) tot.G[st][i] += A.G[st][i];
+      for (int j = 0; j < J; ++j) tot.b[st][j] += A.b[st][j];
+    }
+  for (int st = 0; st < 2; ++st)
+    for (int j = 0; j < J; ++j)
+      for (int jj = 0; jj < j; ++jj) tot.G[st][(size_t)jj * J + j] = tot.G[st][(size_t)j * J + jj];
+  std::vector<char> dropped(J, 0);
+  auto error_with = [&](const std::vector<int>& extra) {
+    double e2[2];
+    for (int st = 0; st < 2; ++st) {
+      const std::vector<double>& Gs = tot.G[st];
+      double v = tot.r2[st];
+      std::vector<int> S;
+      for (int j = 0; j < J; ++j)
+        if (dropped[j]) S.push_back(j);
+      S.insert(S.end(), extra.begin(), extra.end());
+      for (int j : S) v += 2.0 * tot.b[st][j];
+      for (int j : S)
+        for (int jj : S) v += Gs[(size_t)j * J + jj];
+      e2[st] = std::max(v, 0.0);
+    }
+    return stratified(N, e2[0], tot.k2[0], n_off, e2[1], tot.k2[1], M);
+  };
+  double e = error_with({}), tau = tau0;
+  if (e <= margin * eps && J > 0) {
+    std::vector<double> mags(J);
+    for (int j = 0; j < J; ++j) mags[j] = std::fabs(plam[j]);
+    std::vector<double> levels(mags);
+    std::sort(levels.begin(), levels.end());
+    levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
+    std::vector<int> cols;
+    for (double m : levels) {                    // ascending |lambda|, equal |lambda| together
+      cols.clear();
+      for (int j = 0; j < J; ++j)
+        if (mags[j] == m) cols.push_back(j);
+      const double e2 = error_with(cols);
+      if (e2 > margin * eps) break;
+      for (int j : cols) dropped[j] = 1;
+      e = e2;
+      tau = std::max(tau, m);
+    }
+  }
+  if (err) *err = e;
+  return tau;
+}
 }  // namespace hdf

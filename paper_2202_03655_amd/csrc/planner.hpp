@@ -90,6 +90,29 @@ void compress_degree_cross(int k, int L, const SqrtFactor& fx, const SqrtFactor&
 // the side of the kernel matrix (sqrt(N_x N_y) for a rectangular one).
 double tau_threshold(double tol, double nu, double N, int d, int p);
 
+// Tighter degree and rank selection (remark after Eq. bound).  The relative
+// Frobenius error is estimated from M sampled pairs, stratified into the
+// off-diagonal pairs (a != b) and the diagonal at the pairs' first points:
+//   ||E||^2 ~ N (N-1) mean_off e^2 + N mean_diag e^2, the same for ||K||^2.
+// Per pair (device, launch_pairs): r = ||x_a - x_b||, rho^2 of both
+// normalised points, their dot product, and the indices a, b.
+struct PairSample {
+  std::vector<double> r, ra2, rb2, dot;
+  std::vector<int32_t> a, b;
+};
+// Smallest even p <= p_max whose sampled truncation error (kernel vs its
+// degree-p Chebyshev expansion on [0, D]) is <= eps / 2; -1 if none.  p_hint
+// (the budget rule's degree, or -1) only shortens the scan.
+int choose_degree_sampled(int kind, double l, const double* a, int n_coef, double D, double N,
+                          const PairSample& ps, double eps, int p_max, int p_hint);
+// From the factor kept at tau0 (deg[k].lam ordered by |lambda| descending),
+// drop eigenpairs in increasing |lambda| (equal |lambda| together) while the
+// sampled error of U D U^T stays <= margin * eps.  Returns tau >= tau0 (kept:
+// |lambda| > tau) and the final estimate in *err.
+double tune_threshold(int kind, double l, int d, double N, double u0, double u1,
+                      const std::vector<DegreeFactor>& deg, const PairSample& ps, double eps,
+                      double margin, double tau0, double* err);
+
 // Normalised Gegenbauer chain recurrences of the solid harmonics.
 //   level j = 1..d-2 (coordinate x_j, partial radius r_j^2), lower index b:
 //   P_0 = c0, P_1 = c1 * x, P_{n+1} = A_n x P_n - B_n r^2 P_{n-1}.

@@ -19,7 +19,7 @@ HDF_MAX_DEGREE = 60
 STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
           -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP", -7: "HDF_E_DISABLED"}
 
-EXPORTS = ["hdf_build", "hdf_build_cross", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
+EXPORTS = ["hdf_build", "hdf_build_ex", "hdf_build_cross", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
            "hdf_copy_factor", "hdf_copy_factor_y", "hdf_free", "hdf_status_string", "hdf_last_error",
            "hdf_plan_chebyshev", "hdf_plan_degree", "hdf_plan_cores", "hdf_plan_index_set",
            "hdf_plan_compress_cross"]
@@ -41,7 +41,16 @@ class HDFInfo(ctypes.Structure):
         ("t_adjoint_ms", ctypes.c_double),
         ("n_refined", ctypes.c_int32),
         ("s_k", ctypes.c_int32 * (HDF_MAX_DEGREE // 2 + 1)),
+        ("rank_rule", ctypes.c_int32), ("tau_bound", ctypes.c_double), ("est_error", ctypes.c_double),
+        ("degree_bound", ctypes.c_int32),
     ]
+
+
+class BuildOptions(ctypes.Structure):
+    _fields_ = [("rank_rule", ctypes.c_int32), ("n_pairs", ctypes.c_int32), ("margin", ctypes.c_double)]
+
+
+RANK_RULES = {"bound": 0, "sampled": 1}
 
 
 class HDFError(RuntimeError):
@@ -62,6 +71,8 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.hdf_build.argtypes = [vp, i32, i64, i32, i64, i32, dbl, dbl, i32, vp, ctypes.POINTER(vp)]
+    L.hdf_build_ex.argtypes = [vp, i32, i64, i32, i64, i32, dbl, dbl, i32, ctypes.POINTER(BuildOptions), vp,
+                               ctypes.POINTER(vp)]
     L.hdf_build_cross.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, dbl, dbl, i32, vp,
                                   ctypes.POINTER(vp)]
     L.hdf_copy_factor_y.argtypes = [vp, vp, i64, vp, i64, vp]
@@ -112,7 +123,11 @@ def _dev2d(t, dtype, name):
 class Factor:
     """Handle of a built HDF factor K ~ U D U^T (owns the library handle)."""
 
-    def __init__(self, X, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None):
+    def __init__(self, X, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None, rank_rule="bound",
+                 n_pairs=0, margin=0.0):
+        """rank_rule "bound": p and tau from the a-priori budget (Sec. 3.5); "sampled": the tighter
+        rule of the remark after Eq. bound (n_pairs sampled pairs, error kept <= margin * tol;
+        0 selects the library defaults)."""
         L = lib()
         if precision is None:
             precision = HDF_FP64 if X.dtype == torch.float64 else HDF_MIXED
@@ -126,10 +141,11 @@ class Factor:
         self.tol = float(tol)
         self.device = X.device
         h = ctypes.c_void_p()
+        opts = BuildOptions(RANK_RULES[rank_rule], int(n_pairs), float(margin))
         with torch.cuda.device(X.device):
-            _check(L.hdf_build(X.data_ptr(), 0 if dtype == torch.float32 else 1, self.n, self.d,
-                               X.stride(0), KERNELS[kernel], self.lengthscale, self.tol,
-                               precision, _stream(), ctypes.byref(h)))
+            _check(L.hdf_build_ex(X.data_ptr(), 0 if dtype == torch.float32 else 1, self.n, self.d,
+                                  X.stride(0), KERNELS[kernel], self.lengthscale, self.tol,
+                                  precision, ctypes.byref(opts), _stream(), ctypes.byref(h)))
         self._h = h
 
     def __del__(self):

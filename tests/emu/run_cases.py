@@ -19,7 +19,7 @@ import torch
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import cross, hdf as ohdf  # noqa: E402
+from oracle import adaptive, cross, dense, hdf as ohdf  # noqa: E402
 from paper_2202_03655_amd import hdf, workloads as wl  # noqa: E402
 
 LIB = sys.argv[1]
@@ -166,7 +166,32 @@ def case_tiny():
         check(f"tiny n={n}", e <= 1e-12, f"{e:.2e}")
 
 
-CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny}
+def case_sampled():
+    """Tighter degree and rank rule (binary64): degree, ranks, threshold and estimate against the
+    oracle's, K~V against the oracle state and the factor against the dense K."""
+    X = wl.uniform_cube(1200, 4, 104)
+    st = adaptive.build_sampled(X, "gaussian", 0.7, 1e-4)
+    f = hdf.Factor(to_dev(X, torch.float64), "gaussian", 0.7, 1e-4, precision=hdf.HDF_FP64, rank_rule="sampled")
+    inf = f.info()
+    s_o = [dd["s"] for dd in st["deg"]]
+    check("sampled degree", inf["degree_p"] == st["p"] and inf["degree_bound"] == st["p_bound"],
+          f"{inf['degree_p']}/{inf['degree_bound']} vs {st['p']}/{st['p_bound']}")
+    check("sampled ranks", inf["s_k"] == s_o, f"{inf['s_k']} vs {s_o}")
+    check("sampled tau", abs(inf["tau"] / st["tau"] - 1) < 1e-9 and abs(inf["tau_bound"] / st["tau0"] - 1) < 1e-12,
+          f"{inf['tau']:.6e}/{inf['tau_bound']:.6e} vs {st['tau']:.6e}/{st['tau0']:.6e}")
+    check("sampled estimate", abs(inf["est_error"] / st["est_error"] - 1) < 1e-6,
+          f"{inf['est_error']:.6e} vs {st['est_error']:.6e}")
+    V = wl.rhs(1200, 2, 5)
+    e = rel(f.matvec(to_dev(V, torch.float64)).numpy(), ohdf.matvec(st, V))
+    check("sampled matvec", e <= 1e-12, f"{e:.2e}")
+    K = dense.dense_K(X, "gaussian", 0.7)
+    E = torch.eye(1200, dtype=torch.float64)[:, :256].numpy()
+    Kt = f.matvec(to_dev(E, torch.float64)).numpy()
+    e = rel(Kt, K[:, :256])
+    check("sampled guarantee", e <= 1e-4, f"{e:.2e} (rank {inf['rank']}, bound rule {ohdf.build(X, 'gaussian', 0.7, 1e-4)['r']})")
+
+
+CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled}
 
 if __name__ == "__main__":
     _install()
