@@ -47,6 +47,44 @@ def shell(n, d, seed, r0=0.9, r1=1.1):
     return g / np.linalg.norm(g, axis=1)[:, None] * rng.uniform(r0, r1, size=n)[:, None]
 
 
+def housing_like(n, seed):
+    """Tabular cloud in d = 8 shaped like the California Housing features of Sec. 4.2 (not available
+    here): a skewed income, a uniform age, three log-normal counts and a ratio, and two clustered
+    location coordinates (six centres); every feature min-max scaled to [0, 1] as the paper does."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-1.0, 1.0, size=(6, 2))
+    loc = centres[rng.integers(0, 6, n)] + 0.15 * rng.normal(size=(n, 2))
+    inc = rng.lognormal(1.2, 0.45, n)
+    age = rng.uniform(1.0, 52.0, n)
+    rooms = rng.lognormal(1.6, 0.25, n)
+    beds = rooms * rng.uniform(0.15, 0.25, n)
+    pop = rng.lognormal(7.0, 0.7, n)
+    occ = rng.lognormal(1.0, 0.3, n)
+    F = np.column_stack([inc, age, rooms, beds, pop, occ, loc])
+    return (F - F.min(axis=0)) / (F.max(axis=0) - F.min(axis=0))
+
+
+def housing_labels(F, seed):
+    """Smooth response of the features plus N(0, 0.05^2) noise."""
+    noise = np.random.default_rng(seed).normal(scale=0.05, size=len(F))
+    return (np.sin(3.0 * F[:, 0] + 2.0 * F[:, 6]) + F[:, 1] * F[:, 7] - 2.0 * (F[:, 2] - 0.2) ** 2 + noise)
+
+
+def housing_split(n, seed=11, n_points=20640):
+    """Seeded shuffle and the 2/3 - 1/3 train/test split of Sec. 4.2: (X_train, y_train, X_test,
+    y_test) from the first n of n_points (n = n_points: the full set)."""
+    F_all = housing_like(n_points, seed)
+    F, y = F_all[:n], housing_labels(F_all, seed + 1)[:n]
+    order = np.random.default_rng(seed + 2).permutation(n)
+    ntr = 2 * n // 3
+    return F[order[:ntr]], y[order[:ntr]], F[order[ntr:]], y[order[ntr:]]
+
+
+# KRR consumer (Sec. 4.2): clusters, kernel, lengthscale, block tol, lambda, CG rtol and limit
+KRR = dict(n=20640, d=8, clusters=30, kernel="gaussian", l=0.5, tol=1e-4, lam=0.1, rtol=1e-6, max_iter=1024,
+           kmeans_iter=100)
+
+
 def rhs(n, m, seed):
     return np.random.default_rng(seed).normal(size=(n, m))
 
