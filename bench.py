@@ -198,6 +198,103 @@ def cpu_baseline(wname, X, V, n_sample):
                        f"matvec {t2 - t1:.2f}s, rank {st['r']}")
 
 
+# fp64 VALU lane-instructions per (i, j) pair in the inner loop of the off-diagonal kernel
+# k_kmv<8, Gaussian, masked> (AMD assembly of this build, loop unrolled by 4: 140 fp64 + 36 other VALU
+# instructions per 4 pairs); the VALU issue peak is 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+KMV_VALU_PER_PAIR = 44.0
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def run_krr(steps):
+    """KRR consumer (Sec. 4.2) on the housing-shaped d = 8 workload: k-means, the system with HDF diagonal
+    blocks and its preconditioner, PCG to rtol, predictions; everything resident on the device."""
+    import numpy as np
+    import torch
+    from paper_2202_03655_amd import hdf, workloads as wl
+    c = wl.KRR
+    Xtr, ytr, Xte, yte = wl.housing_split(c["n"])
+    Xd = torch.tensor(Xtr, device="cuda")
+    yd = torch.tensor(ytr, device="cuda")
+    Xq = torch.tensor(Xte, device="cuda")
+
+    def fit_predict():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lab, _, its = hdf.kmeans(Xd, c["clusters"], max_iter=c["kmeans_iter"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sysm = hdf.KRR(Xd, lab, c["clusters"], c["kernel"], c["l"], c["tol"], c["lam"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        w, it, rr = sysm.solve(yd, c["max_iter"], c["rtol"])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        pred = hdf.kernel_matvec(Xq, Xd, w, c["kernel"], c["l"])
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        return dict(kmeans=t1 - t0, create=t2 - t1, solve=t3 - t2, predict=t4 - t3, its=its, it=it, rr=rr,
+                    sysm=sysm, w=w, pred=pred, lab=lab)
+
+    fit_predict()
+    runs = [fit_predict() for _ in range(max(1, steps))]
+    med = {k: float(np.median([r[k] for r in runs])) * 1e3 for k in ("kmeans", "create", "solve", "predict")}
+    last = runs[-1]
+    sysm, inf = last["sysm"], last["sysm"].info()
+    # off-diagonal kernel: HIP events around its launch inside hdf_krr_apply
+    v = torch.randn(len(Xtr), dtype=torch.float64, device="cuda")
+    od = []
+    for _ in range(10):
+        sysm.apply(v)
+        od.append(sysm.info()["t_offdiag_ms"])
+    od_ms = float(np.mean(od[2:]))
+    n = len(Xtr)
+    sizes = np.bincount(last["lab"].cpu().numpy(), minlength=c["clusters"])
+    pairs = float(n) * n - float((sizes.astype(np.float64) ** 2).sum())
+    evals = float(n) * n            # the kernel evaluates every pair and masks the own cluster
+    achieved = evals / (od_ms * 1e-3)
+    peak = VALU_PEAK_LANE_OPS / KMV_VALU_PER_PAIR
+    mse = float(((last["pred"].cpu().numpy() - yte) ** 2).mean())
+    fit = med["kmeans"] + med["create"] + med["solve"]
+    return {
+        "workload": f"housing8_krr: N={c['n']} d=8 housing-shaped cloud, {n} train / {len(Xte)} test, "
+                    f"{c['clusters']} k-means clusters, {c['kernel']} l={c['l']}, block tol {c['tol']}, "
+                    f"lambda {c['lam']}, PCG to rtol {c['rtol']} (max {c['max_iter']})",
+        "fit_ms": round(fit, 2), "fit_predict_ms": round(fit + med["predict"], 2),
+        "phases_ms": {k: round(v, 2) for k, v in med.items()},
+        "create_ms": {"factors": round(inf["t_factor_ms"], 2), "precond": round(inf["t_precond_ms"], 2)},
+        "kmeans_iterations": last["its"], "cg_iterations": last["it"], "relres": last["rr"],
+        "ms_per_cg_iteration": round(med["solve"] / max(1, last["it"]), 4),
+        "test_mse": mse, "label_var": float(np.var(yte)),
+        "blocks": {"n": inf["n_blocks"], "max": inf["max_block"], "max_degree": inf["max_degree"],
+                   "sum_rank": inf["sum_rank"], "factor_bytes": inf["factor_bytes"],
+                   "precond_bytes": inf["precond_bytes"]},
+        "offdiag_kernel": {"ms": round(od_ms, 4), "pair_evals": evals, "offdiag_pairs": pairs,
+                           "roofline": {"kernel": "k_kmv", "bound": "alu", "achieved": round(achieved / 1e9, 1),
+                                        "peak": round(peak / 1e9, 1), "unit": "Gpair/s",
+                                        "frac": round(achieved / peak, 4),
+                                        "valu_per_pair": KMV_VALU_PER_PAIR}},
+        "_state": (Xtr, ytr, last["lab"].cpu().numpy()),
+    }
+
+
+def krr_cpu_baseline(Xtr, ytr, labels):
+    """The oracle on the same system: block factors and preconditioner, then two CG iterations."""
+    import numpy as np
+    from oracle import krr
+    from paper_2202_03655_amd import workloads as wl
+    c = wl.KRR
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    S = krr.create(Xtr, labels, c["clusters"], c["kernel"], c["l"], c["tol"], c["lam"])
+    t1 = time.perf_counter()
+    krr.solve(S, ytr, 0.0, 2)
+    t2 = time.perf_counter()
+    return dict(value=round((t2 - t1) / 2 * 1e3, 1), unit="ms per CG iteration", cores=cores, kind="oracle",
+                create_ms=round((t1 - t0) * 1e3, 1),
+                sample="the full housing8_krr system (same labels): oracle block factors + Cholesky "
+                       "preconditioner, then 2 PCG iterations")
+
+
 def calibrate_copy(nbytes):
     """Plain device copy of known size, used to scale the PMC byte counters."""
     import torch
@@ -225,6 +322,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--no-krr", action="store_true", help="skip the KRR consumer (Sec. 4.2)")
+    ap.add_argument("--krr-only", action="store_true",
+                    help="run only the KRR consumer and print its JSON object (for profiling)")
     ap.add_argument("--cross", type=int, default=0, metavar="NQ",
                     help="also time the general factor K(X*, X) (X* = NQ query points) and its product")
     args = ap.parse_args()
@@ -240,6 +340,11 @@ def main():
         return
     from paper_2202_03655_amd import hdf, workloads
     hdf.lib()
+    if args.krr_only:
+        kr = run_krr(max(1, args.steps))
+        kr.pop("_state")
+        print(json.dumps({"krr": kr}), flush=True)
+        return
     cfg = workloads.CONFIGS[args.workload]
     X = workloads.points(args.workload)
     if args.precision == "mixed":
@@ -323,6 +428,15 @@ def main():
                                "est_error": si["est_error"]}
     if args.cross:
         out["cross"] = run_cross(args.workload, X, args.cross, m, args.precision, args.steps, args.warmup)
+    if not args.no_krr:
+        kr = run_krr(max(1, args.steps // 2))
+        state = kr.pop("_state")
+        print(f"# krr fit {kr['fit_ms']} ms {kr['phases_ms']}, {kr['cg_iterations']} CG iterations "
+              f"({kr['ms_per_cg_iteration']} ms each), off-diagonal kernel {kr['offdiag_kernel']['ms']} ms",
+              file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            kr["cpu_baseline"] = krr_cpu_baseline(*state)
+        out["krr"] = kr
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, X, V, min(args.cpu_sample, N))
     print(json.dumps(out), flush=True)

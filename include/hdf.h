@@ -266,6 +266,107 @@ hdf_status hdf_plan_index_set(int d, int k, int32_t* table, int64_t* count);
 hdf_status hdf_plan_compress_cross(int L, const double* Gx, const double* Gy, const double* M, double tau,
                                    double null_rel, int32_t* s, double* sig, double* Ex, double* Ey);
 
+/* ---- Kernel ridge regression consumer (Sec. 4.2).  All binary64.  The
+ * weights solve (lambda I + K) w = y (Eq. opt) by preconditioned conjugate
+ * gradients; the diagonal blocks of K, one per k-means cluster, are HDF
+ * factors (hdf_build, HDF_FP64), the off-diagonal blocks are exact kernel
+ * values, and the preconditioner is block diagonal with the exact inverses
+ * of the blocks lambda I + K_{C_i C_i}.  Predictions are K(x*, x) w
+ * (hdf_kernel_matvec). ---- */
+
+typedef struct hdf_krr* hdf_krr_handle;     /* opaque, owned by the library */
+
+#define HDF_MAX_CLUSTERS 256
+
+/* Lloyd's k-means (the clustering of Sec. 4.2).
+ *   points    device float64, n x d (ld >= d), 1 <= d <= HDF_MAX_DIM.
+ *   k         1 <= k <= min(n, HDF_MAX_CLUSTERS); max_iter >= 1.
+ *   seed      the k initial centres are distinct points, index
+ *             (u >> 11) mod n of successive SplitMix64 outputs u from this
+ *             seed, a repeated index skipped.
+ *   labels    device int32, n: the cluster of every point.
+ *   centres   device float64, k x d (row-major, leading dimension d).
+ *   iterations host (may be NULL): assignments made.
+ * A point goes to the centre of smallest sum_j (x_j - c_j)^2 (no fused
+ * multiply-add, coordinates in order), ties to the lower index; a centre
+ * becomes the mean of its members, an empty cluster keeps its centre; the
+ * iteration stops at the first assignment that changes no label, or after
+ * max_iter assignments.  One blocking synchronisation per assignment. */
+hdf_status hdf_kmeans(const double* points, int64_t n, int d, int64_t ld, int k, int max_iter,
+                      uint64_t seed, int32_t* labels, double* centres, int* iterations,
+                      void* hip_stream);
+
+/* out = K(X, Y) w with exact kernel values (the prediction K(x*, x) w of
+ * Sec. 4.2).  x device nx x d (ldx >= d), y device ny x d (ldy >= d),
+ * 1 <= d <= HDF_MAX_DIM, w device ny, out device nx (must not overlap w).
+ * Fixed summation order: the same inputs give the same bits. */
+hdf_status hdf_kernel_matvec(const double* x, int64_t nx, int64_t ldx, const double* y, int64_t ny,
+                             int64_t ldy, int d, hdf_kernel kernel, double lengthscale,
+                             const double* w, double* out, void* hip_stream);
+
+/* Build the KRR system for points with cluster labels (e.g. from
+ * hdf_kmeans).
+ *   points  device float64, n x d (ld >= d), 3 <= d <= HDF_MAX_DIM.
+ *   labels  device int32, n, each in [0, k); 1 <= k <= HDF_MAX_CLUSTERS.
+ *   tol     tolerance of every diagonal-block factor (hdf_build).
+ *   lambda  regularisation, > 0.
+ * Blocking: labels are read back, and each block factor synchronises as
+ * hdf_build does.  HDF_E_ARG for a label out of range or a cluster larger
+ * than 16384 points; HDF_E_INFEASIBLE when a block factor is, or when a
+ * preconditioner block is not numerically positive definite. */
+hdf_status hdf_krr_create(const double* points, int64_t n, int d, int64_t ld, const int32_t* labels,
+                          int k, hdf_kernel kernel, double lengthscale, double tol, double lambda,
+                          void* hip_stream, hdf_krr_handle* out);
+
+/* out = (lambda I + blockdiag(U_i D_i U_i^T) + offdiag(K)) v: the system
+ * operator.  v, out device float64, n, in the caller's point order; they
+ * must not overlap.  No host synchronisation. */
+hdf_status hdf_krr_apply(hdf_krr_handle h, const double* v, double* out, void* hip_stream);
+
+/* z = blockdiag((lambda I + K_{C_i C_i})^{-1}) r: the preconditioner.  r, z
+ * device float64, n, caller's order, not overlapping.  No synchronisation. */
+hdf_status hdf_krr_precond(hdf_krr_handle h, const double* r, double* z, void* hip_stream);
+
+/* Preconditioned CG from w = 0 (Saad, Alg. 9.1), stopped at the first
+ * iteration whose recursive residual satisfies ||r|| <= rtol ||y||, or after
+ * max_iter iterations.
+ *   y, w       device float64, n, caller's order, not overlapping.
+ *   iterations host (may be NULL): iterations made (0 when y = 0).
+ *   relres     host (may be NULL): ||r|| / ||y|| at the end.
+ * The iterations run on the device, scalars included; the host reads the
+ * convergence flag once per batch of 8 iterations (one synchronisation per
+ * batch).  Iterations enqueued after convergence leave w unchanged. */
+hdf_status hdf_krr_solve(hdf_krr_handle h, const double* y, double* w, int max_iter, double rtol,
+                         int* iterations, double* relres, void* hip_stream);
+
+typedef struct {
+  int64_t n_points;
+  int32_t n_dim, n_clusters;       /* k as given                               */
+  int32_t n_blocks;                /* non-empty clusters                       */
+  int32_t max_block;               /* largest cluster                          */
+  int32_t max_degree;              /* largest Chebyshev degree over the blocks */
+  int64_t sum_rank;                /* sum of the block ranks                   */
+  int64_t factor_bytes;            /* device bytes of the block factors        */
+  int64_t precond_bytes;           /* device bytes of the inverse blocks       */
+  double  t_factor_ms;             /* host wall: block factors (hdf_build)     */
+  double  t_precond_ms;            /* host wall: dense blocks, Cholesky,
+                                      inverses (incl. their synchronisation)  */
+  double  t_offdiag_ms;            /* last operator application: off-diagonal
+                                      kernel (HIP events)                      */
+  double  t_solve_ms;              /* last hdf_krr_solve (HIP events)          */
+  int32_t last_iterations;
+  double  last_relres;
+} hdf_krr_info_t;
+
+hdf_status hdf_krr_info(hdf_krr_handle h, hdf_krr_info_t* info);
+
+/* The factor of cluster c (NULL for an empty cluster), owned by the KRR
+ * handle; usable with hdf_info, hdf_get_plan, hdf_copy_factor and
+ * hdf_matvec (its points are the members of c in increasing caller index). */
+hdf_status hdf_krr_block(hdf_krr_handle h, int c, hdf_handle* block);
+
+void hdf_krr_free(hdf_krr_handle h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,6 +27,7 @@ off-diagonal blocks, Cholesky solves for the preconditioner.
 """
 import numpy as np
 from scipy.linalg import cho_factor, cho_solve
+from scipy.spatial.distance import cdist
 
 from . import hdf, splitmix
 from .kernels import kappa
@@ -101,20 +102,20 @@ def create(X, labels, k, kernel, l, tol, lam):
             continue
         Xc = X[idx]
         st = hdf.build(Xc, kernel, l, tol)
-        B = kappa(kernel, np.sqrt(((Xc[:, None, :] - Xc[None, :, :]) ** 2).sum(-1)), l) + lam * np.eye(len(idx))
+        B = kappa(kernel, cdist(Xc, Xc), l) + lam * np.eye(len(idx))
         blocks.append(dict(idx=idx, st=st, chol=cho_factor(B, lower=True)))
     return dict(X=X, labels=np.asarray(labels), k=k, kernel=kernel, l=l, tol=tol, lam=lam,
                 perm=perm, offsets=offsets, blocks=blocks)
 
 
-def offdiag_apply(S, v, rows=None, chunk=256):
+def offdiag_apply(S, v, rows=None, chunk=1024):
     """sum over j outside the cluster of i of k(||x_i - x_j||) v_j, for the given rows (all if None)."""
     X, lab = S["X"], S["labels"]
     rows = np.arange(len(X)) if rows is None else np.asarray(rows)
     out = np.zeros(len(rows))
     for s in range(0, len(rows), chunk):
         r = rows[s:s + chunk]
-        Kr = kappa(S["kernel"], np.sqrt(((X[r][:, None, :] - X[None, :, :]) ** 2).sum(-1)), S["l"])
+        Kr = kappa(S["kernel"], cdist(X[r], X), S["l"])
         Kr[lab[r][:, None] == lab[None, :]] = 0.0
         out[s:s + chunk] = Kr @ v
     return out
@@ -173,11 +174,10 @@ def solve(S, y, rtol, max_iter):
     return pcg(lambda v: apply(S, v), lambda r: precond(S, r), y, rtol, max_iter)
 
 
-def predict(X, Xq, w, kernel, l, chunk=256):
+def predict(X, Xq, w, kernel, l, chunk=1024):
     """K(x*, x) w with the exact kernel."""
     X, Xq = np.asarray(X, dtype=np.float64), np.asarray(Xq, dtype=np.float64)
     out = np.zeros(len(Xq))
     for s in range(0, len(Xq), chunk):
-        q = Xq[s:s + chunk]
-        out[s:s + chunk] = kappa(kernel, np.sqrt(((q[:, None, :] - X[None, :, :]) ** 2).sum(-1)), l) @ w
+        out[s:s + chunk] = kappa(kernel, cdist(Xq[s:s + chunk], X), l) @ w
     return out

@@ -26,15 +26,16 @@ def build(verbose=False):
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src in ("planner.cpp", "capi.cpp"):
+    for src in ("planner.cpp", "capi.cpp", "krr.cpp"):
         o = os.path.join(objdir, src + ".o")
         _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", *COMMON, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
-    o = os.path.join(objdir, "kernels.hip.o")
-    out = _run([HIPCC, *DEVICE_FLAGS, *COMMON, "-c", os.path.join(CSRC, "kernels.hip"), "-o", o])
-    if verbose and out:
-        print(out)
-    objs.append(o)
+    for src in ("kernels.hip", "krr_kernels.hip"):
+        o = os.path.join(objdir, src + ".o")
+        out = _run([HIPCC, *DEVICE_FLAGS, *COMMON, "-c", os.path.join(CSRC, src), "-o", o])
+        if verbose and out:
+            print(out)
+        objs.append(o)
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE_FLAGS, "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -17,6 +17,7 @@
 #include "../../include/hdf.h"
 #include "kernels.hpp"
 #include "planner.hpp"
+#include "status.hpp"
 
 namespace {
 
@@ -53,6 +54,11 @@ double now_ms() {
 }
 
 }  // namespace
+
+namespace hdf {
+hdf_status set_error(hdf_status s, const std::string& msg) { return fail(s, msg); }
+void clear_error() { g_err.clear(); }
+}  // namespace hdf
 
 struct hdf_factor {
   int d = 0, prec = 0, dtype = 0, kernel = 0;

@@ -22,7 +22,10 @@ STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
 EXPORTS = ["hdf_build", "hdf_build_ex", "hdf_build_cross", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
            "hdf_copy_factor", "hdf_copy_factor_y", "hdf_free", "hdf_status_string", "hdf_last_error",
            "hdf_plan_chebyshev", "hdf_plan_degree", "hdf_plan_cores", "hdf_plan_index_set",
-           "hdf_plan_compress_cross"]
+           "hdf_plan_compress_cross", "hdf_kmeans", "hdf_kernel_matvec", "hdf_krr_create", "hdf_krr_apply",
+           "hdf_krr_precond", "hdf_krr_solve", "hdf_krr_info", "hdf_krr_block", "hdf_krr_free"]
+
+KMEANS_SEED = 0x48444602
 
 
 class HDFInfo(ctypes.Structure):
@@ -51,6 +54,16 @@ class BuildOptions(ctypes.Structure):
 
 
 RANK_RULES = {"bound": 0, "sampled": 1}
+
+
+class KRRInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_int64), ("n_dim", ctypes.c_int32), ("n_clusters", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int32), ("max_block", ctypes.c_int32), ("max_degree", ctypes.c_int32),
+        ("sum_rank", ctypes.c_int64), ("factor_bytes", ctypes.c_int64), ("precond_bytes", ctypes.c_int64),
+        ("t_factor_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double), ("t_offdiag_ms", ctypes.c_double),
+        ("t_solve_ms", ctypes.c_double), ("last_iterations", ctypes.c_int32), ("last_relres", ctypes.c_double),
+    ]
 
 
 class HDFError(RuntimeError):
@@ -91,9 +104,19 @@ def lib():
     L.hdf_plan_degree.argtypes = [vp, i32, dbl, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.hdf_plan_cores.argtypes = [vp, i32, i32, dbl, dbl, vp]
     L.hdf_plan_index_set.argtypes = [i32, i32, vp, ctypes.POINTER(i64)]
+    L.hdf_kmeans.argtypes = [vp, i64, i32, i64, i32, i32, ctypes.c_uint64, vp, vp, ctypes.POINTER(i32), vp]
+    L.hdf_kernel_matvec.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, dbl, vp, vp, vp]
+    L.hdf_krr_create.argtypes = [vp, i64, i32, i64, vp, i32, i32, dbl, dbl, dbl, vp, ctypes.POINTER(vp)]
+    L.hdf_krr_apply.argtypes = [vp, vp, vp, vp]
+    L.hdf_krr_precond.argtypes = [vp, vp, vp, vp]
+    L.hdf_krr_solve.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+    L.hdf_krr_info.argtypes = [vp, ctypes.POINTER(KRRInfo)]
+    L.hdf_krr_block.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.hdf_krr_free.argtypes = [vp]
+    L.hdf_krr_free.restype = None
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("hdf_free", "hdf_status_string", "hdf_last_error"):
+        if name not in ("hdf_free", "hdf_status_string", "hdf_last_error", "hdf_krr_free"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -150,7 +173,7 @@ class Factor:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib is not None:
+        if h is not None and h.value and _lib is not None and getattr(self, "_owned", True):
             _lib.hdf_free(h)
             self._h = None
 
@@ -359,3 +382,112 @@ def plan_index_set(d, k):
     t = np.zeros((max(cnt.value, 1), d - 2), dtype=np.int32)
     _check(lib().hdf_plan_index_set(d, k, t.ctypes.data, ctypes.byref(cnt)))
     return t[:cnt.value]
+
+
+# -- kernel ridge regression consumer (Sec. 4.2) -----------------------------
+def _dev1d(t, name, n=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA (HIP) tensor")
+    t = t.reshape(-1).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return t
+
+
+def _dev_i32(t, name, n):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32:
+        raise TypeError(f"{name} must be an int32 CUDA (HIP) tensor")
+    t = t.reshape(-1).contiguous()
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return t
+
+
+def kmeans(X, k, max_iter=100, seed=KMEANS_SEED):
+    """Lloyd's k-means on the device: (labels int32 (n,), centres (k, d), assignments made)."""
+    X = _dev2d(X, torch.float64, "X")
+    n, d = X.shape
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    centres = torch.empty((k, d), dtype=torch.float64, device=X.device)
+    its = ctypes.c_int(0)
+    with torch.cuda.device(X.device):
+        _check(lib().hdf_kmeans(X.data_ptr(), n, d, X.stride(0), int(k), int(max_iter), int(seed),
+                                labels.data_ptr(), centres.data_ptr(), ctypes.byref(its), _stream()))
+    return labels, centres, its.value
+
+
+def kernel_matvec(X, Y, w, kernel="gaussian", lengthscale=1.0):
+    """K(X, Y) w with exact kernel values (binary64)."""
+    X = _dev2d(X, torch.float64, "X")
+    Y = _dev2d(Y, torch.float64, "Y")
+    if X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y must have the same number of columns")
+    w = _dev1d(w, "w", Y.shape[0])
+    out = torch.empty(X.shape[0], dtype=torch.float64, device=X.device)
+    with torch.cuda.device(X.device):
+        _check(lib().hdf_kernel_matvec(X.data_ptr(), X.shape[0], X.stride(0), Y.data_ptr(), Y.shape[0], Y.stride(0),
+                                       X.shape[1], KERNELS[kernel], float(lengthscale), w.data_ptr(), out.data_ptr(),
+                                       _stream()))
+    return out
+
+
+class KRR:
+    """The KRR system (lambda I + K) with HDF diagonal blocks per cluster (owns the library handle)."""
+
+    def __init__(self, X, labels, k, kernel="gaussian", lengthscale=1.0, tol=1e-4, lam=0.1):
+        X = _dev2d(X, torch.float64, "X")
+        self.n, self.d = X.shape
+        labels = _dev_i32(labels, "labels", self.n)
+        self.k, self.kernel, self.lengthscale = int(k), kernel, float(lengthscale)
+        self.device = X.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(X.device):
+            _check(lib().hdf_krr_create(X.data_ptr(), self.n, self.d, X.stride(0), labels.data_ptr(), self.k,
+                                        KERNELS[kernel], self.lengthscale, float(tol), float(lam), _stream(),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hdf_krr_free(h)
+            self._h = None
+
+    def apply(self, v):
+        v = _dev1d(v, "v", self.n)
+        out = torch.empty_like(v)
+        _check(lib().hdf_krr_apply(self._h, v.data_ptr(), out.data_ptr(), _stream()))
+        return out
+
+    def precond(self, r):
+        r = _dev1d(r, "r", self.n)
+        z = torch.empty_like(r)
+        _check(lib().hdf_krr_precond(self._h, r.data_ptr(), z.data_ptr(), _stream()))
+        return z
+
+    def solve(self, y, max_iter=1024, rtol=1e-6):
+        """(w, iterations, relative residual) of preconditioned CG from w = 0."""
+        y = _dev1d(y, "y", self.n)
+        w = torch.empty_like(y)
+        its, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+        _check(lib().hdf_krr_solve(self._h, y.data_ptr(), w.data_ptr(), int(max_iter), float(rtol),
+                                   ctypes.byref(its), ctypes.byref(rel), _stream()))
+        return w, its.value, rel.value
+
+    def info(self):
+        inf = KRRInfo()
+        _check(lib().hdf_krr_info(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in KRRInfo._fields_}
+
+    def block(self, c):
+        """The HDF factor of cluster c (None if empty), borrowed from this handle."""
+        h = ctypes.c_void_p()
+        _check(lib().hdf_krr_block(self._h, int(c), ctypes.byref(h)))
+        if not h.value:
+            return None
+        f = Factor.__new__(Factor)
+        f._h, f._owned, f._parent = h, False, self
+        inf = f.info()
+        f.n, f.d, f.dtype, f.precision = inf["n_points"], inf["n_dim"], torch.float64, HDF_FP64
+        f.kernel, f.lengthscale, f.device = self.kernel, self.lengthscale, self.device
+        return f

@@ -1,7 +1,7 @@
 """Build the CPU-emulated library (libhdf_emu.so) under ASan/UBSan.
 
-The product sources (capi.cpp, planner.cpp and kernels.hip through
-translate.py) are compiled unchanged for the host, with the dF/dX kernels
+The product sources (capi.cpp, planner.cpp, krr.cpp, and kernels.hip and
+krr_kernels.hip through translate.py) are compiled unchanged for the host, with the dF/dX kernels
 dispatched (-DHDF_ADJOINT_KERNEL=1).  The build lands in tests/emu/_build/<hash>
 and is reused while sources and flags are unchanged.
 """
@@ -18,7 +18,8 @@ CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 FLAGS = ["-std=c++17", "-g", "-O1", "-fPIC", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
          "-fno-sanitize-recover=undefined", "-ftrivial-auto-var-init=pattern", "-DHDF_ADJOINT_KERNEL=1",
          "-Wno-psabi", "-Wno-unused-value", "-I", os.path.join(HERE, "shim"), "-I", CSRC]
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "kernels.hpp", "capi.cpp", "planner.cpp", "planner.hpp")] + \
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "kernels.hpp", "capi.cpp", "planner.cpp", "planner.hpp",
+                                            "krr_kernels.hip", "krr_kernels.hpp", "krr.cpp", "status.hpp")] + \
           [os.path.join(ROOT, "include", "hdf.h")] + \
           [os.path.join(HERE, f) for f in ("emu_hip.h", "emu_rt.cpp", "translate.py", "build.py")]
 
@@ -53,7 +54,10 @@ def build():
     translate = mod.translate
     kern = os.path.join(tmp, "kernels_emu.cpp")
     open(kern, "w").write(translate(open(os.path.join(CSRC, "kernels.hip")).read()))
-    units = [kern, os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"), os.path.join(HERE, "emu_rt.cpp")]
+    kern2 = os.path.join(tmp, "krr_kernels_emu.cpp")
+    open(kern2, "w").write(translate(open(os.path.join(CSRC, "krr_kernels.hip")).read(), "krr_kernels.hpp"))
+    units = [kern, kern2, os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"),
+             os.path.join(CSRC, "krr.cpp"), os.path.join(HERE, "emu_rt.cpp")]
 
     def compile_one(src):
         obj = os.path.join(tmp, os.path.basename(src) + ".o")

@@ -15,6 +15,7 @@ typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1, hipErrorNotReady = 600 };
 typedef struct emu_stream* hipStream_t;
 typedef struct emu_event* hipEvent_t;
+enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2 };
 enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                      hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 };
 
@@ -29,6 +30,10 @@ hipError_t hipMemsetAsync(void* dst, int v, size_t b, hipStream_t s);
 hipError_t hipStreamSynchronize(hipStream_t s);
 hipError_t hipDeviceSynchronize();
 hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned flags);
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned flags);
+hipError_t hipStreamDestroy(hipStream_t s);
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventSynchronize(hipEvent_t e);
@@ -67,6 +72,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 f4 mfma_f32(float a, float b, f4 c);
 d4 mfma_f64(double a, double b, d4 c);
 void check_launch(unsigned grid, unsigned block, size_t shm);
+int syncthreads_count(int p);
+double shfl_xor(double v, int mask);
 void enqueue(hipStream_t s, std::function<void()> f);
 void run_grid(dim3 grid, unsigned block, size_t shm, const std::function<void()>& body);
 extern const char* g_kernel_name;
@@ -91,6 +98,10 @@ void launch(const char* name, dim3 grid, dim3 block, size_t shm, hipStream_t s, 
 #define blockDim (emu::g_blockDim)
 #define gridDim (emu::g_gridDim)
 #define __syncthreads() emu::syncthreads()
+#define __syncthreads_count(p) emu::syncthreads_count(p)
+#define __shfl_xor(v, m) emu::shfl_xor(v, m)
+using std::max;
+using std::min;
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32(a, b, c)
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64(a, b, c)
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))

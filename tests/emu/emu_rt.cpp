@@ -19,7 +19,8 @@
 //   EMU_STACK_KB, EMU_VERBOSE, EMU_WARN_EXIT_BARRIER
 // Faults it reports: out-of-bounds and use-after-free (ASan), misaligned
 // vector accesses (UBSan), host memory passed to a kernel, divergent barriers,
-// MFMA issued by part of a wave or from different call sites, deadlock.
+// MFMA or a lane shuffle issued by part of a wave or from different call
+// sites, deadlock.
 #define EMU_DEVICE_CODE
 #include "emu_hip.h"
 
@@ -34,7 +35,7 @@
 
 namespace emu {
 
-enum { READY = 0, BARRIER = 1, MFMA32 = 2, MFMA64 = 3, DONE = 4 };
+enum { READY = 0, BARRIER = 1, MFMA32 = 2, MFMA64 = 3, DONE = 4, SHFL = 5 };
 
 struct Fiber {
   void* sp = nullptr;
@@ -127,6 +128,29 @@ __attribute__((noinline)) void syncthreads() {
   cur->site = __builtin_return_address(0);
   cur->state = BARRIER;
   to_main();
+}
+
+// __syncthreads_count: a barrier that also counts the threads with p != 0
+static int g_count_acc = 0;
+int syncthreads_count(int p) {
+  g_count_acc += p != 0;
+  syncthreads();
+  const int r = g_count_acc;
+  syncthreads();
+  if (tidx().x == 0) g_count_acc = 0;
+  syncthreads();
+  return r;
+}
+
+// __shfl_xor: a wave-wide collective; lane L receives the value of lane L ^ mask
+__attribute__((noinline)) double shfl_xor(double v, int mask) {
+  Fiber* f = cur;
+  f->site = __builtin_return_address(0);
+  f->a = v;
+  f->b = mask;
+  f->state = SHFL;
+  to_main();
+  return f->dout[0];
 }
 
 template <int MODE, typename T>
@@ -246,15 +270,33 @@ void run_grid(dim3 grid, unsigned block, size_t shm, const std::function<void()>
       int nd = 0, nb = 0, nm = 0;
       for (unsigned t = 0; t < block; ++t) {
         const int s = fibers[t].state;
-        nd += s == DONE; nb += s == BARRIER; nm += s == MFMA32 || s == MFMA64;
+        nd += s == DONE; nb += s == BARRIER; nm += s == MFMA32 || s == MFMA64 || s == SHFL;
       }
       if (nd == (int)block) break;
       bool any = false;
       for (unsigned w = 0; w * 64 < block; ++w) {
         Fiber* wf = &fibers[w * 64];
         const unsigned nl = std::min<unsigned>(64, block - w * 64);
-        int c32 = 0, c64 = 0;
-        for (unsigned L = 0; L < nl; ++L) { c32 += wf[L].state == MFMA32; c64 += wf[L].state == MFMA64; }
+        int c32 = 0, c64 = 0, csh = 0;
+        for (unsigned L = 0; L < nl; ++L) {
+          c32 += wf[L].state == MFMA32; c64 += wf[L].state == MFMA64; csh += wf[L].state == SHFL;
+        }
+        if (csh) {
+          if (csh == 64) {
+            const int mask = (int)wf[0].b;
+            for (unsigned L = 1; L < 64; ++L)
+              if (wf[L].site != wf[0].site || (int)wf[L].b != mask) die("shuffle lanes at different call sites or masks");
+            if (mask < 0 || mask > 63) die("shuffle mask out of range");
+            for (unsigned L = 0; L < 64; ++L) wf[L].dout[0] = wf[L ^ mask].a;
+            for (unsigned L = 0; L < 64; ++L) wf[L].state = READY;
+            any = true;
+          } else {
+            for (unsigned L = 0; L < nl; ++L)
+              if (wf[L].state == DONE || wf[L].state == BARRIER || wf[L].state == MFMA32 || wf[L].state == MFMA64)
+                die("shuffle issued by part of a wave");
+          }
+          continue;
+        }
         if (c32 + c64 == 0) continue;
         if (nl != 64) die("MFMA in a partial wave");
         if (c32 == 64 || c64 == 64) {
@@ -421,6 +463,11 @@ hipError_t hipMemsetAsync(void* dst, int v, size_t b, hipStream_t s) {
 hipError_t hipStreamSynchronize(hipStream_t) { emu::flush(); return hipSuccess; }
 hipError_t hipDeviceSynchronize() { emu::flush(); return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) { *e = new emu_event; return hipSuccess; }
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = new emu_event; return hipSuccess; }
+// one queue runs all work in submission order: every stream wait is already satisfied
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { static char dummy[8]; *s = (hipStream_t)dummy; return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
   e->done = false;

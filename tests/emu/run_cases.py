@@ -30,7 +30,7 @@ _libc = ctypes.CDLL(None)
 _libc.mprotect.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
 _keep = []
 _G = 1 << 20
-_NP = {torch.float64: np.float64, torch.float32: np.float32}
+_NP = {torch.float64: np.float64, torch.float32: np.float32, torch.int32: np.int32}
 
 
 def dev_empty(shape, dtype, fill=np.nan):
@@ -43,7 +43,7 @@ def dev_empty(shape, dtype, fill=np.nan):
     base = ctypes.addressof(ctypes.c_char.from_buffer(mm))
     assert _libc.mprotect(base, _G, 0) == 0 and _libc.mprotect(base + _G + body, _G, 0) == 0
     arr = np.frombuffer(mm, dtype=np_dtype, count=n, offset=_G + body - nbytes).reshape(shape)
-    arr[...] = fill
+    arr[...] = fill if np.dtype(np_dtype).kind == "f" else -7
     _raw.emu_register(arr.ctypes.data, max(arr.nbytes, 1))
     _keep.append(mm)
     return torch.from_numpy(arr)
@@ -86,6 +86,22 @@ def _install():
             t = t.unsqueeze(1)
         return t if t.dim() == 2 and t.stride(1) == 1 else t.contiguous()
     hdf._dev2d = dev2d
+
+    def dev1d(t, name, n=None):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+            raise TypeError(name)
+        t = t.reshape(-1).contiguous()
+        if n is not None and t.numel() != n:
+            raise ValueError(name)
+        return t
+    hdf._dev1d = dev1d
+
+    def dev_i32(t, name, n):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or t.numel() != n:
+            raise TypeError(name)
+        return t.reshape(-1).contiguous()
+    hdf._dev_i32 = dev_i32
+    torch.empty_like = lambda t: dev_empty(tuple(t.shape), t.dtype)
     real_empty = torch.empty
 
     def empty(*a, **k):                      # outputs the binding allocates
@@ -191,7 +207,58 @@ def case_sampled():
     check("sampled guarantee", e <= 1e-4, f"{e:.2e} (rank {inf['rank']}, bound rule {ohdf.build(X, 'gaussian', 0.7, 1e-4)['r']})")
 
 
-CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled}
+def case_krr():
+    """KRR consumer: k-means, the system operator, the preconditioner, CG and the dense kernel matvec
+    against the oracle, on a ragged d = 3 cloud (one cluster left empty) and a d = 8 housing-shaped one."""
+    from oracle import krr
+    for name, X, k, kern, l, tol, use in (
+            ("d3", wl.unit_ball(613, 3, 31), 5, "gaussian", 0.8, 1e-6, 4),
+            ("d8", wl.housing_split(600)[0], 4, "gaussian", 0.5, 1e-3, 3)):
+        n = len(X)
+        Xd = to_dev(X, torch.float64)
+        lab, C, its = hdf.kmeans(Xd, use, max_iter=100)
+        lo, Co, itso, _ = krr.kmeans(X, use, max_iter=100)
+        lab_np = lab.numpy().copy()
+        check(f"krr {name} kmeans labels", np.array_equal(lab_np, lo) and its == itso,
+              f"{int((lab_np != lo).sum())} differ, {its} vs {itso} assignments")
+        check(f"krr {name} kmeans centres", np.abs(C.numpy() - Co).max() <= 1e-12, f"{np.abs(C.numpy() - Co).max():.1e}")
+        # k clusters, `use` of them populated: the rest are empty blocks
+        S = krr.create(X, lo, k, kern, l, tol, 0.1)
+        sysm = hdf.KRR(Xd, to_dev(lo.astype(np.int32), torch.int32), k, kern, l, tol, 0.1)
+        v = wl.rhs(n, 1, 32)[:, 0]
+        e = rel(sysm.apply(to_dev(v, torch.float64)).numpy(), krr.apply(S, v))
+        check(f"krr {name} apply", e <= 1e-12, f"{e:.2e}")
+        e = rel(sysm.precond(to_dev(v, torch.float64)).numpy(), krr.precond(S, v))
+        check(f"krr {name} precond", e <= 1e-10, f"{e:.2e}")
+        y = np.sin(3 * X[:, 0]) + X[:, 1] * X[:, 2]
+        # a fixed number of iterations (rtol 0): the iterate is unique, no stopping decision
+        w, it, rr = sysm.solve(to_dev(y, torch.float64), max_iter=9, rtol=0.0)
+        wo, ito, hist = krr.solve(S, y, 0.0, 9)
+        e = rel(w.numpy(), wo)
+        check(f"krr {name} 9 iterations", it == ito == 9 and e <= 1e-8 and abs(rr / hist[-1] - 1) <= 1e-6,
+              f"w {e:.2e}, relres {rr:.3e} vs {hist[-1]:.3e}")
+        # converged: the CG residual is not monotone, so where it first crosses rtol depends on rounding;
+        # the solution must meet rtol under the oracle's operator
+        w, it, rr = sysm.solve(to_dev(y, torch.float64), max_iter=300, rtol=1e-3)
+        wo, ito, hist = krr.solve(S, y, 1e-3, 300)
+        true = np.linalg.norm(y - krr.apply(S, w.numpy())) / np.linalg.norm(y)
+        check(f"krr {name} solve to 1e-3", rr <= 1e-3 and true <= 2e-3 and abs(it - ito) <= max(2, 0.05 * ito),
+              f"{it} vs {ito} iterations, true residual {true:.2e}, relres {rr:.2e} vs {hist[-1]:.2e}")
+        Xq = wl.unit_ball(77, X.shape[1], 33) * 0.5 + 0.3
+        e = rel(hdf.kernel_matvec(to_dev(Xq, torch.float64), Xd, to_dev(wo, torch.float64), kern, l).numpy(),
+                krr.predict(X, Xq, wo, kern, l))
+        check(f"krr {name} predict", e <= 1e-12, f"{e:.2e}")
+        w0, it0, _ = sysm.solve(to_dev(np.zeros(n), torch.float64))
+        check(f"krr {name} zero rhs", it0 == 0 and not np.any(w0.numpy()), f"{it0} iterations")
+        w0, it0, _ = sysm.solve(to_dev(y, torch.float64), max_iter=0)
+        check(f"krr {name} no iterations", it0 == 0 and not np.any(w0.numpy()), f"{it0} iterations")
+        inf = sysm.info()
+        check(f"krr {name} blocks", inf["n_blocks"] == use and sysm.block(k - 1) is None,
+              f"{inf['n_blocks']} blocks, ranks {inf['sum_rank']}")
+
+
+CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
+         "krr": case_krr}
 
 if __name__ == "__main__":
     _install()

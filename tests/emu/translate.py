@@ -1,4 +1,4 @@
-"""Translate kernels.hip into C++ for the CPU emulation (emu_hip.h).
+"""Translate a .hip source (kernels.hip, krr_kernels.hip) into C++ for the CPU emulation (emu_hip.h).
 
 Three mechanical rewrites, nothing else: triple-chevron launches become
 emu::launch calls, __shared__ arrays become static arrays filled with garbage
@@ -20,7 +20,7 @@ template <> struct StructCheck<hdf::BuildTables> {
 '''
 
 
-def translate(src):
+def translate(src, header="kernels.hpp"):
     n0 = src.count("<<<")
     src, n = re.subn(r'(k_\w+(?:<[^<>;]*?>)?)<<<(.*?)>>>\(',
                      lambda m: f'emu::launch("{m.group(1)}", {m.group(2)}, {m.group(1)}, ', src)
@@ -30,14 +30,20 @@ def translate(src):
 
     def shared(m):
         typ, rest = re.match(r'(\w+)\s+(.*)', m.group(1)).groups()
-        names = re.findall(r'(\w+)\s*(?:\[[^\]]*\])+\s*(?:,|$)', rest)
-        if not names:
-            raise ValueError(m.group(0))
-        return f'static {typ} {rest};' + ''.join(f' emu::garbage_once({x}, sizeof({x}));' for x in names)
+        arrays = re.findall(r'(\w+)\s*(?:\[[^\]]*\])+\s*(?:,|$)', rest)
+        scalar = re.fullmatch(r'\s*(\w+)\s*', rest)
+        if arrays:
+            return f'static {typ} {rest};' + ''.join(f' emu::garbage_once({x}, sizeof({x}));' for x in arrays)
+        if scalar:
+            x = scalar.group(1)
+            return f'static {typ} {x}; emu::garbage_once(&{x}, sizeof({x}));'
+        raise ValueError(m.group(0))
     src = re.sub(r'__shared__ ([^;]*);', shared, src)
-    if '#include "kernels.hpp"\n' not in src:
-        raise ValueError("kernels.hpp include not found")
-    src = src.replace('#include "kernels.hpp"\n', '#include "kernels.hpp"\n' + _HOOK, 1)
+    inc = f'#include "{header}"\n'
+    if inc not in src:
+        raise ValueError(f"{header} include not found")
+    if header == "kernels.hpp":
+        src = src.replace(inc, inc + _HOOK, 1)
     return '#define EMU_DEVICE_CODE\n' + src
 
 
