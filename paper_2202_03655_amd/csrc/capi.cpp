@@ -100,7 +100,7 @@ struct hdf_factor {
   DevBuf items_dev, gitems_dev, gq_dev;
   int items_cpl = 0, n_groups = 0, max_nq = 0;
   // matvec / adjoint workspace
-  DevBuf ws_part, ws_W, ws_Wd, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
+  DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
   // adjoint tables: row of U^T V per harmonic row in the recursion's visiting
   // order, per-degree (s_k, first radial row), coefficient stream scratch
   std::vector<int32_t> adj_src_host;
@@ -813,7 +813,11 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
       for (size_t di = 0; di < h->degs.size(); ++di)
         for (int h0 = 0; h0 < h->degs[di].nh; h0 += 16)
           for (int ct = 0; ct < h->degs[di].s * cpl; ++ct) items.push_back(hdf::TileDev{(int32_t)di, h0, ct, 0});
-      const int per = hdf::matvec_items_per_group();
+      // few points (a factor of a small cluster): smaller groups, so that the launch still has
+      // >= 512 workgroups; the splits over points are at most (n + 255) / 256
+      int per = hdf::matvec_items_per_group();
+      const int64_t max_splits = std::min<int64_t>((n + 255) / 256, 1024);
+      while (per > 4 && (int64_t)((items.size() + per - 1) / per) * max_splits < 512) per /= 2;
       std::vector<int32_t> gi, gq;
       int max_nq = 0;
       for (size_t i0 = 0; i0 < items.size(); i0 += per) {
@@ -903,9 +907,20 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
   const int m16 = (int)((m + 15) / 16 * 16);
   hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
   if (st != HDF_OK) return st;
+  // few points: split the harmonic rows so that pass 2 still has >= 1024 wavefronts
+  const int64_t waves = ((n + 63) / 64) * (m16 / 16);
+  int nz = 1, hchunk = 0;
+  if (waves < 1024 && h->H >= 32) {
+    const int64_t want = std::min<int64_t>((1024 + waves - 1) / waves, h->H / 16);
+    if (want > 1) {
+      hchunk = (int)(((h->H + want - 1) / want + 15) / 16 * 16);
+      nz = (int)((h->H + hchunk - 1) / hchunk);
+    }
+  }
+  if (nz > 1) HIPCHK(h->ws_n.ensure((size_t)nz * n * m * el));
   HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
                               (int)h->degs.size(), h->max_s, h->ws_Wd.p, m16, KV, ldkv, n, (int)m,
-                              h->prec, s));
+                              h->prec, nz > 1 ? hchunk : 0, nz, nz > 1 ? h->ws_n.p : nullptr, s));
   HIPCHK(hipEventRecord(h->ev_mv[3], s));
   h->mv_timed = true;
   return HDF_OK;

@@ -1410,9 +1410,11 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
   T* lds = reinterpret_cast<T*>(smem_raw);        // [2][half]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
   const int cpl = m16 / 16;
-  const int my0 = it0 + wave * kMvTPW;
+  // a group of up to 4 * kMvTPW items is split evenly over the four wavefronts
+  const int ipw = (it1 - it0 + 3) / 4;
+  const int my0 = it0 + wave * ipw;
   int n_mine = it1 - my0;
-  n_mine = n_mine < 0 ? 0 : (n_mine > kMvTPW ? kMvTPW : n_mine);
+  n_mine = n_mine < 0 ? 0 : (n_mine > ipw ? ipw : n_mine);
   // per-item descriptors resolved once: first Phi row, rows in the tile,
   // LDS offset of its radial row, output column base
   __shared__ int64_t d_row[4 * kMvTPW];
@@ -1428,7 +1430,7 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
   }
   const int64_t p_begin = (int64_t)split * split_len;
   const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
-  const int wbase = wave * kMvTPW;
+  const int wbase = wave * ipw;
 
   // staging of chunk p: thread tid owns V entries e = tid + 256 j (< 32 m16)
   // and q entries e = tid + 256 j (< 32 nq)
@@ -1576,16 +1578,22 @@ __global__ void k_mv_reduce(const double* __restrict__ part, int n_splits, int64
 // sum_h phi_h(i) Wd[(k,h,l)][c] on MFMA (reduction over harmonics) and folds
 // Z into KV with the radial functions q_{k,l}(i).  MFMA row i of point tile
 // u is point p0 + 4 i + u, so each lane reads 4 consecutive points of a
-// harmonic row with one 16-byte load.
+// harmonic row with one 16-byte load.  With hchunk > 0 (few points, many
+// harmonics) blockIdx.z takes the harmonic rows [z hchunk, (z+1) hchunk)
+// only and writes its share of KV to part[z][n][m]; k_mv_n_sum adds the
+// shares in z order.
 template <typename T, int NCT>
 __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
                                               const DegDev* __restrict__ degs, int n_deg,
                                               const T* __restrict__ Wd, int m16,
-                                              T* __restrict__ KV, int64_t ldkv, int64_t n, int m) {
+                                              T* __restrict__ KV, int64_t ldkv, int64_t n, int m,
+                                              int hchunk, T* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
   const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
   const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int zlo = hchunk > 0 ? (int)blockIdx.z * hchunk : 0;
+  const int zhi = hchunk > 0 ? zlo + hchunk : 0x7fffffff;
   const int c0 = blockIdx.y * 16;
   const int64_t pa = p0 + 4 * li;                // this lane's four A points
   T kv[4][4];
@@ -1595,6 +1603,10 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
     for (int e = 0; e < 4; ++e) kv[u][e] = 0;
   for (int di = 0; di < n_deg; ++di) {
     const DegDev dg = degs[di];
+    // this workgroup's harmonics of the degree: [hlo, hhi)
+    const int hlo = zlo > dg.hoff ? zlo - dg.hoff : 0;
+    const int hhi = (zhi - dg.hoff) < dg.nh ? zhi - dg.hoff : dg.nh;
+    if (hlo >= hhi) continue;
     for (int l0 = 0; l0 < dg.s; l0 += NCT) {
       Acc acc[4][NCT];
 #pragma unroll
@@ -1610,7 +1622,7 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           const int hh = hb + 4 * kb + g;
-          const T* prow = phi + (int64_t)(dg.hoff + (hh < dg.nh ? hh : 0)) * ld_phi;
+          const T* prow = phi + (int64_t)(dg.hoff + (hh < hhi ? hh : hlo)) * ld_phi;
           if constexpr (sizeof(T) == 4) {
             const floatx4 w = *reinterpret_cast<const floatx4*>(prow + pa);
 #pragma unroll
@@ -1627,8 +1639,8 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
           const int hh = hb + 4 * kb + g;
-          const T* wrow = Wd + (int64_t)(dg.roff + (hh < dg.nh ? hh : 0) * dg.s) * m16 + c0 + li;
-          const T hmask = hh < dg.nh ? (T)1 : (T)0;
+          const T* wrow = Wd + (int64_t)(dg.roff + (hh < hhi ? hh : hlo) * dg.s) * m16 + c0 + li;
+          const T hmask = hh < hhi ? (T)1 : (T)0;
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             const int l = l0 + ct;
@@ -1637,9 +1649,9 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
         }
       };
       T w_nxt[KB][NCT];
-      load_batch(0, v_nxt);
-      load_w(0, w_nxt);
-      for (int hb = 0; hb < dg.nh; hb += 4 * KB) {
+      load_batch(hlo, v_nxt);
+      load_w(hlo, w_nxt);
+      for (int hb = hlo; hb < hhi; hb += 4 * KB) {
         T v[KB][4], bw[KB][NCT];
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
@@ -1648,7 +1660,7 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) bw[kb][ct] = w_nxt[kb][ct];
         }
-        if (hb + 4 * KB < dg.nh) {
+        if (hb + 4 * KB < hhi) {
           load_batch(hb + 4 * KB, v_nxt);
           load_w(hb + 4 * KB, w_nxt);
         }
@@ -1657,7 +1669,7 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
           const int hh = hb + 4 * kb + g;
           T a[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a[u] = (hh < dg.nh && pa + u < n) ? v[kb][u] : (T)0;
+          for (int u = 0; u < 4; ++u) a[u] = (hh < hhi && pa + u < n) ? v[kb][u] : (T)0;
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             if (l0 + ct >= dg.s) break;           // uniform: live radial functions only
@@ -1684,14 +1696,28 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
   }
   const int c = c0 + li;
   if (c < m) {
+    T* dst = part ? part + (int64_t)blockIdx.z * n * m : KV;
+    const int64_t ld = part ? m : ldkv;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t pt = p0 + 4 * Mfma<T>::row(g, e) + u;
-        if (pt < n) KV[pt * ldkv + c] = kv[u][e];
+        if (pt < n) dst[pt * ld + c] = kv[u][e];
       }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mv_n_sum(const T* __restrict__ part, int nz, int64_t n, int m,
+                                                  T* __restrict__ KV, int64_t ldkv) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * m) return;
+  const int64_t pt = e / m;
+  const int c = (int)(e - pt * m);
+  T s = 0;
+  for (int z = 0; z < nz; ++z) s += part[((int64_t)z * n + pt) * m + c];
+  KV[pt * ldkv + c] = s;
 }
 
 constexpr int kMvNctF = 4;   // column tiles per pass, binary32
@@ -1732,16 +1758,25 @@ hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t ra
 
 hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
-                           void* KV, int64_t ldkv, int64_t n, int m, int prec, hipStream_t s) {
+                           void* KV, int64_t ldkv, int64_t n, int m, int prec, int hchunk, int nz,
+                           void* part, hipStream_t s) {
   (void)max_s;
-  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)(m16 / 16));
-  if (prec == 1)
+  if (nz < 1 || (nz > 1 && (hchunk <= 0 || !part))) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)(m16 / 16), (unsigned)nz);
+  const int hc = nz > 1 ? hchunk : 0;
+  const unsigned nb = (unsigned)((n * m + 255) / 256);
+  if (prec == 1) {
+    float* dst = nz > 1 ? (float*)part : nullptr;
     k_mv_n<float, kMvNctF><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
-                                              n_deg, (const float*)Wd, m16, (float*)KV, ldkv, n, m);
-  else
+                                              n_deg, (const float*)Wd, m16, (float*)KV, ldkv, n, m, hc, dst);
+    if (nz > 1) k_mv_n_sum<float><<<nb, 256, 0, s>>>((const float*)part, nz, n, m, (float*)KV, ldkv);
+  } else {
+    double* dst = nz > 1 ? (double*)part : nullptr;
     k_mv_n<double, kMvNctD><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
                                                degs, n_deg, (const double*)Wd, m16, (double*)KV,
-                                               ldkv, n, m);
+                                               ldkv, n, m, hc, dst);
+    if (nz > 1) k_mv_n_sum<double><<<nb, 256, 0, s>>>((const double*)part, nz, n, m, (double*)KV, ldkv);
+  }
   return hipGetLastError();
 }
 

@@ -114,9 +114,12 @@ hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t ra
                                 const double* lam_row, double* W, void* Wd, int prec,
                                 hipStream_t s);
 // Pass 2: KV[i][c] = sum_rows U[i,row] Wd[row][c].
+// nz > 1: harmonic rows split into nz chunks of hchunk rows, each chunk's share
+// of KV in part (nz x n x m, storage type), summed in chunk order into KV
 hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
-                           void* KV, int64_t ldkv, int64_t n, int m, int prec, hipStream_t s);
+                           void* KV, int64_t ldkv, int64_t n, int m, int prec, int hchunk, int nz,
+                           void* part, hipStream_t s);
 
 // Adjoint: dX[i] (+)= dF/dx_i for F = sum_c w_c^T U C U^T v_c, restricted to
 // the radial rows [row0, row1) (degrees whose rows lie inside) and the
