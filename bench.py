@@ -62,7 +62,7 @@ def read_traffic(kernel, workload):
     return None
 
 
-def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule="bound"):
+def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule="bound", storage="factor"):
     import torch
     from paper_2202_03655_amd import hdf
     cfg = hdf_cfg(wname)
@@ -75,7 +75,8 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule=
 
     def step():
         t0 = time.perf_counter()
-        f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule)
+        f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule,
+                       storage=storage)
         t1 = time.perf_counter()
         f.matvec(Vd, out=out)
         t2 = time.perf_counter()
@@ -108,7 +109,7 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule=
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     # separate matvec timing on a resident factor (wall clock of the call)
-    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule)
+    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule, storage=storage)
     for _ in range(2):
         f.matvec(Vd, out=out)
     torch.cuda.synchronize()
@@ -323,6 +324,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--no-krr", action="store_true", help="skip the KRR consumer (Sec. 4.2)")
+    ap.add_argument("--no-matrix-free", action="store_true", help="skip the matrix-free factor run")
     ap.add_argument("--krr-only", action="store_true",
                     help="run only the KRR consumer and print its JSON object (for profiling)")
     ap.add_argument("--cross", type=int, default=0, metavar="NQ",
@@ -426,6 +428,17 @@ def main():
                                "p": si["degree_p"], "p_bound": si["degree_bound"], "rank": si["rank"],
                                "tau": si["tau"], "tau_bound": si["tau_bound"],
                                "est_error": si["est_error"]}
+    if not args.no_matrix_free:
+        # the same step with nothing stored per point: the factor is re-evaluated chunk by chunk in each pass
+        rm = run_gpu(args.workload, X, V, Wm, args.precision, args.steps, args.warmup, False, "bound", "none")
+        mi = rm["info"]
+        out["matrix_free"] = {"ms_per_step": round(rm["ms_per_step"], 3),
+                              "value": round(N / (rm["ms_per_step"] * 1e-3) / 1e6, 3),
+                              "build_ms": round(rm["build_ms"], 3), "matvec_ms": round(rm["matvec_ms"], 3),
+                              "pass1_with_eval_ms": round(rm["k_mv_t_ms"], 4),
+                              "pass2_with_eval_ms": round(rm["k_mv_n_ms"], 4),
+                              "chunk_points": mi["chunk_points"], "scratch_bytes": mi["factor_bytes"],
+                              "stored_factor_bytes": info["factor_bytes"], "rank": mi["rank"]}
     if args.cross:
         out["cross"] = run_cross(args.workload, X, args.cross, m, args.precision, args.steps, args.warmup)
     if not args.no_krr:

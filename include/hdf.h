@@ -109,6 +109,8 @@ typedef struct {
   int32_t  degree_bound;     /* degree the budget rule picks (may differ from
                                 degree_p under HDF_RULE_SAMPLED; -1 if above
                                 HDF_MAX_DEGREE)                             */
+  int32_t  storage;          /* hdf_storage                                  */
+  int64_t  chunk_points;     /* HDF_STORE_NONE: points per chunk; 0 otherwise */
 } hdf_info_t;
 
 /* Build the factor (Algorithm 1, symmetric case, Remark 1).
@@ -140,12 +142,27 @@ typedef enum {
                             the sampled error of U D U^T stays <= margin tol */
 } hdf_rank_rule;
 
+/* Where the factor lives between products. */
+typedef enum {
+  HDF_STORE_FACTOR = 0,  /* harmonics and radial functions of all N points
+                            stored once at build, (H + S) x N values        */
+  HDF_STORE_NONE   = 1   /* matrix-free: nothing per point is stored; every
+                            product re-evaluates them chunk by chunk into a
+                            scratch of (H + S) x chunk values, once per pass
+                            (Sec. 3.6 cost O(N r) per product, plus the
+                            harmonic evaluation O(N H d) twice)            */
+} hdf_storage;
+
 /* Options of hdf_build_ex; zero-initialised fields take the defaults. */
 typedef struct {
   int32_t rank_rule;     /* hdf_rank_rule (default HDF_RULE_BOUND)          */
   int32_t n_pairs;       /* sampled pairs, 1 .. 1048576 (default 16384)      */
   double  margin;        /* share of tol the sampled error may use, (0, 1]
                             (default 0.8)                                    */
+  int32_t storage;       /* hdf_storage (default HDF_STORE_FACTOR)          */
+  int32_t pad;
+  int64_t chunk;         /* HDF_STORE_NONE: points per chunk, >= 64
+                            (default 262144)                                 */
 } hdf_build_options;
 
 /* hdf_build with options (NULL: defaults, identical to hdf_build).  Under
@@ -154,7 +171,12 @@ typedef struct {
  * stratified into the off-diagonal pairs and the diagonal at the pairs'
  * first points, ||E||^2 ~ N(N-1) mean_off e^2 + N mean_diag e^2 (likewise
  * ||K||^2).  The estimate is not a bound: the result meets tol up to the
- * sampling error that the margin absorbs.  No additional synchronisation. */
+ * sampling error that the margin absorbs.  No additional synchronisation.
+ * Under HDF_STORE_NONE the build stops before the factor evaluation and
+ * factor_bytes (hdf_info) is the size of the chunk scratch; hdf_matvec and
+ * hdf_backward (dF/dl) re-evaluate the factor per chunk, hdf_copy_factor
+ * returns HDF_E_ARG.  The memory budget of hdf_build applies to the
+ * scratch. */
 hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t ld,
                         hdf_kernel kernel, double lengthscale, double tol, hdf_precision prec,
                         const hdf_build_options* opts, void* hip_stream, hdf_handle* out);

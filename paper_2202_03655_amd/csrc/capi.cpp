@@ -68,6 +68,9 @@ struct hdf_factor {
   double u0 = 0, u1 = 1, nu = 0, tail = 0, tau = 0;
   int p = 0, K = 0;
   int rank_rule = HDF_RULE_BOUND, p_bound = -1;
+  // HDF_STORE_NONE: the factor is re-evaluated per chunk of points into cphi / cq
+  int storage = HDF_STORE_FACTOR;
+  int64_t chunk = 0, ldC = 0;
   double tau0 = 0, est_error = -1.0;             // budget threshold, sampled estimate
   std::vector<double> a;                          // p+1 coefficients
   std::vector<std::vector<double>> cores;
@@ -101,6 +104,7 @@ struct hdf_factor {
   int items_cpl = 0, n_groups = 0, max_nq = 0;
   // matvec / adjoint workspace
   DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
+  DevBuf cphi, cq;                                // matrix-free chunk scratch
   // adjoint tables: row of U^T V per harmonic row in the recursion's visiting
   // order, per-degree (s_k, first radial row), coefficient stream scratch
   std::vector<int32_t> adj_src_host;
@@ -220,7 +224,8 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   timer.t = now_ms();
 
   // 5. memory budget, then the factor evaluation
-  const size_t fbytes = (size_t)(f->H + f->S) * (f->ldN + (f->cross ? f->ldN2 : 0)) * f->elem();
+  const bool mfree = f->storage == HDF_STORE_NONE;
+  const size_t fbytes = (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->elem();
   size_t freeb = 0, totb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totb));
   const size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)(0.6 * (double)freeb));
@@ -231,8 +236,13 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     return fail(HDF_E_INFEASIBLE, buf);
   }
   if (f->H > 0) {
-    HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
-    HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
+    if (mfree) {
+      HIPCHK(f->cphi.ensure((size_t)f->H * f->ldC * f->elem()));
+      HIPCHK(f->cq.ensure((size_t)f->S * f->ldC * f->elem()));
+    } else {
+      HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
+      HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
+    }
     if (f->cross) {
       HIPCHK(f->phi2.ensure((size_t)f->H * f->ldN2 * f->elem()));
       HIPCHK(f->q2.ensure((size_t)f->S * f->ldN2 * f->elem()));
@@ -334,6 +344,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     HIPCHK(f->degs_by_k.ensure(dbk.size() * sizeof(hdf::DegDev)));
     HIPCHK(hipMemcpyAsync(f->degs_by_k.p, dbk.data(), dbk.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (mfree) return HDF_OK;                   // evaluated chunk by chunk in every product
     HIPCHK(hipEventCreate(&f->ev_b0));
     HIPCHK(hipEventCreate(&f->ev_b1));
     HIPCHK(hipEventRecord(f->ev_b0, s));
@@ -405,10 +416,19 @@ hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t
   const double margin = (opts && opts->margin != 0.0) ? opts->margin : 0.8;
   if (n_pairs < 1 || n_pairs > (1 << 20)) return fail(HDF_E_ARG, "n_pairs must be in [1, 1048576]");
   if (!(margin > 0.0 && margin <= 1.0)) return fail(HDF_E_ARG, "margin must be in (0, 1]");
+  const int storage = opts ? opts->storage : HDF_STORE_FACTOR;
+  if (storage != HDF_STORE_FACTOR && storage != HDF_STORE_NONE) return fail(HDF_E_ARG, "unknown storage");
+  const int64_t chunk = (opts && opts->chunk) ? opts->chunk : 262144;
+  if (storage == HDF_STORE_NONE && chunk < 64) return fail(HDF_E_ARG, "chunk must be >= 64");
   hipStream_t s = (hipStream_t)hip_stream;
 
   std::unique_ptr<hdf_factor> f(new hdf_factor());
   f->rank_rule = rule;
+  if (storage == HDF_STORE_NONE) {
+    f->storage = HDF_STORE_NONE;
+    f->chunk = std::min<int64_t>(chunk, n);
+    f->ldC = (f->chunk + 63) / 64 * 64 + 64;
+  }
   f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
   f->N = n; f->l = lengthscale; f->tol = tol;
   // rows of the factor are padded by at least 64 points: the streaming kernels
@@ -781,12 +801,99 @@ hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y
 // ------------------------------------------------------------------ matvec
 // Pass 1 (W = U^T V, binary64) and the scaled copy Wd = D W for pass 2.
 // side 0: the factor's (X) rows; side 1: the Y rows of a general factor.
+// Matrix-free factor: evaluate the harmonics and radial functions of points [c0, c0 + nc) into the
+// chunk scratch (padding columns cleared, as for a stored factor).
+static hdf_status eval_chunk(hdf_handle h, int64_t c0, int64_t nc, hipStream_t s) {
+  const size_t in_el = h->dtype == 0 ? 4 : 8;
+  HIPCHK(hdf::launch_build((const char*)h->x_soa.p + c0 * in_el, h->dtype, h->ldN, nc, h->d,
+                           (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, h->prec, h->cphi.p, h->ldC,
+                           h->cq.p, h->ldC, s));
+  HIPCHK(clear_padding(h->cphi.p, h->H, nc, h->ldC, h->elem(), s));
+  HIPCHK(clear_padding(h->cq.p, h->S, nc, h->ldC, h->elem(), s));
+  return HDF_OK;
+}
+
+static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
+                        DevBuf& Wd, hipStream_t s, bool timed);
+
+// Pass 1 of a matrix-free factor: per chunk, evaluate the factor, then contract it into its own range
+// of split partials; one fixed-order reduction over all chunks' partials gives W.
+static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
+                                DevBuf& Wd, hipStream_t s, bool timed) {
+  const size_t el = h->elem();
+  const int cpl = m16 / 16;
+  const size_t per_split = (size_t)h->r * m16 * sizeof(double);
+  // work items and groups as for a stored factor of chunk points
+  hdf_status st = pass1(h, 2, V, m, ldv, m16, W, Wd, s, false);   // side 2: tables only
+  if (st != HDF_OK) return st;
+  const bool lds = m16 <= 64 && hdf::matvec_lds_bytes(m16, h->max_nq, h->prec) <= 65536;
+  std::vector<int> splits;
+  std::vector<int64_t> slen;
+  int total = 0;
+  for (int64_t c0 = 0; c0 < h->N; c0 += h->chunk) {
+    const int64_t nc = std::min(h->chunk, h->N - c0);
+    int ns;
+    int64_t len;
+    if (lds) {
+      ns = (int)std::max<int64_t>(1, 1024 / std::max(1, h->n_groups));
+      ns = (int)std::min<int64_t>(ns, (nc + 255) / 256);
+      ns = std::max(ns, 1);
+      len = ((nc + ns - 1) / ns + 31) / 32 * 32;
+    } else {
+      ns = (int)std::max<int64_t>(1, 16384 / std::max<int64_t>(1, (int64_t)h->n_tiles));
+      ns = (int)std::min<int64_t>(ns, (nc + 1023) / 1024);
+      ns = std::max(ns, 1);
+      len = ((nc + ns - 1) / ns + 15) / 16 * 16;
+    }
+    ns = (int)((nc + len - 1) / len);
+    splits.push_back(ns);
+    slen.push_back(len);
+    total += ns;
+  }
+  if ((double)per_split * total > 1.5e9)
+    return fail(HDF_E_INFEASIBLE, "matrix-free pass 1 needs more than 1.5 GB of partial sums: use a larger chunk");
+  HIPCHK(h->ws_part.ensure(per_split * total));
+  HIPCHK(W.ensure((size_t)h->r * m16 * sizeof(double)));
+  HIPCHK(Wd.ensure((size_t)h->r * m16 * el));
+  if (timed) {
+    if (!h->ev_mv[0])
+      for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(h->ev_mv[0], s));
+  }
+  int slot = 0;
+  size_t ci = 0;
+  for (int64_t c0 = 0; c0 < h->N; c0 += h->chunk, ++ci) {
+    const int64_t nc = std::min(h->chunk, h->N - c0);
+    st = eval_chunk(h, c0, nc, s);
+    if (st != HDF_OK) return st;
+    const void* Vc = (const char*)V + c0 * ldv * el;
+    double* part = (double*)h->ws_part.p + (size_t)slot * h->r * m16;
+    if (lds)
+      HIPCHK(hdf::launch_matvec_t_lds(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
+                                      (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
+                                      (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, Vc, ldv, nc, (int)m,
+                                      m16, splits[ci], slen[ci], h->r, part, h->prec, s));
+    else
+      HIPCHK(hdf::launch_matvec_t(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
+                                  (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, h->max_s * cpl, Vc, ldv, nc,
+                                  (int)m, m16, splits[ci], slen[ci], h->r, part, h->prec, s));
+    slot += splits[ci];
+  }
+  if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
+  HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, total, h->r, m16, (const double*)h->lam_row.p,
+                                   (double*)W.p, Wd.p, h->prec, s));
+  if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
+  return HDF_OK;
+}
+
+// side 2 (matrix-free factors): build the work-item tables only.
 static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
                         DevBuf& Wd, hipStream_t s, bool timed) {
-  const int64_t n = side ? h->N2 : h->N;
-  const void* phi = side ? h->phi2.p : h->phi.p;
-  const void* qv = side ? h->q2.p : h->q.p;
-  const int64_t ldn = side ? h->ldN2 : h->ldN;
+  if (h->storage == HDF_STORE_NONE && side != 2) return pass1_chunked(h, V, m, ldv, m16, W, Wd, s, timed);
+  const int64_t n = side == 1 ? h->N2 : (side == 2 ? h->chunk : h->N);
+  const void* phi = side == 1 ? h->phi2.p : h->phi.p;
+  const void* qv = side == 1 ? h->q2.p : h->q.p;
+  const int64_t ldn = side == 1 ? h->ldN2 : h->ldN;
   const size_t el = h->elem();
   const int cpl = m16 / 16;
   const int max_nct = h->max_s * cpl;
@@ -806,6 +913,7 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
     h->tiles_cpl = cpl;
   }
   const size_t per_split = (size_t)h->r * m16 * sizeof(double);
+  if (side == 2 && m16 > 64) return HDF_OK;
   if (m16 <= 64) {
     // LDS-staged variant: B operand staged once per workgroup and chunk
     if (h->items_cpl != cpl) {
@@ -841,6 +949,7 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
       h->max_nq = max_nq;
       h->items_cpl = cpl;
     }
+    if (side == 2) return HDF_OK;
     if (hdf::matvec_lds_bytes(m16, h->max_nq, h->prec) <= 65536) {
       int n_splits = (int)std::max<int64_t>(1, 1024 / std::max(1, h->n_groups));
       n_splits = (int)std::min<int64_t>(n_splits, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
@@ -869,6 +978,7 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
       return HDF_OK;
     }
   }
+  if (side == 2) return HDF_OK;
   // about 16k wavefronts in pass 1, partial records capped at ~96 MB
   int n_splits = (int)std::max<int64_t>(1, 16384 / std::max<int64_t>(1, (int64_t)h->n_tiles));
   n_splits = (int)std::min<int64_t>(n_splits, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
@@ -896,17 +1006,10 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
   return HDF_OK;
 }
 
-static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV,
-                              int64_t ldkv, hipStream_t s) {
-  const int64_t n = h->N;
+// Pass 2 over n points of a factor (phi, q with leading dimension ld): KV = U (D W), W from pass 1.
+static hdf_status pass2(hdf_handle h, const void* phi, const void* q, int64_t ld, int64_t n, int64_t m, int m16,
+                        void* KV, int64_t ldkv, hipStream_t s) {
   const size_t el = h->elem();
-  if (h->r == 0) {
-    HIPCHK(hipMemset2DAsync(KV, ldkv * el, 0, m * el, n, s));
-    return HDF_OK;
-  }
-  const int m16 = (int)((m + 15) / 16 * 16);
-  hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
-  if (st != HDF_OK) return st;
   // few points: split the harmonic rows so that pass 2 still has >= 1024 wavefronts
   const int64_t waves = ((n + 63) / 64) * (m16 / 16);
   int nz = 1, hchunk = 0;
@@ -918,9 +1021,35 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
     }
   }
   if (nz > 1) HIPCHK(h->ws_n.ensure((size_t)nz * n * m * el));
-  HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
-                              (int)h->degs.size(), h->max_s, h->ws_Wd.p, m16, KV, ldkv, n, (int)m,
-                              h->prec, nz > 1 ? hchunk : 0, nz, nz > 1 ? h->ws_n.p : nullptr, s));
+  HIPCHK(hdf::launch_matvec_n(phi, ld, q, ld, (const hdf::DegDev*)h->degs_dev.p, (int)h->degs.size(), h->max_s,
+                              h->ws_Wd.p, m16, KV, ldkv, n, (int)m, h->prec, nz > 1 ? hchunk : 0, nz,
+                              nz > 1 ? h->ws_n.p : nullptr, s));
+  return HDF_OK;
+}
+
+static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV,
+                              int64_t ldkv, hipStream_t s) {
+  const int64_t n = h->N;
+  const size_t el = h->elem();
+  if (h->r == 0) {
+    HIPCHK(hipMemset2DAsync(KV, ldkv * el, 0, m * el, n, s));
+    return HDF_OK;
+  }
+  const int m16 = (int)((m + 15) / 16 * 16);
+  hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
+  if (st != HDF_OK) return st;
+  if (h->storage == HDF_STORE_NONE) {
+    for (int64_t c0 = 0; c0 < n; c0 += h->chunk) {
+      const int64_t nc = std::min(h->chunk, n - c0);
+      st = eval_chunk(h, c0, nc, s);
+      if (st != HDF_OK) return st;
+      st = pass2(h, h->cphi.p, h->cq.p, h->ldC, nc, m, m16, (char*)KV + c0 * ldkv * el, ldkv, s);
+      if (st != HDF_OK) return st;
+    }
+  } else {
+    st = pass2(h, h->phi.p, h->q.p, h->ldN, n, m, m16, KV, ldkv, s);
+    if (st != HDF_OK) return st;
+  }
   HIPCHK(hipEventRecord(h->ev_mv[3], s));
   h->mv_timed = true;
   return HDF_OK;
@@ -1111,7 +1240,10 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   info->center_radius = h->geo.R;
   info->rho2_min = h->u0;
   info->rho2_max = h->u1;
-  info->factor_bytes = (int64_t)((h->H + h->S) * (h->ldN + (h->cross ? h->ldN2 : 0)) * h->elem());
+  info->factor_bytes = (int64_t)((h->H + h->S) *
+                                 (h->storage == HDF_STORE_NONE ? h->ldC : h->ldN + (h->cross ? h->ldN2 : 0)) * h->elem());
+  info->storage = h->storage;
+  info->chunk_points = h->storage == HDF_STORE_NONE ? h->chunk : 0;
   info->t_prep_ms = h->t_prep;
   info->t_plan_ms = h->t_plan;
   info->t_gram_ms = h->t_gram;
@@ -1168,6 +1300,7 @@ hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_
                            void* hip_stream) {
   g_err.clear();
   if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  if (h->storage == HDF_STORE_NONE) return fail(HDF_E_ARG, "a matrix-free factor (HDF_STORE_NONE) stores no factor");
   if ((phi_out && ld_phi < h->N) || (q_out && ld_q < h->N)) return fail(HDF_E_ARG, "leading dimension < n");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t el = h->elem();

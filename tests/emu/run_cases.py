@@ -207,6 +207,38 @@ def case_sampled():
     check("sampled guarantee", e <= 1e-4, f"{e:.2e} (rank {inf['rank']}, bound rule {ohdf.build(X, 'gaussian', 0.7, 1e-4)['r']})")
 
 
+def case_mfree():
+    """Matrix-free factor (HDF_STORE_NONE): K~V per chunk against the oracle and the stored factor, on a
+    ragged chunking (three chunks, the last short), with m above the LDS-staged limit, and dF/dl."""
+    X = wl.unit_ball(2345, 3, 71)
+    st = ohdf.build(X, "gaussian", 1.0, 1e-6)
+    Xd = to_dev(X, torch.float64)
+    fs = hdf.Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64)
+    fm = hdf.Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64, storage="none", chunk=1000)
+    inf = fm.info()
+    check("mfree info", inf["storage"] == 1 and inf["chunk_points"] == 1000 and inf["rank"] == st["r"],
+          f"storage {inf['storage']} chunk {inf['chunk_points']} rank {inf['rank']}")
+    for m in (1, 17, 70):
+        V = wl.rhs(2345, m, 72 + m)
+        Vd = to_dev(V, torch.float64)
+        km = fm.matvec(Vd).numpy()
+        e1 = rel(km, ohdf.matvec(st, V))
+        e2 = rel(km, fs.matvec(Vd).numpy())
+        check(f"mfree matvec m={m}", e1 <= 1e-12 and e2 <= 1e-13, f"vs oracle {e1:.2e}, vs stored {e2:.2e}")
+    W = wl.rhs(2345, 2, 80)
+    V = wl.rhs(2345, 2, 81)
+    dlm, _ = fm.backward(to_dev(W, torch.float64), to_dev(V, torch.float64), need_x=False)
+    dls, _ = fs.backward(to_dev(W, torch.float64), to_dev(V, torch.float64), need_x=False)
+    check("mfree dF/dl", abs(dlm - dls) <= 1e-12 * abs(dls), f"{dlm:.12e} vs {dls:.12e}")
+    Xf = wl.uniform_cube(1013, 4, 104).astype(np.float32)
+    fm32 = hdf.Factor(to_dev(Xf, torch.float32), "gaussian", 0.7, 1e-5, precision=hdf.HDF_MIXED, storage="none",
+                      chunk=300)
+    fs32 = hdf.Factor(to_dev(Xf, torch.float32), "gaussian", 0.7, 1e-5, precision=hdf.HDF_MIXED)
+    V = wl.rhs(1013, 5, 82).astype(np.float32)
+    e = rel(fm32.matvec(to_dev(V, torch.float32)).numpy(), fs32.matvec(to_dev(V, torch.float32)).numpy())
+    check("mfree mixed vs stored", e <= 1e-6, f"{e:.2e}")
+
+
 def case_krr():
     """KRR consumer: k-means, the system operator, the preconditioner, CG and the dense kernel matvec
     against the oracle, on a ragged d = 3 cloud (one cluster left empty) and a d = 8 housing-shaped one."""
@@ -258,7 +290,7 @@ def case_krr():
 
 
 CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
-         "krr": case_krr}
+         "krr": case_krr, "mfree": case_mfree}
 
 if __name__ == "__main__":
     _install()
