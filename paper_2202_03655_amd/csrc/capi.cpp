@@ -11,6 +11,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,22 +29,133 @@ hdf_status fail(hdf_status s, const std::string& msg) {
   return s;
 }
 
+// Caching device allocator.  A build allocates gigabytes (the stored factor)
+// and hipMalloc / hipFree of that size cost about a millisecond each, so freed
+// blocks are kept per device and reused for requests of the same size class
+// (a block serves requests down to 80 % of its size).  Blocks are returned
+// only when no enqueued work can still use them: the handle destructor waits
+// for the device first, and a buffer that grows waits before giving back its
+// old block.  When hipMalloc fails, the device's cached blocks are released
+// and the allocation is tried again.  The cache holds at most a quarter of
+// the device memory; it lives until the process ends.
+#ifndef HDF_ALLOC_CACHE
+#define HDF_ALLOC_CACHE 1      // 0: exact-size hipMalloc / hipFree (the CPU emulation's memory checks)
+#endif
+namespace pool {
+struct Block {
+  void* p;
+  int dev;
+};
+std::mutex& mu() {
+  static std::mutex* m = new std::mutex;
+  return *m;
+}
+std::multimap<size_t, Block>& blocks() {
+  static auto* b = new std::multimap<size_t, Block>;
+  return *b;
+}
+std::map<int, size_t>& cached() {
+  static auto* c = new std::map<int, size_t>;
+  return *c;
+}
+size_t size_class(size_t b) {
+  const size_t g = (size_t)2 << 20;
+  return b < g ? (b + 255) / 256 * 256 : (b + g - 1) / g * g;
+}
+void trim(int dev) {
+  std::lock_guard<std::mutex> lk(mu());
+  for (auto it = blocks().begin(); it != blocks().end();) {
+    if (it->second.dev == dev) {
+      hipFree(it->second.p);
+      cached()[dev] -= it->first;
+      it = blocks().erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+hipError_t alloc(void** p, size_t b, size_t* got, int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (!HDF_ALLOC_CACHE) {
+    e = hipMalloc(p, b);
+    *got = e == hipSuccess ? b : 0;
+    *dev_out = dev;
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+  }
+  const size_t want = size_class(b);
+  {
+    std::lock_guard<std::mutex> lk(mu());
+    for (auto it = blocks().lower_bound(want); it != blocks().end() && it->first <= want + want / 4; ++it) {
+      if (it->second.dev != dev) continue;
+      *p = it->second.p;
+      *got = it->first;
+      *dev_out = dev;
+      cached()[dev] -= it->first;
+      blocks().erase(it);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, want);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    trim(dev);
+    e = hipMalloc(p, want);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return e;
+  }
+  *got = want;
+  *dev_out = dev;
+  return hipSuccess;
+}
+void release(void* p, size_t bytes, int dev) {
+  if (!HDF_ALLOC_CACHE) {
+    hipFree(p);
+    return;
+  }
+  static size_t cap = 0;
+  std::lock_guard<std::mutex> lk(mu());
+  if (!cap) {
+    size_t f = 0, t = 0;
+    cap = (hipMemGetInfo(&f, &t) == hipSuccess && t) ? t / 4 : ((size_t)16 << 30);
+  }
+  if (cached()[dev] + bytes > cap) {
+    hipFree(p);
+    return;
+  }
+  blocks().insert({bytes, Block{p, dev}});
+  cached()[dev] += bytes;
+}
+size_t cached_bytes(int dev) {
+  std::lock_guard<std::mutex> lk(mu());
+  return cached()[dev];
+}
+}  // namespace pool
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  int dev = 0;
   ~DevBuf() { release(); }
   void release() {
-    if (p) hipFree(p);
+    if (p) pool::release(p, bytes, dev);
     p = nullptr;
     bytes = 0;
   }
   hipError_t ensure(size_t b) {
     if (b <= bytes && p) return hipSuccess;
-    release();
-    hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
-    if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
-    else p = nullptr;
-    return e;
+    if (p) {
+      // work enqueued on the old block may still run
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      release();
+    }
+    return pool::alloc(&p, std::max<size_t>(b, 256), &bytes, &dev);
   }
 };
 
@@ -102,6 +214,9 @@ struct hdf_factor {
   // LDS-staged pass 1: items (degree, 16-row tile, column tile), groups
   DevBuf items_dev, gitems_dev, gq_dev;
   int items_cpl = 0, n_groups = 0, max_nq = 0;
+  // host copies of the pass-1 tables: they outlive their asynchronous uploads
+  std::vector<hdf::TileDev> tiles_host, items_host;
+  std::vector<int32_t> gi_host, gq_host;
   // matvec / adjoint workspace
   DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
   DevBuf cphi, cq;                                // matrix-free chunk scratch
@@ -112,6 +227,8 @@ struct hdf_factor {
   DevBuf adj_src, adj_kinfo, adj_stream;
   hdf::BuildTables tables{};
   ~hdf_factor() {
+    // the device buffers go back to the allocator cache once no enqueued work can use them
+    (void)hipDeviceSynchronize();
     if (ev_b0) hipEventDestroy(ev_b0);
     if (ev_b1) hipEventDestroy(ev_b1);
     for (auto& e : ev_mv)
@@ -228,6 +345,10 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   const size_t fbytes = (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->elem();
   size_t freeb = 0, totb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totb));
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) freeb += pool::cached_bytes(dev);   // reusable blocks
+  }
   const size_t budget = std::max<size_t>((size_t)1 << 30, (size_t)(0.6 * (double)freeb));
   if (fbytes > budget) {
     char buf[200];
@@ -899,7 +1020,8 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
   const int max_nct = h->max_s * cpl;
   if (h->tiles_cpl != cpl) {
     // work items: (degree, row block, column slice), no empty slices
-    std::vector<hdf::TileDev> tiles;
+    std::vector<hdf::TileDev>& tiles = h->tiles_host;
+    tiles.clear();
     const int nct = hdf::matvec_col_tiles(h->prec);
     for (size_t di = 0; di < h->degs.size(); ++di)
       for (int h0 = 0; h0 < h->degs[di].nh; h0 += hdf::matvec_row_block())
@@ -908,7 +1030,6 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
     HIPCHK(h->tiles_dev.ensure(tiles.size() * sizeof(hdf::TileDev)));
     HIPCHK(hipMemcpyAsync(h->tiles_dev.p, tiles.data(), tiles.size() * sizeof(hdf::TileDev),
                           hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
     h->n_tiles = (int)tiles.size();
     h->tiles_cpl = cpl;
   }
@@ -917,7 +1038,8 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
   if (m16 <= 64) {
     // LDS-staged variant: B operand staged once per workgroup and chunk
     if (h->items_cpl != cpl) {
-      std::vector<hdf::TileDev> items;
+      std::vector<hdf::TileDev>& items = h->items_host;
+      items.clear();
       for (size_t di = 0; di < h->degs.size(); ++di)
         for (int h0 = 0; h0 < h->degs[di].nh; h0 += 16)
           for (int ct = 0; ct < h->degs[di].s * cpl; ++ct) items.push_back(hdf::TileDev{(int32_t)di, h0, ct, 0});
@@ -926,7 +1048,10 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
       int per = hdf::matvec_items_per_group();
       const int64_t max_splits = std::min<int64_t>((n + 255) / 256, 1024);
       while (per > 4 && (int64_t)((items.size() + per - 1) / per) * max_splits < 512) per /= 2;
-      std::vector<int32_t> gi, gq;
+      std::vector<int32_t>& gi = h->gi_host;
+      std::vector<int32_t>& gq = h->gq_host;
+      gi.clear();
+      gq.clear();
       int max_nq = 0;
       for (size_t i0 = 0; i0 < items.size(); i0 += per) {
         const size_t i1 = std::min(items.size(), i0 + per);
@@ -944,7 +1069,6 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
       HIPCHK(hipMemcpyAsync(h->items_dev.p, items.data(), items.size() * sizeof(hdf::TileDev), hipMemcpyHostToDevice, s));
       HIPCHK(hipMemcpyAsync(h->gitems_dev.p, gi.data(), gi.size() * 4, hipMemcpyHostToDevice, s));
       HIPCHK(hipMemcpyAsync(h->gq_dev.p, gq.data(), gq.size() * 4, hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
       h->n_groups = (int)gi.size() - 1;
       h->max_nq = max_nq;
       h->items_cpl = cpl;

@@ -39,6 +39,7 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipMemGetInfo(size_t* f, size_t* t);
+hipError_t hipGetDevice(int* d);
 hipError_t hipGetLastError();
 const char* hipGetErrorString(hipError_t e);
 void emu_flush();

@@ -481,6 +481,7 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
   return hipSuccess;
 }
 hipError_t hipMemGetInfo(size_t* f, size_t* t) { *f = (size_t)200 << 30; *t = (size_t)288 << 30; return hipSuccess; }
+hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
 hipError_t hipGetLastError() { hipError_t e = emu::g_last; emu::g_last = hipSuccess; return e; }
 const char* hipGetErrorString(hipError_t e) { return e ? "emulated error" : "no error"; }
 void emu_flush() { emu::flush(); }
