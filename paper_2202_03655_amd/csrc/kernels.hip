@@ -379,33 +379,35 @@ __device__ __forceinline__ void radial_point(const Tin* __restrict__ x_soa, int6
 // 16g..16g+15) supplies point tile*16 + g + 4e, lane r of the group supplies
 // row / column index r of the two operands.  Any bijection between (g, e)
 // and the 16 points is valid because the points are summed over.
-template <typename Tin, int MODE>
+// NRT x NCT moment tiles (rows k < 16 NRT, columns c < 16 NCT) are compile-time
+// sizes, so the accumulators of unused tiles take no registers.
+template <typename Tin, int MODE, int NRT, int NCT>
 __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
                                                int d, const GeoDev* __restrict__ geo, double u0,
-                                               double u1, int K, int nrt, int nct,
-                                               double* __restrict__ part) {
+                                               double u1, int K, double* __restrict__ part) {
+  constexpr int nrt = NRT, nct = NCT;
   typedef typename std::conditional<MODE == 0, double, float>::type T;
   typedef typename Mfma<T>::V V;
   __shared__ double sh[4][4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const double Reff = geo->Reff;
-  double dacc[kGramRowTiles][kGramColTiles][4];
+  double dacc[NRT][NCT][4];
 #pragma unroll
-  for (int a = 0; a < kGramRowTiles; ++a)
+  for (int a = 0; a < NRT; ++a)
 #pragma unroll
-    for (int b = 0; b < kGramColTiles; ++b)
+    for (int b = 0; b < NCT; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) dacc[a][b][e] = 0.0;
   const int64_t ntile = (n + 15) / 16;
   int since_flush = 0;
-  V acc[kGramRowTiles][kGramColTiles];
+  V acc[NRT][NCT];
 #pragma unroll
-  for (int a = 0; a < kGramRowTiles; ++a)
+  for (int a = 0; a < NRT; ++a)
 #pragma unroll
-    for (int b = 0; b < kGramColTiles; ++b) acc[a][b] = V{0, 0, 0, 0};
+    for (int b = 0; b < NCT; ++b) acc[a][b] = V{0, 0, 0, 0};
   for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
-    double t[4], w[kGramRowTiles][4], tc[kGramColTiles][4];
+    double t[4], w[NRT][4], tc[NCT][4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t i = tile * 16 + g + 4 * e;
@@ -413,7 +415,7 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
       if (i < n) radial_point(x_soa, ldx, i, d, geo, Reff, u0, u1, rho2, tt);
       t[e] = tt;
 #pragma unroll
-      for (int a = 0; a < kGramRowTiles; ++a) {
+      for (int a = 0; a < NRT; ++a) {
         const int k = a * 16 + li;
         double pw = 0.0;
         if (i < n && a < nrt && k <= K) {
@@ -432,7 +434,7 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
 #pragma unroll
     for (int e = 0; e < 4; ++e) { tm1[e] = 1.0; t0[e] = t[e]; }
 #pragma unroll
-    for (int b = 0; b < kGramColTiles; ++b) {
+    for (int b = 0; b < NCT; ++b) {
       if (b >= nct) break;
 #pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
@@ -451,10 +453,10 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
     for (int e = 0; e < 4; ++e) {
       const int64_t i = tile * 16 + g + 4 * e;
 #pragma unroll
-      for (int a = 0; a < kGramRowTiles; ++a) {
+      for (int a = 0; a < NRT; ++a) {
         if (a >= nrt) continue;
 #pragma unroll
-        for (int b = 0; b < kGramColTiles; ++b) {
+        for (int b = 0; b < NCT; ++b) {
           if (b >= nct) continue;
           const double wv = (i < n) ? w[a][e] : 0.0;
           if constexpr (MODE == 2) {
@@ -473,9 +475,9 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
     if (MODE != 0 && ++since_flush == 4) {
       since_flush = 0;
 #pragma unroll
-      for (int a = 0; a < kGramRowTiles; ++a)
+      for (int a = 0; a < NRT; ++a)
 #pragma unroll
-        for (int b = 0; b < kGramColTiles; ++b) {
+        for (int b = 0; b < NCT; ++b) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) dacc[a][b][e] += (double)acc[a][b][e];
           acc[a][b] = V{0, 0, 0, 0};
@@ -483,18 +485,18 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
     }
   }
 #pragma unroll
-  for (int a = 0; a < kGramRowTiles; ++a)
+  for (int a = 0; a < NRT; ++a)
 #pragma unroll
-    for (int b = 0; b < kGramColTiles; ++b)
+    for (int b = 0; b < NCT; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) dacc[a][b][e] += (double)acc[a][b][e];
   // combine the four waves in a fixed order, one 16x16 tile at a time
   const int rows = nrt * 16, cols = nct * 16;
   double* out = part + (int64_t)blockIdx.x * rows * cols;
 #pragma unroll
-  for (int a = 0; a < kGramRowTiles; ++a)
+  for (int a = 0; a < NRT; ++a)
 #pragma unroll
-    for (int b = 0; b < kGramColTiles; ++b) {
+    for (int b = 0; b < NCT; ++b) {
       if (a >= nrt || b >= nct) continue;
       __syncthreads();
 #pragma unroll
@@ -544,9 +546,16 @@ hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int
   const int nrt = (K + 1 + 15) / 16, nct = (2 * K + 1 + 15) / 16;
   if (nrt > kGramRowTiles || nct > kGramColTiles) return hipErrorInvalidValue;
   const int nb = gram_blocks(n);
+#define GRAM_TILES(TIN, MODE, R, C)                                                               \
+  k_gram<TIN, MODE, R, C><<<nb, 256, 0, s>>>((const TIN*)x_soa, ldx, n, d, geo, u0, u1, K, partials)
 #define GRAM_LAUNCH(TIN, MODE)                                                                    \
-  k_gram<TIN, MODE><<<nb, 256, 0, s>>>((const TIN*)x_soa, ldx, n, d, geo, u0, u1, K, nrt, nct, \
-                                       partials)
+  do {                                                                                            \
+    if (nrt == 1 && nct == 1) GRAM_TILES(TIN, MODE, 1, 1);                                         \
+    else if (nrt == 1 && nct == 2) GRAM_TILES(TIN, MODE, 1, 2);                                    \
+    else if (nrt == 2 && nct == 3) GRAM_TILES(TIN, MODE, 2, 3);                                    \
+    else if (nrt == 2 && nct == 4) GRAM_TILES(TIN, MODE, 2, 4);                                    \
+    else return hipErrorInvalidValue;                                                             \
+  } while (0)
   if (dtype == 0) {
     if (mode == 0) GRAM_LAUNCH(float, 0);
     else if (mode == 1) GRAM_LAUNCH(float, 1);
@@ -557,6 +566,7 @@ hipError_t launch_gram(const void* x_soa, int dtype, int64_t ldx, int64_t n, int
     else GRAM_LAUNCH(double, 2);
   }
 #undef GRAM_LAUNCH
+#undef GRAM_TILES
   const int total = nrt * 16 * nct * 16;
   k_gram_fin<<<(total + 63) / 64, 256, 0, s>>>(partials, nb, total, moments);
   return hipGetLastError();
