@@ -1584,15 +1584,17 @@ __global__ void k_mv_reduce(const double* __restrict__ part, int n_splits, int64
 }
 
 // Pass 2, KV = U (D W).  One wavefront owns 64 points and one 16-column
-// chunk of the right-hand sides; per degree it forms Z[i][(l,c)] =
-// sum_h phi_h(i) Wd[(k,h,l)][c] on MFMA (reduction over harmonics) and folds
-// Z into KV with the radial functions q_{k,l}(i).  MFMA row i of point tile
-// u is point p0 + 4 i + u, so each lane reads 4 consecutive points of a
-// harmonic row with one 16-byte load.  With hchunk > 0 (few points, many
-// harmonics) blockIdx.z takes the harmonic rows [z hchunk, (z+1) hchunk)
-// only and writes its share of KV to part[z][n][m]; k_mv_n_sum adds the
-// shares in z order.
-template <typename T, int NCT>
+// chunk of the right-hand sides.  The reduction runs over the rank columns
+// (k, h, l) directly: the MFMA A operand is U[i, (k,h,l)] = phi_h(i) q_{k,l}(i),
+// formed in registers from one load of each harmonic row and the point's
+// radial values, and B is row (k,h,l) of D W.  Each harmonic row is read
+// once, and the four accumulators (one per point tile) are the output itself.
+// MFMA row i of point tile u is point p0 + 4 i + u, so each lane reads 4
+// consecutive points of a harmonic (or radial) row with one 16-byte load.
+// With hchunk > 0 (few points, many harmonics) blockIdx.z takes the harmonic
+// rows [z hchunk, (z+1) hchunk) only and writes its share of KV to
+// part[z][n][m]; k_mv_n_sum adds the shares in z order.
+template <typename T>
 __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
                                               const DegDev* __restrict__ degs, int n_deg,
@@ -1602,105 +1604,63 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
   typedef typename Mfma<T>::V Acc;
   const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
   const int64_t p0 = (int64_t)blockIdx.x * 64;
-  const int zlo = hchunk > 0 ? (int)blockIdx.z * hchunk : 0;
-  const int zhi = hchunk > 0 ? zlo + hchunk : 0x7fffffff;
   const int c0 = blockIdx.y * 16;
   const int64_t pa = p0 + 4 * li;                // this lane's four A points
-  T kv[4][4];
+  const int zlo = hchunk > 0 ? (int)blockIdx.z * hchunk : 0;
+  const int zhi = hchunk > 0 ? zlo + hchunk : 0x7fffffff;
+  Acc acc[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 4; ++u) acc[u] = Acc{0, 0, 0, 0};
+  // four consecutive points of a padded row (in bounds up to 63 points past n)
+  auto load4 = [&](const T* row, T (&o)[4]) {
+    if constexpr (sizeof(T) == 4) {
+      const floatx4 w = *reinterpret_cast<const floatx4*>(row + pa);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) kv[u][e] = 0;
+      for (int u = 0; u < 4; ++u) o[u] = w[u];
+    } else {
+      const doublex2 w0 = *reinterpret_cast<const doublex2*>(row + pa);
+      const doublex2 w1 = *reinterpret_cast<const doublex2*>(row + pa + 2);
+      o[0] = w0[0]; o[1] = w0[1]; o[2] = w1[0]; o[3] = w1[1];
+    }
+  };
+  constexpr int KB = 4;                          // K-steps per batch: 16 harmonics
   for (int di = 0; di < n_deg; ++di) {
     const DegDev dg = degs[di];
     // this workgroup's harmonics of the degree: [hlo, hhi)
     const int hlo = zlo > dg.hoff ? zlo - dg.hoff : 0;
     const int hhi = (zhi - dg.hoff) < dg.nh ? zhi - dg.hoff : dg.nh;
     if (hlo >= hhi) continue;
-    for (int l0 = 0; l0 < dg.s; l0 += NCT) {
-      Acc acc[4][NCT];
+    // harmonic rows of a batch (clamped rows, masked values), the next batch in flight
+    auto load_batch = [&](int hb, T (&vv)[KB][4]) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int kb = 0; kb < KB; ++kb) {
+        const int hh = hb + 4 * kb + g;
+        load4(phi + (int64_t)(dg.hoff + (hh < hhi ? hh : hlo)) * ld_phi, vv[kb]);
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = Acc{0, 0, 0, 0};
-      // batches of 4 K-steps (16 harmonics): every load of a batch is issued
-      // before its MFMAs, and the next batch's Phi loads before this batch's
-      // MFMAs (software pipeline)
-      constexpr int KB = 4;
-      T v_nxt[KB][4];
-      auto load_batch = [&](int hb, T (&vv)[KB][4]) {
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const int hh = hb + 4 * kb + g;
-          const T* prow = phi + (int64_t)(dg.hoff + (hh < hhi ? hh : hlo)) * ld_phi;
-          if constexpr (sizeof(T) == 4) {
-            const floatx4 w = *reinterpret_cast<const floatx4*>(prow + pa);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) vv[kb][u] = w[u];
-          } else {
-            const doublex2 w0 = *reinterpret_cast<const doublex2*>(prow + pa);
-            const doublex2 w1 = *reinterpret_cast<const doublex2*>(prow + pa + 2);
-            vv[kb][0] = w0[0]; vv[kb][1] = w0[1]; vv[kb][2] = w1[0]; vv[kb][3] = w1[1];
-          }
-        }
-      };
-      // B operands (rows of D W) of a batch, fetched together with its Phi rows
-      auto load_w = [&](int hb, T (&bb)[KB][NCT]) {
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const int hh = hb + 4 * kb + g;
-          const T* wrow = Wd + (int64_t)(dg.roff + (hh < hhi ? hh : hlo) * dg.s) * m16 + c0 + li;
-          const T hmask = hh < hhi ? (T)1 : (T)0;
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) {
-            const int l = l0 + ct;
-            bb[kb][ct] = (l < dg.s) ? wrow[(int64_t)(l < dg.s ? l : 0) * m16] * hmask : (T)0;
-          }
-        }
-      };
-      T w_nxt[KB][NCT];
-      load_batch(hlo, v_nxt);
-      load_w(hlo, w_nxt);
-      for (int hb = hlo; hb < hhi; hb += 4 * KB) {
-        T v[KB][4], bw[KB][NCT];
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) v[kb][u] = v_nxt[kb][u];
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) bw[kb][ct] = w_nxt[kb][ct];
-        }
-        if (hb + 4 * KB < hhi) {
-          load_batch(hb + 4 * KB, v_nxt);
-          load_w(hb + 4 * KB, w_nxt);
-        }
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const int hh = hb + 4 * kb + g;
-          T a[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) a[u] = (hh < hhi && pa + u < n) ? v[kb][u] : (T)0;
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) {
-            if (l0 + ct >= dg.s) break;           // uniform: live radial functions only
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u][ct] = Mfma<T>::run(a[u], bw[kb][ct], acc[u][ct]);
-          }
-        }
+        for (int u = 0; u < 4; ++u) vv[kb][u] = (hh < hhi && pa + u < n) ? vv[kb][u] : (T)0;
       }
+    };
+    T v_nxt[KB][4];
+    load_batch(hlo, v_nxt);
+    for (int hb = hlo; hb < hhi; hb += 4 * KB) {
+      T v[KB][4];
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) {
-        const int l = l0 + ct;
-        if (l >= dg.s) continue;
-        const T* qrow = q + (int64_t)(dg.qoff + l) * ld_q;
+      for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) v[kb][u] = v_nxt[kb][u];
+      if (hb + 4 * KB < hhi) load_batch(hb + 4 * KB, v_nxt);
+      for (int l = 0; l < dg.s; ++l) {
+        T ql[4], bw[KB];
+        load4(q + (int64_t)(dg.qoff + l) * ld_q, ql);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t pt = p0 + 4 * Mfma<T>::row(g, e) + u;
-            const T ql = qrow[pt];                // padded row: in bounds
-            kv[u][e] += ((pt < n) ? ql : (T)0) * acc[u][ct][e];
-          }
+        for (int kb = 0; kb < KB; ++kb) {
+          const int hh = hb + 4 * kb + g;
+          bw[kb] = Wd[(int64_t)(dg.roff + (hh < hhi ? hh : hlo) * dg.s + l) * m16 + c0 + li];
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] = Mfma<T>::run(v[kb][u] * ql[u], bw[kb], acc[u]);
       }
     }
   }
@@ -1713,7 +1673,7 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t pt = p0 + 4 * Mfma<T>::row(g, e) + u;
-        if (pt < n) dst[pt * ld + c] = kv[u][e];
+        if (pt < n) dst[pt * ld + c] = acc[u][e];
       }
   }
 }
@@ -1730,8 +1690,8 @@ __global__ void __launch_bounds__(256) k_mv_n_sum(const T* __restrict__ part, in
   KV[pt * ldkv + c] = s;
 }
 
-constexpr int kMvNctF = 4;   // column tiles per pass, binary32
-constexpr int kMvNctD = 2;   // column tiles per pass, binary64
+constexpr int kMvNctF = 4;   // column tiles per item of k_mv_t, binary32
+constexpr int kMvNctD = 2;   // column tiles per item of k_mv_t, binary64
 
 int matvec_row_block() { return 16 * kMvtRowTiles; }
 int matvec_col_tiles(int prec) { return prec == 1 ? kMvNctF : kMvNctD; }
@@ -1777,14 +1737,13 @@ hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64
   const unsigned nb = (unsigned)((n * m + 255) / 256);
   if (prec == 1) {
     float* dst = nz > 1 ? (float*)part : nullptr;
-    k_mv_n<float, kMvNctF><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
-                                              n_deg, (const float*)Wd, m16, (float*)KV, ldkv, n, m, hc, dst);
+    k_mv_n<float><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs, n_deg,
+                                      (const float*)Wd, m16, (float*)KV, ldkv, n, m, hc, dst);
     if (nz > 1) k_mv_n_sum<float><<<nb, 256, 0, s>>>((const float*)part, nz, n, m, (float*)KV, ldkv);
   } else {
     double* dst = nz > 1 ? (double*)part : nullptr;
-    k_mv_n<double, kMvNctD><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
-                                               degs, n_deg, (const double*)Wd, m16, (double*)KV,
-                                               ldkv, n, m, hc, dst);
+    k_mv_n<double><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q, degs, n_deg,
+                                       (const double*)Wd, m16, (double*)KV, ldkv, n, m, hc, dst);
     if (nz > 1) k_mv_n_sum<double><<<nb, 256, 0, s>>>((const double*)part, nz, n, m, (double*)KV, ldkv);
   }
   return hipGetLastError();
