@@ -384,7 +384,8 @@ hdf_status hdf_krr_info(hdf_krr_handle h, hdf_krr_info_t* info);
 
 /* The factor of cluster c (NULL for an empty cluster), owned by the KRR
  * handle; usable with hdf_info, hdf_get_plan, hdf_copy_factor and
- * hdf_matvec (its points are the members of c in increasing caller index). */
+ * hdf_matvec (its points are the members of c in increasing caller index).
+ * Its products are not timed: hdf_info reports -1 for their kernel times. */
 hdf_status hdf_krr_block(hdf_krr_handle h, int c, hdf_handle* block);
 
 void hdf_krr_free(hdf_krr_handle h);

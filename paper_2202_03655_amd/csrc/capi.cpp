@@ -172,6 +172,7 @@ hdf_status set_error(hdf_status s, const std::string& msg) { return fail(s, msg)
 void clear_error() { g_err.clear(); }
 }  // namespace hdf
 
+
 struct hdf_factor {
   int d = 0, prec = 0, dtype = 0, kernel = 0;
   int64_t N = 0, ldN = 0;
@@ -207,6 +208,7 @@ struct hdf_factor {
   hipEvent_t ev_mv[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_adj[2] = {nullptr, nullptr};
   bool mv_timed = false, adj_timed = false;
+  bool time_products = true;                      // HIP events around the product's kernels
   // device storage
   DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
       lam_row, moments;
@@ -238,6 +240,8 @@ struct hdf_factor {
   }
   size_t elem() const { return prec == HDF_MIXED ? 4 : 8; }
 };
+
+void hdf::set_product_timing(hdf_factor* h, bool on) { h->time_products = on; }
 
 // dF/dX (k_adj_pack + k_adjoint) is compiled but not dispatched unless enabled.
 #ifndef HDF_ADJOINT_KERNEL
@@ -1160,7 +1164,8 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
     return HDF_OK;
   }
   const int m16 = (int)((m + 15) / 16 * 16);
-  hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, true);
+  const bool timed = h->time_products;
+  hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, timed);
   if (st != HDF_OK) return st;
   if (h->storage == HDF_STORE_NONE) {
     for (int64_t c0 = 0; c0 < n; c0 += h->chunk) {
@@ -1174,8 +1179,10 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
     st = pass2(h, h->phi.p, h->q.p, h->ldN, n, m, m16, KV, ldkv, s);
     if (st != HDF_OK) return st;
   }
-  HIPCHK(hipEventRecord(h->ev_mv[3], s));
-  h->mv_timed = true;
+  if (timed) {
+    HIPCHK(hipEventRecord(h->ev_mv[3], s));
+    h->mv_timed = true;
+  }
   return HDF_OK;
 }
 

@@ -289,6 +289,7 @@ hdf_status hdf_krr_create(const double* points, int64_t n, int d, int64_t ld, co
                               hip_stream, &h->fac[c]);
     if (st != HDF_OK)
       return hdf::set_error(st, "factor of cluster " + std::to_string(c) + ": " + hdf_last_error());
+    hdf::set_product_timing(h->fac[c], false);
   }
   h->t_factor = now_ms() - t0;
   // preconditioner: dense blocks, Cholesky, inverses
