@@ -216,6 +216,8 @@ struct hdf_factor {
   // LDS-staged pass 1: items (degree, 16-row tile, column tile), groups
   DevBuf items_dev, gitems_dev, gq_dev;
   int items_cpl = 0, n_groups = 0, max_nq = 0;
+  // host copies of uploaded build tables: they outlive their asynchronous uploads
+  std::vector<std::vector<char>> host_keep;
   // host copies of the pass-1 tables: they outlive their asynchronous uploads
   std::vector<hdf::TileDev> tiles_host, items_host;
   std::vector<int32_t> gi_host, gq_host;
@@ -396,8 +398,15 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       for (size_t di = 0; di < f->degs.size(); ++di)
         f->adj_kinfo_host[f->kept_k[di]] = hdf::KInfo{f->degs[di].s, f->degs[di].qoff};
     }
-    HIPCHK(f->col_of.ensure(col_of.size() * sizeof(int32_t)));
-    HIPCHK(hipMemcpyAsync(f->col_of.p, col_of.data(), col_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // uploads from copies the handle keeps, so no synchronisation is needed before the
+    // host vectors below go out of scope
+    auto upload = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
+      hipError_t e = b.ensure(bytes);
+      if (e != hipSuccess) return e;
+      f->host_keep.emplace_back((const char*)src, (const char*)src + bytes);
+      return hipMemcpyAsync(b.p, f->host_keep.back().data(), bytes, hipMemcpyHostToDevice, s);
+    };
+    HIPCHK(upload(f->col_of, col_of.data(), col_of.size() * sizeof(int32_t)));
     // recurrence coefficients as (A, B) pairs in the storage type
     hdf::ChainCoeffs cc;
     hdf::chain_coeffs(d, Kh, cc);
@@ -421,28 +430,17 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     auto upload_typed = [&](DevBuf& b, const std::vector<double>& v) -> hipError_t {
       if (f->prec == HDF_MIXED) {
         std::vector<float> tmp(v.begin(), v.end());
-        hipError_t e = b.ensure(tmp.size() * 4);
-        if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(b.p, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return e;
-        return hipStreamSynchronize(s);      // tmp goes out of scope
+        return upload(b, tmp.data(), tmp.size() * 4);
       }
-      hipError_t e = b.ensure(v.size() * 8);
-      if (e != hipSuccess) return e;
-      e = hipMemcpyAsync(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s);
-      if (e != hipSuccess) return e;
-      return hipStreamSynchronize(s);
+      return upload(b, v.data(), v.size() * 8);
     };
     HIPCHK(upload_typed(f->chain, pd));
     HIPCHK(upload_typed(f->q_coef, qc));
     if (f->cross) HIPCHK(upload_typed(f->q_coef2, qc2));
-    HIPCHK(f->q_len.ensure(ql.size() * 4));
-    HIPCHK(f->q_off.ensure(qo.size() * 4));
-    HIPCHK(hipMemcpyAsync(f->q_len.p, ql.data(), ql.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(f->q_off.p, qo.data(), qo.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(upload(f->q_len, ql.data(), ql.size() * 4));
+    HIPCHK(upload(f->q_off, qo.data(), qo.size() * 4));
     // contraction tables
-    HIPCHK(f->degs_dev.ensure(f->degs.size() * sizeof(hdf::DegDev)));
-    HIPCHK(hipMemcpyAsync(f->degs_dev.p, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
+    HIPCHK(upload(f->degs_dev, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev)));
     std::vector<double> lr;
     lr.reserve(f->r);
     for (size_t di = 0; di < f->degs.size(); ++di) {
@@ -450,9 +448,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       for (int h = 0; h < f->degs[di].nh; ++h)
         for (int l = 0; l < df.s; ++l) lr.push_back(f->cross ? 1.0 : df.lam[l]);
     }
-    HIPCHK(f->lam_row.ensure(lr.size() * 8));
-    HIPCHK(hipMemcpyAsync(f->lam_row.p, lr.data(), lr.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
+    HIPCHK(upload(f->lam_row, lr.data(), lr.size() * 8));
 
     hdf::BuildTables tb{};
     tb.col_of = (const int32_t*)f->col_of.p;
@@ -466,9 +462,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     std::vector<hdf::DegDev> dbk(K + 1);
     for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
     for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
-    HIPCHK(f->degs_by_k.ensure(dbk.size() * sizeof(hdf::DegDev)));
-    HIPCHK(hipMemcpyAsync(f->degs_by_k.p, dbk.data(), dbk.size() * sizeof(hdf::DegDev), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(upload(f->degs_by_k, dbk.data(), dbk.size() * sizeof(hdf::DegDev)));
     if (mfree) return HDF_OK;                   // evaluated chunk by chunk in every product
     HIPCHK(hipEventCreate(&f->ev_b0));
     HIPCHK(hipEventCreate(&f->ev_b1));
