@@ -1399,7 +1399,22 @@ constexpr int kMvStage = 8;
 template <typename T>
 struct MvtBatch { static constexpr int value = 2; };
 
-template <typename T>
+// Eight consecutive staged radial values (16-byte aligned in LDS) with wide LDS reads.
+__device__ __forceinline__ void lds_read8(const float* p, float (&v)[8]) {
+  const floatx4 a = *reinterpret_cast<const floatx4*>(p), b = *reinterpret_cast<const floatx4*>(p + 4);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) { v[t] = a[t]; v[4 + t] = b[t]; }
+}
+__device__ __forceinline__ void lds_read8(const double* p, double (&v)[8]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const double2 a = *reinterpret_cast<const double2*>(p + 2 * t);
+    v[2 * t] = a[0];
+    v[2 * t + 1] = a[1];
+  }
+}
+
+template <typename T, int CPL>
 __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int64_t ld_phi,
                                                    const T* __restrict__ q, int64_t ld_q,
                                                    const DegDev* __restrict__ degs,
@@ -1418,7 +1433,8 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
   const int vst = m16 + 1;                        // padded V row (bank spread)
   const int half = kMvCH * vst + max_nq * kMvCH;  // one buffer: V then q
   T* lds = reinterpret_cast<T*>(smem_raw);        // [2][half]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: item branches stay scalar
   const int cpl = m16 / 16;
   // a group of up to 4 * kMvTPW items is split evenly over the four wavefronts
   const int ipw = (it1 - it0 + 3) / 4;
@@ -1465,16 +1481,31 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
       if (e < kMvCH * nq) buf[kMvCH * vst + e] = sq[j];
     }
   };
-  // Phi rows of items [b0, b0 + NB) at chunk p (clamped, in-bounds rows;
-  // callers guarantee n_mine > 0 so every descriptor read is initialised)
+  // Phi rows of items [b0, b0 + NB) at chunk p, loaded without masks: a lane
+  // past its degree's last harmonic reads the tile's first row (its output
+  // rows are never written), an item past n_mine repeats the first item, and
+  // points past the split meet a zero B operand.  Every load is in bounds:
+  // p is a multiple of 32 below n and the rows are padded to at least the
+  // next multiple of 64 plus 64 columns.
+  int64_t prow[kMvTPW];                           // element offsets from phi (global loads, not flat)
   auto load_batch = [&](int64_t p, int b0, T (&a)[NB][8]) {
     const int64_t pb = p + 8 * g;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int i = b0 + j;
-      const int di = wbase + (i < n_mine ? i : 0);
-      const bool ok = (i < n_mine) && li < d_nr[di];
-      load8(phi + (d_row[di] + (ok ? li : 0)) * ld_phi, pb, p_end, ok, a[j]);
+      const T* r = phi + (prow[b0 + j] + pb);
+      if constexpr (sizeof(T) == 4) {
+        const floatx4 v0 = *reinterpret_cast<const floatx4*>(r);
+        const floatx4 v1 = *reinterpret_cast<const floatx4*>(r + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { a[j][e] = v0[e]; a[j][4 + e] = v1[e]; }
+      } else {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const doublex2 w = *reinterpret_cast<const doublex2*>(r + 2 * h);
+          a[j][2 * h] = w[0];
+          a[j][2 * h + 1] = w[1];
+        }
+      }
     }
   };
 
@@ -1483,6 +1514,16 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
   for (int i = 0; i < kMvTPW; ++i) acc[i] = Acc{0, 0, 0, 0};
   stage_load(p_begin);
   __syncthreads();                                // descriptors visible
+  // per-item row pointers and radial-row offsets, held in registers for the whole point range
+  int rq[kMvTPW];
+#pragma unroll
+  for (int i = 0; i < kMvTPW; ++i) {
+    const bool any = n_mine > 0;
+    const int di = wbase + (i < n_mine ? i : 0);
+    const int nr = any ? d_nr[di] : 1;
+    prow[i] = ((any ? d_row[di] : 0) + (li < nr ? li : 0)) * ld_phi;
+    rq[i] = (any ? d_qr[di] : kMvCH * vst) + 8 * g;
+  }
   stage_store(lds);
   T a_cur[NB][8], a_nxt[NB][8];
   if (n_mine > 0) load_batch(p_begin, 0, a_cur);
@@ -1493,6 +1534,13 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
     const bool has_next = pn < p_end;             // uniform
     if (has_next) stage_load(pn);
     const T* cur = lds + buf * half;
+    // CPL > 0: this lane's V values of the chunk (points 8 g + t, column 16 cc + li), shared by the
+    // items; CPL == 0: every item reads its V values from LDS
+    T vr[CPL > 0 ? CPL : 1][8];
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) vr[cc][t] = cc < cpl ? cur[(8 * g + t) * vst + 16 * cc + li] : (T)0;
     if (n_mine > 0) {                             // uniform
 #pragma unroll
       for (int b0 = 0; b0 < kMvTPW; b0 += NB) {
@@ -1501,15 +1549,36 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
           // the next chunk (re-reads this chunk's first batch at the end)
           const bool same = b0 + NB < n_mine;
           load_batch(same ? p : (has_next ? pn : p), same ? b0 + NB : 0, a_nxt);
+          if constexpr (CPL > 0) {
+            // the batch's radial values first (offsets of items past n_mine are valid), so one
+            // wait covers the LDS reads of the whole batch
+            T q8[NB][8];
 #pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const int i = b0 + j;
-            if (i < n_mine) {                     // uniform
-              const int di = wbase + i;
-              const T* qb = cur + d_qr[di] + 8 * g;
-              const T* vb = cur + (8 * g) * vst + d_c[di] + li;
+            for (int j = 0; j < NB; ++j) lds_read8(cur + rq[b0 + j], q8[j]);
 #pragma unroll
-              for (int t = 0; t < 8; ++t) acc[i] = Mfma<T>::run(a_cur[j][t], qb[t] * vb[t * vst], acc[i]);
+            for (int j = 0; j < NB; ++j) {
+              const int i = b0 + j;
+              if (i < n_mine) {                   // uniform
+                const int ci = CPL > 1 ? d_c[wbase + i] >> 4 : 0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                  T v = vr[0][t];
+#pragma unroll
+                  for (int cc = 1; cc < CPL; ++cc) v = ci == cc ? vr[cc][t] : v;
+                  acc[i] = Mfma<T>::run(a_cur[j][t], q8[j][t] * v, acc[i]);
+                }
+              }
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              const int i = b0 + j;
+              if (i < n_mine) {                   // uniform
+                const T* qb = cur + rq[i];
+                const T* vb = cur + (8 * g) * vst + d_c[wbase + i] + li;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) acc[i] = Mfma<T>::run(a_cur[j][t], qb[t] * vb[t * vst], acc[i]);
+              }
             }
           }
 #pragma unroll
@@ -1553,14 +1622,17 @@ hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, i
                                int64_t rank, double* partials, int prec, hipStream_t s) {
   const dim3 grid(n_splits, n_groups);
   const size_t lds = matvec_lds_bytes(m16, max_nq, prec);
-  if (prec == 1)
-    k_mv_t_lds<float><<<grid, 256, lds, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs, items,
-                                            group_items, group_q, max_nq, (const float*)V, ldv, n, m, m16,
-                                            split_len, rank, partials);
-  else
-    k_mv_t_lds<double><<<grid, 256, lds, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q, degs,
-                                             items, group_items, group_q, max_nq, (const double*)V, ldv, n, m,
-                                             m16, split_len, rank, partials);
+#define HDF_MVT(T, C)                                                                                        \
+  k_mv_t_lds<T, C><<<grid, 256, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, degs, items, group_items, \
+                                          group_q, max_nq, (const T*)V, ldv, n, m, m16, split_len, rank, partials)
+  // V held in registers where that keeps two wavefronts per SIMD (binary32, one column tile)
+  if (prec == 1) {
+    if (m16 == 16) HDF_MVT(float, 1);
+    else HDF_MVT(float, 0);
+  } else {
+    HDF_MVT(double, 0);
+  }
+#undef HDF_MVT
   return hipGetLastError();
 }
 

@@ -106,5 +106,7 @@ using std::min;
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32(a, b, c)
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu::mfma_f64(a, b, c)
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
+// the kernels apply it only to wave-uniform values, which every lane already holds
+#define __builtin_amdgcn_readfirstlane(x) (x)
 
 #endif

@@ -154,6 +154,10 @@ def case_mixed():
     KV = f.matvec(to_dev(V, torch.float32)).numpy().astype(np.float64)
     e = rel(KV, ohdf.matvec(st, V))
     check("mixed matvec", e <= 1e-5 + 1e-6, f"{e:.2e}")
+    for m in (1, 64):     # one column tile per rank (many distinct row tiles per group); the widest staged B
+        V = wl.rhs(1013, m, 10 + m)
+        e = rel(f.matvec(to_dev(V, torch.float32)).numpy().astype(np.float64), ohdf.matvec(st, V))
+        check(f"mixed matvec m={m}", e <= 1e-5 + 1e-6, f"{e:.2e}")
     W = wl.rhs(1013, 1, 9)
     dl, dX = f.backward(to_dev(W, torch.float32), to_dev(V[:, :1], torch.float32))
     e = rel(dX.numpy().astype(np.float64), ohdf.grad_x(st, W, V[:, :1]))
