@@ -1712,6 +1712,19 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
         for (int u = 0; u < 4; ++u) vv[kb][u] = (hh < hhi && pa + u < n) ? vv[kb][u] : (T)0;
       }
     };
+    // radial values of function l at this lane's points and the batch's rows of D W for l
+    auto load_l = [&](int hb, int l, T (&ql)[4], T (&bw)[KB]) {
+      load4(q + (int64_t)(dg.qoff + l) * ld_q, ql);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int hh = hb + 4 * kb + g;
+        bw[kb] = Wd[(int64_t)(dg.roff + (hh < hhi ? hh : hlo) * dg.s + l) * m16 + c0 + li];
+      }
+    };
+    // binary32 issue order per batch: the operands of l = 0, then the next batch's rows, then
+    // those of l + 1 ahead of l's MFMAs, so no wait of this batch covers the next batch's rows.
+    // binary64 loads l's operands at l (the extra registers would cost a wavefront per SIMD).
+    constexpr bool ahead = sizeof(T) == 4;
     T v_nxt[KB][4];
     load_batch(hlo, v_nxt);
     for (int hb = hlo; hb < hhi; hb += 4 * KB) {
@@ -1720,19 +1733,26 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
       for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[kb][u] = v_nxt[kb][u];
+      T ql[4], bw[KB];
+      if constexpr (ahead) load_l(hb, 0, ql, bw);
       if (hb + 4 * KB < hhi) load_batch(hb + 4 * KB, v_nxt);
       for (int l = 0; l < dg.s; ++l) {
-        T ql[4], bw[KB];
-        load4(q + (int64_t)(dg.qoff + l) * ld_q, ql);
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const int hh = hb + 4 * kb + g;
-          bw[kb] = Wd[(int64_t)(dg.roff + (hh < hhi ? hh : hlo) * dg.s + l) * m16 + c0 + li];
+        T qn[4], bn[KB];
+        if constexpr (ahead) {
+          if (l + 1 < dg.s) load_l(hb, l + 1, qn, bn);
+        } else {
+          load_l(hb, l, ql, bw);
         }
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
           for (int u = 0; u < 4; ++u) acc[u] = Mfma<T>::run(v[kb][u] * ql[u], bw[kb], acc[u]);
+        if constexpr (ahead) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) ql[u] = qn[u];
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) bw[kb] = bn[kb];
+        }
       }
     }
   }
