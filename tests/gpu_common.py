@@ -57,3 +57,33 @@ def oracle_phi(st, kept):
 
 def rel_fro(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def degree_blocks(f):
+    """(k, harmonic offset, |H_k|, radial offset, s_k) of the kept degrees."""
+    inf = f.info()
+    out, h0, q0 = [], 0, 0
+    for k, s in enumerate(inf["s_k"]):
+        if s == 0:
+            continue
+        nh = harmonics.count(f.d, k)
+        out.append((k, h0, nh, q0, s))
+        h0 += nh
+        q0 += s
+    return out
+
+
+def torch_contraction(f, V):
+    """K~V = sum_k sum_l q_kl o (Phi_k^T (lam_kl (Phi_k^T (q_kl o V)))) in
+    binary64 with torch GEMMs on the device factor (no library kernels)."""
+    phi, q = f.factor_parts()
+    lam = torch.tensor(f.plan()["lam"], dtype=torch.float64, device="cuda")
+    Vd = V.double()
+    out = torch.zeros_like(Vd)
+    for k, h0, nh, q0, s in degree_blocks(f):
+        P = phi[h0:h0 + nh].double()                       # nh x N
+        for l in range(s):
+            ql = q[q0 + l].double()                        # N
+            W = P @ (ql[:, None] * Vd)                     # nh x m
+            out += ql[:, None] * (P.t().contiguous() @ (lam[q0 + l] * W))
+    return out

@@ -17,7 +17,8 @@ import torch
 
 from oracle import hdf as ohdf
 from paper_2202_03655_amd import workloads as wl
-from tests.gpu_common import BACKWARD_OFF, ambiguous_ranks, gpu_build, oracle_for, rel_fro, to_dev
+from tests.gpu_common import (BACKWARD_OFF, ambiguous_ranks, degree_blocks, gpu_build, oracle_for, rel_fro,
+                               to_dev, torch_contraction)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -34,37 +35,6 @@ def sample_rows(n, count=62, seed=5):
     """First and last point (ragged tail) plus seeded interior rows."""
     rng = np.random.default_rng(seed)
     return np.unique(np.concatenate([[0, n - 1], rng.choice(n, count, replace=False)]))
-
-
-def degree_blocks(f):
-    """(k, harmonic offset, |H_k|, radial offset, s_k) of the kept degrees."""
-    from oracle import harmonics
-    inf = f.info()
-    out, h0, q0 = [], 0, 0
-    for k, s in enumerate(inf["s_k"]):
-        if s == 0:
-            continue
-        nh = harmonics.count(f.d, k)
-        out.append((k, h0, nh, q0, s))
-        h0 += nh
-        q0 += s
-    return out
-
-
-def torch_contraction(f, V):
-    """K~V = sum_k sum_l q_kl o (Phi_k^T (lam_kl (Phi_k^T (q_kl o V)))) in
-    binary64 with torch GEMMs on the device factor (no library kernels)."""
-    phi, q = f.factor_parts()
-    lam = torch.tensor(f.plan()["lam"], dtype=torch.float64, device="cuda")
-    Vd = V.double()
-    out = torch.zeros_like(Vd)
-    for k, h0, nh, q0, s in degree_blocks(f):
-        P = phi[h0:h0 + nh].double()                       # nh x N
-        for l in range(s):
-            ql = q[q0 + l].double()                        # N
-            W = P @ (ql[:, None] * Vd)                     # nh x m
-            out += ql[:, None] * (P.t().contiguous() @ (lam[q0 + l] * W))
-    return out
 
 
 def sampled_guarantee(f, X, kernel, l, pairs=16384, seed=9):
