@@ -131,15 +131,20 @@ static void dct2(const std::vector<double>& f, std::vector<double>& y, const Dct
   for (size_t i = 0; i < n; ++i) y[i] = v[i].real() * tb.pc[i] - v[i].imag() * tb.ps[i];
 }
 
+// The sampled function f(D |x|) is even, so node j and node n - 1 - j carry the
+// same value: the odd coefficients vanish and the even ones are a length-n/2
+// DCT-II of the first half, sum_j f_j cos(pi (2i) (2j+1) / (2n)) =
+// 2 sum_{j < n/2} f_j cos(pi i (2j+1) / n).
 void chebyshev_coeffs(int kind, double D, double l, int n, bool derivative, double* a) {
-  const DctTables& tb = dct_tables((size_t)n);
-  std::vector<double> f(n), y;
-  for (int j = 0; j < n; ++j) {
-    const double r = D * std::fabs(tb.node[j]);
+  const DctTables& tn = dct_tables((size_t)n);
+  const int h = n / 2;
+  std::vector<double> f(h), y;
+  for (int j = 0; j < h; ++j) {
+    const double r = D * std::fabs(tn.node[j]);
     f[j] = derivative ? kernel_dl(kind, r, l) : kernel_value(kind, r, l);
   }
-  dct2(f, y, tb);
-  for (int i = 0; i < n; ++i) a[i] = (i % 2) ? 0.0 : y[i] * 2.0 / n;
+  dct2(f, y, dct_tables((size_t)h));
+  for (int i = 0; i < n; ++i) a[i] = (i % 2) ? 0.0 : y[i / 2] * 4.0 / n;
   a[0] *= 0.5;
 }
 
