@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -265,21 +266,27 @@ namespace {
 // ascending, +m then -m), then the chain levels from d-2 down to 1; each
 // innermost iteration is one harmonic.  Returns its canonical row or -1 for a
 // dropped degree.
-void loop_order_columns(int d, int K, const std::map<std::vector<int>, int>& canon,
+// A harmonic's index (k, mu_1 .. mu_{d-3}, m) packed one byte per entry (d <= 8,
+// k and mu <= 30, m + 128 in [98, 158]).
+static uint64_t harmonic_key(int k, const int32_t* mu, int nmu, int m) {
+  uint64_t key = (uint64_t)k;
+  for (int j = 0; j < nmu; ++j) key = key << 8 | (uint64_t)mu[j];
+  return key << 8 | (uint64_t)(m + 128);
+}
+
+void loop_order_columns(int d, int K, const std::unordered_map<uint64_t, int>& canon,
                         std::vector<int32_t>& col_of) {
   col_of.clear();
-  std::vector<int> path;   // upper indices from level d-2 down to level 1
+  std::vector<int32_t> path, mus;   // upper indices from level d-2 down to level 1
   std::function<void(int, int, int)> rec = [&](int level, int b, int msigned) {
     for (int nn = 0; nn <= K - b; ++nn) {
       const int a = b + nn;
       path.push_back(a);
       if (level == 1) {
         // path = [mu_{d-3}, ..., mu_1, k] (for d = 3: [k])
-        std::vector<int> key;
-        key.push_back(path.back());                       // k
-        for (int j = (int)path.size() - 2; j >= 0; --j) key.push_back(path[j]);   // mu_1..mu_{d-3}
-        key.push_back(msigned);
-        auto it = canon.find(key);
+        mus.clear();
+        for (int j = (int)path.size() - 2; j >= 0; --j) mus.push_back(path[j]);   // mu_1..mu_{d-3}
+        auto it = canon.find(harmonic_key(path.back(), mus.data(), (int)mus.size(), msigned));
         col_of.push_back(it == canon.end() ? -1 : it->second);
       } else {
         rec(level - 1, a, msigned);
@@ -317,7 +324,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   const int64_t n = f->N;
   // kept degrees, offsets, tables
   int64_t hoff = 0, qoff = 0, roff = 0;
-  std::map<std::vector<int>, int> canon;
+  std::unordered_map<uint64_t, int> canon;
   for (int k = 0; k <= K; ++k) {
     const hdf::DegreeFactor& df = f->deg[k];
     if (df.s == 0) continue;
@@ -328,14 +335,12 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     f->kept_k.push_back(k);
     std::vector<int32_t> tab;
     hdf::index_set(d, k, tab);
+    canon.reserve(canon.size() + (size_t)nh);
     for (int64_t h = 0; h < nh; ++h) {
-      std::vector<int> key(1, k);
+      const int32_t* t = &tab[(size_t)h * (d - 2)];
       f->index_table.push_back(k);
-      for (int j = 0; j < d - 2; ++j) {
-        key.push_back(tab[(size_t)h * (d - 2) + j]);
-        f->index_table.push_back(tab[(size_t)h * (d - 2) + j]);
-      }
-      canon[key] = (int)(hoff + h);
+      for (int j = 0; j < d - 2; ++j) f->index_table.push_back(t[j]);
+      canon[harmonic_key(k, t, d - 3, t[d - 3])] = (int)(hoff + h);
     }
     hoff += nh;
     qoff += df.s;
