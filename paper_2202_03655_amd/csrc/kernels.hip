@@ -1487,12 +1487,17 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
   // points past the split meet a zero B operand.  Every load is in bounds:
   // p is a multiple of 32 below n and the rows are padded to at least the
   // next multiple of 64 plus 64 columns.
-  int64_t prow[kMvTPW];                           // element offsets from phi (global loads, not flat)
-  auto load_batch = [&](int64_t p, int b0, T (&a)[NB][8]) {
+  // row offsets from phi (global loads, not flat) in units of 64 elements: ld_phi is a multiple of 64,
+  // and 2^32 such units exceed any device memory, so 32 bits per item suffice
+  uint32_t prow[kMvTPW];
+  // the rows of items [b0, b0 + NB) (first = false: of items [0, NB)) at chunk p; b0 is a compile-time
+  // constant, so the offsets are selected, never indexed at run time (which would keep them in scratch)
+  auto load_batch = [&](int64_t p, int b0, T (&a)[NB][8], bool first = false) {
     const int64_t pb = p + 8 * g;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const T* r = phi + (prow[b0 + j] + pb);
+      const uint32_t ro = first ? prow[j] : prow[b0 + j];
+      const T* r = phi + (((int64_t)ro << 6) + pb);
       if constexpr (sizeof(T) == 4) {
         const floatx4 v0 = *reinterpret_cast<const floatx4*>(r);
         const floatx4 v1 = *reinterpret_cast<const floatx4*>(r + 4);
@@ -1521,7 +1526,7 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
     const bool any = n_mine > 0;
     const int di = wbase + (i < n_mine ? i : 0);
     const int nr = any ? d_nr[di] : 1;
-    prow[i] = ((any ? d_row[di] : 0) + (li < nr ? li : 0)) * ld_phi;
+    prow[i] = (uint32_t)((((any ? d_row[di] : 0) + (li < nr ? li : 0)) * ld_phi) >> 6);
     rq[i] = (any ? d_qr[di] : kMvCH * vst) + 8 * g;
   }
   stage_store(lds);
@@ -1548,7 +1553,7 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
           // next step: the following batch of this chunk, else batch 0 of
           // the next chunk (re-reads this chunk's first batch at the end)
           const bool same = b0 + NB < n_mine;
-          load_batch(same ? p : (has_next ? pn : p), same ? b0 + NB : 0, a_nxt);
+          load_batch(same ? p : (has_next ? pn : p), b0 + NB < kMvTPW ? b0 + NB : 0, a_nxt, !same);
           if constexpr (CPL > 0) {
             // the batch's radial values first (offsets of items past n_mine are valid), so one
             // wait covers the LDS reads of the whole batch
@@ -1620,6 +1625,7 @@ hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, i
                                const int32_t* group_q, int n_groups, int max_nq, const void* V,
                                int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
                                int64_t rank, double* partials, int prec, hipStream_t s) {
+  if (ld_phi % 64 != 0) return hipErrorInvalidValue;   // row offsets are held in units of 64 elements
   const dim3 grid(n_splits, n_groups);
   const size_t lds = matvec_lds_bytes(m16, max_nq, prec);
 #define HDF_MVT(T, C)                                                                                        \
