@@ -200,7 +200,7 @@ def cpu_baseline(wname, X, V, n_sample):
 
 
 # fp64 VALU lane-instructions per (i, j) pair in the inner loop of the off-diagonal kernel
-# k_kmv<8, Gaussian, masked> (AMD assembly of this build, loop unrolled by 4: 140 fp64 + 36 other VALU
+# k_kmv<8, Gaussian, masked> (its compiled gfx950 assembly, loop unrolled by 4: 140 fp64 + 36 other VALU
 # instructions per 4 pairs); the VALU issue peak is 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 KMV_VALU_PER_PAIR = 44.0
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -355,8 +355,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(every box has a single MI355X); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the sharding is a design, not code); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -2,9 +2,8 @@
 
 The paper's experiments (Sec. 4.1, the Fig. 3 paragraph) use the Cauchy kernel,
 a Gaussian and the Matern kernels with nu = 1.5 and nu = 2.5.  The Gaussian is
-taken here as exp(-r^2 / (2 l^2)) (the lengthscale convention of the workloads
-this build is measured on; the paper writes exp(-(r/sigma)^2), i.e. sigma =
-sqrt(2) l).  Every function accepts real or complex ``r`` / ``l`` so that the
+taken here as exp(-r^2 / (2 l^2)) (the lengthscale convention of the synthetic
+workloads; the paper writes exp(-(r/sigma)^2), i.e. sigma = sqrt(2) l).  Every function accepts real or complex ``r`` / ``l`` so that the
 complex-step derivative can be used on it.
 """
 import numpy as np
