@@ -673,7 +673,8 @@ hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t
     double gmax = 0.0, gmin = INFINITY;
     for (double v : pcs[k].lam1c) { gmax = std::max(gmax, v); gmin = std::min(gmin, v); }
     const double cond = gmax / gmin;
-    hdf::compress_degree(k, L, G.data(), f->cores[k].data(), f->tau, floor_rel, f->deg[k]);
+    hdf::compress_degree_eig(k, L, pcs[k].w1.data(), pcs[k].V1.data(), f->cores[k].data(), f->tau, floor_rel,
+                             f->deg[k]);
     double lmax = 0.0;
     for (double v : f->deg[k].lam) lmax = std::max(lmax, std::fabs(v));
     const double est = eta1 * cond * (lmax > 0 ? f->tau / lmax : 1.0);

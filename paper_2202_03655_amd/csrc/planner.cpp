@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <limits>
 #include <complex>
 #include <map>
 #include <memory>
@@ -396,20 +397,20 @@ void chain_coeffs(int d, int K, ChainCoeffs& out) {
 void jacobi_eigh(int n, double* A, double* w, double* V) {
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+  // Cyclic sweeps with the threshold rule: a rotation is skipped when |a_pq| is below half a unit roundoff
+  // of sqrt(|a_pp a_qq|) (it would move no diagonal entry), and the iteration ends after a sweep without a
+  // rotation.  (An off-diagonal mass test at the unit-roundoff level is never met once rounding noise of
+  // order n eps |A| fills the off-diagonal entries.)
+  const double eps = std::numeric_limits<double>::epsilon();
   for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        const double v = A[i * n + j] * A[i * n + j];
-        tot += v;
-        if (i != j) off += v;
-      }
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    int rotated = 0;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
         const double apq = A[p * n + q];
         if (apq == 0.0) continue;
         const double app = A[p * n + p], aqq = A[q * n + q];
+        if (std::fabs(apq) <= 0.5 * eps * std::sqrt(std::fabs(app * aqq))) continue;
+        ++rotated;
         const double theta = (aqq - app) / (2.0 * apq);
         const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
         const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
@@ -430,6 +431,7 @@ void jacobi_eigh(int n, double* A, double* w, double* V) {
           V[k * n + q] = s * vkp + c * vkq;
         }
       }
+    if (rotated == 0) break;
   }
   for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
 }
@@ -444,6 +446,17 @@ void compress_degree(int k, int L, const double* G, const double* M, double tau,
   out.Ep.clear();
   std::vector<double> Gc(G, G + (size_t)L * L), wg(L), Vg((size_t)L * L);
   jacobi_eigh(L, Gc.data(), wg.data(), Vg.data());
+  compress_degree_eig(k, L, wg.data(), Vg.data(), M, tau, null_rel, out);
+}
+
+void compress_degree_eig(int k, int L, const double* wg, const double* Vg, const double* M, double tau,
+                         double null_rel, DegreeFactor& out) {
+  out.k = k;
+  out.L = L;
+  out.s = 0;
+  out.lam.clear();
+  out.E.clear();
+  out.Ep.clear();
   double gmax = 0.0;
   for (int i = 0; i < L; ++i) gmax = std::max(gmax, wg[i]);
   if (!(gmax > 0.0)) return;
@@ -674,6 +687,7 @@ void gram_precondition(int L, const double* G1, double floor_rel, Precond& pc) {
   std::vector<double> Gc(G1, G1 + (size_t)L * L), w(L);
   pc.V1.assign((size_t)L * L, 0.0);
   jacobi_eigh(L, Gc.data(), w.data(), pc.V1.data());
+  pc.w1 = w;
   double gmax = 0.0;
   for (int i = 0; i < L; ++i) gmax = std::max(gmax, w[i]);
   if (!(gmax > 0.0)) gmax = 1.0;

@@ -47,6 +47,9 @@ struct DegreeFactor {
 };
 void compress_degree(int k, int L, const double* G, const double* M, double tau,
                      double null_rel, DegreeFactor& out);
+// The same from an eigendecomposition G = Vg diag(wg) Vg^T already at hand (Vg row-major L x L).
+void compress_degree_eig(int k, int L, const double* wg, const double* Vg, const double* M, double tau,
+                         double null_rel, DegreeFactor& out);
 
 // Two-pass (CholeskyQR2-style) compression.  Pass 1: from the radial Gram G1
 // (L x L) build the preconditioner T1 = V1 diag(lam1c)^{-1/2} (L x L,
@@ -58,6 +61,7 @@ void compress_degree(int k, int L, const double* G, const double* M, double tau,
 struct Precond {
   int L = 0;
   std::vector<double> V1, lam1c, T1;   // L x L row-major; T1 = V1 diag(lam1c^-1/2)
+  std::vector<double> w1;              // eigenvalues of G1 before the clamp (G1 = V1 diag(w1) V1^T)
 };
 void gram_precondition(int L, const double* G1, double floor_rel, Precond& pc);
 void compress_degree_refined(int k, int L, const double* G2, const Precond& pc, const double* M,
