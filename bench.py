@@ -108,6 +108,18 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule=
         del f
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    # build to completion: the build call returns with the factor evaluation still running on the
+    # device, so each build here is followed by a device synchronisation before the clock stops
+    reps = max(3, steps)
+    tb = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule,
+                       storage=storage)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        del f
+    build_done_s = sorted(tb)[len(tb) // 2]
     # separate matvec timing on a resident factor (wall clock of the call)
     f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule, storage=storage)
     for _ in range(2):
@@ -121,7 +133,8 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule=
     mv_s = (time.perf_counter() - t0) / reps
     del f
     avg = {k: sum(v) / len(v) for k, v in rec.items()}
-    return dict(ms_per_step=1e3 * t_total / steps, build_ms=1e3 * avg["build_s"], matvec_ms=1e3 * mv_s,
+    return dict(ms_per_step=1e3 * t_total / steps, build_ms=1e3 * build_done_s,
+                build_return_ms=1e3 * avg["build_s"], matvec_ms=1e3 * mv_s,
                 backward_ms=1e3 * avg["bw_s"],
                 build_phases_ms={k[2:]: round(avg[k], 3) for k in ("h_prep", "h_plan", "h_gram", "h_compress",
                                                                    "h_finish")},
@@ -422,6 +435,8 @@ def main():
                    "tol": cfg["tol"], "rhs": m, "precision": args.precision,
                    "step": "hdf_build + hdf_matvec(16 RHS)" + (" + hdf_backward" if with_backward else "")},
         "build_mpoints_s": round(N / (res["build_ms"] * 1e-3) / 1e6, 3),
+        "build_ms": round(res["build_ms"], 3),
+        "build_return_ms": round(res["build_return_ms"], 3),
         "matvec_gflops": round(mv_flops / (res["matvec_ms"] * 1e-3) / 1e9, 1),
         "kernel_ms": {"build": round(res["k_build_ms"], 4), "matvec_pass1": round(res["k_mv_t_ms"], 4),
                       "matvec_reduce": round(res["k_mv_reduce_ms"], 4), "matvec_pass2": round(res["k_mv_n_ms"], 4),

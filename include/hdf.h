@@ -49,9 +49,17 @@ typedef enum {
 
 typedef enum {
   HDF_FP64  = 0,      /* every device step in binary64                        */
-  HDF_MIXED = 1       /* binary32 factor, harmonics and MFMA contractions;
-                         binary64 geometry, reductions and compression        */
+  HDF_MIXED = 1       /* binary32 data (points, V, KV); binary32 factor,
+                         harmonics and MFMA contractions with binary64
+                         geometry, reductions and compression, split (hi/lo)
+                         binary32 Gram.  For tol <= HDF_SPLIT_TOL the factor
+                         is stored and contracted in binary64 instead (its
+                         binary32 rounding alone exceeds such tolerances, and
+                         binary64 MFMA costs less than a three-product hi/lo
+                         binary32 split): see hdf_info_t.factor_precision  */
 } hdf_precision;
+
+#define HDF_SPLIT_TOL 1e-6   /* HDF_MIXED: tolerances at or below use a binary64 factor */
 
 typedef enum {
   HDF_OK           =  0,
@@ -111,6 +119,10 @@ typedef struct {
                                 HDF_MAX_DEGREE)                             */
   int32_t  storage;          /* hdf_storage                                  */
   int64_t  chunk_points;     /* HDF_STORE_NONE: points per chunk; 0 otherwise */
+  int32_t  factor_precision; /* storage and arithmetic of the factor and its
+                                contractions: HDF_MIXED = binary32,
+                                HDF_FP64 = binary64 (HDF_MIXED builds with
+                                tol <= HDF_SPLIT_TOL report HDF_FP64)        */
 } hdf_info_t;
 
 /* Build the factor (Algorithm 1, symmetric case, Remark 1).
@@ -236,7 +248,8 @@ hdf_status hdf_get_plan(hdf_handle h, int32_t* index_table, double* lambda,
 /* Copy the stored factor into caller buffers (device to device, enqueued on
  * hip_stream).  phi_out: H x n (harmonic-major, leading dimension ld_phi >= n),
  * q_out: S x n (radial functions, leading dimension ld_q >= n); element type
- * = float32 for HDF_MIXED, float64 for HDF_FP64.  Either may be NULL.
+ * = the factor's (hdf_info_t.factor_precision: float32 for HDF_MIXED,
+ * float64 for HDF_FP64).  Either may be NULL.
  * Column (k,h,l) of U is phi[row of h] * q[row of (k,l)] elementwise
  * (Algorithm 1: Xbar^(k)[:, l] times the harmonic). */
 hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_out, int64_t ld_q,

@@ -153,16 +153,3 @@ def radial_cores(a, p, d, u0, u1, dps=60):
         cores.append([[float(mpmath.mpf(v.numerator) / v.denominator * Z) for v in row]
                       for row in Mx])
     return cores
-
-
-def radial_cores_power(a, p, d):
-    """Binary64 cores in the power basis (rho^2)^a, including Z_j (testing aid)."""
-    a_ex = exact(list(a[: p + 1]))
-    Tp = T_prime(a_ex, p, d)
-    out = []
-    for j in range(p // 2 + 1):
-        P = power_core(Tp, p, j)
-        Z = Z_mp(j, d)
-        out.append([[float(mpmath.mpf(v.numerator) / v.denominator * Z) for v in row]
-                    for row in P])
-    return out

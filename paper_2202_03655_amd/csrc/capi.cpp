@@ -241,7 +241,11 @@ struct hdf_factor {
     for (auto& e : ev_adj)
       if (e) hipEventDestroy(e);
   }
-  size_t elem() const { return prec == HDF_MIXED ? 4 : 8; }
+  // factor storage and arithmetic (1 = binary32, 0 = binary64) and its element size; the
+  // caller's data (points, V, KV, W, dX) is in the points' type (dtype) throughout
+  int fprec = 1;
+  size_t felem() const { return fprec == 1 ? 4 : 8; }
+  size_t ioel() const { return dtype == 0 ? 4 : 8; }
 };
 
 void hdf::set_product_timing(hdf_factor* h, bool on) { h->time_products = on; }
@@ -320,7 +324,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     ~FinishTimer() { f->t_finish = now_ms() - t; }
   } timer{f, 0.0};
   const int K = f->K, d = f->d, dtype = f->dtype;
-  const int prec = f->prec;
+  const int prec = f->fprec;
   const int64_t n = f->N;
   // kept degrees, offsets, tables
   int64_t hoff = 0, qoff = 0, roff = 0;
@@ -353,7 +357,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
 
   // 5. memory budget, then the factor evaluation
   const bool mfree = f->storage == HDF_STORE_NONE;
-  const size_t fbytes = (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->elem();
+  const size_t fbytes = (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->felem();
   size_t freeb = 0, totb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totb));
   {
@@ -369,15 +373,15 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   }
   if (f->H > 0) {
     if (mfree) {
-      HIPCHK(f->cphi.ensure((size_t)f->H * f->ldC * f->elem()));
-      HIPCHK(f->cq.ensure((size_t)f->S * f->ldC * f->elem()));
+      HIPCHK(f->cphi.ensure((size_t)f->H * f->ldC * f->felem()));
+      HIPCHK(f->cq.ensure((size_t)f->S * f->ldC * f->felem()));
     } else {
-      HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->elem()));
-      HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->elem()));
+      HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->felem()));
+      HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->felem()));
     }
     if (f->cross) {
-      HIPCHK(f->phi2.ensure((size_t)f->H * f->ldN2 * f->elem()));
-      HIPCHK(f->q2.ensure((size_t)f->S * f->ldN2 * f->elem()));
+      HIPCHK(f->phi2.ensure((size_t)f->H * f->ldN2 * f->felem()));
+      HIPCHK(f->q2.ensure((size_t)f->S * f->ldN2 * f->felem()));
     }
     // The harmonic recurrences run up to the largest kept degree only:
     // dropped top degrees would be evaluated and discarded by both the factor
@@ -433,7 +437,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       }
     }
     auto upload_typed = [&](DevBuf& b, const std::vector<double>& v) -> hipError_t {
-      if (f->prec == HDF_MIXED) {
+      if (f->fprec == 1) {
         std::vector<float> tmp(v.begin(), v.end());
         return upload(b, tmp.data(), tmp.size() * 4);
       }
@@ -476,15 +480,15 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
                              f->u0, f->u1, tb, prec, f->phi.p, f->ldN, f->q.p, f->ldN, s));
     // rows are padded past N: clear the padding so contraction kernels may
     // read whole 8-point groups without masking
-    HIPCHK(clear_padding(f->phi.p, f->H, n, f->ldN, f->elem(), s));
-    HIPCHK(clear_padding(f->q.p, f->S, n, f->ldN, f->elem(), s));
+    HIPCHK(clear_padding(f->phi.p, f->H, n, f->ldN, f->felem(), s));
+    HIPCHK(clear_padding(f->q.p, f->S, n, f->ldN, f->felem(), s));
     if (f->cross) {
       f->tables2 = tb;
       f->tables2.q_coef = f->q_coef2.p;
       HIPCHK(hdf::launch_build(f->x_soa2.p, dtype, f->ldN2, f->N2, d, (const hdf::GeoDev*)f->geo_dev.p,
                                f->u0, f->u1, f->tables2, prec, f->phi2.p, f->ldN2, f->q2.p, f->ldN2, s));
-      HIPCHK(clear_padding(f->phi2.p, f->H, f->N2, f->ldN2, f->elem(), s));
-      HIPCHK(clear_padding(f->q2.p, f->S, f->N2, f->ldN2, f->elem(), s));
+      HIPCHK(clear_padding(f->phi2.p, f->H, f->N2, f->ldN2, f->felem(), s));
+      HIPCHK(clear_padding(f->q2.p, f->S, f->N2, f->ldN2, f->felem(), s));
     }
     HIPCHK(hipEventRecord(f->ev_b1, s));
   }
@@ -554,6 +558,7 @@ hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t
     f->ldC = (f->chunk + 63) / 64 * 64 + 64;
   }
   f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
+  f->fprec = (prec == HDF_MIXED && tol > HDF_SPLIT_TOL) ? 1 : 0;
   f->N = n; f->l = lengthscale; f->tol = tol;
   // rows of the factor are padded by at least 64 points: the streaming kernels
   // issue unconditional 16-byte loads up to 63 points past the last point
@@ -757,6 +762,7 @@ hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y
   std::unique_ptr<hdf_factor> f(new hdf_factor());
   f->cross = true;
   f->d = d; f->prec = prec; f->dtype = dtype; f->kernel = kernel;
+  f->fprec = (prec == HDF_MIXED && tol > HDF_SPLIT_TOL) ? 1 : 0;
   f->N = nx; f->N2 = ny; f->l = lengthscale; f->tol = tol;
   f->ldN = (nx + 63) / 64 * 64 + 64;
   f->ldN2 = (ny + 63) / 64 * 64 + 64;
@@ -931,10 +937,10 @@ hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y
 static hdf_status eval_chunk(hdf_handle h, int64_t c0, int64_t nc, hipStream_t s) {
   const size_t in_el = h->dtype == 0 ? 4 : 8;
   HIPCHK(hdf::launch_build((const char*)h->x_soa.p + c0 * in_el, h->dtype, h->ldN, nc, h->d,
-                           (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, h->prec, h->cphi.p, h->ldC,
+                           (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, h->fprec, h->cphi.p, h->ldC,
                            h->cq.p, h->ldC, s));
-  HIPCHK(clear_padding(h->cphi.p, h->H, nc, h->ldC, h->elem(), s));
-  HIPCHK(clear_padding(h->cq.p, h->S, nc, h->ldC, h->elem(), s));
+  HIPCHK(clear_padding(h->cphi.p, h->H, nc, h->ldC, h->felem(), s));
+  HIPCHK(clear_padding(h->cq.p, h->S, nc, h->ldC, h->felem(), s));
   return HDF_OK;
 }
 
@@ -945,13 +951,13 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
 // of split partials; one fixed-order reduction over all chunks' partials gives W.
 static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
                                 DevBuf& Wd, hipStream_t s, bool timed) {
-  const size_t el = h->elem();
+  const size_t el = h->felem();
   const int cpl = m16 / 16;
   const size_t per_split = (size_t)h->r * m16 * sizeof(double);
   // work items and groups as for a stored factor of chunk points
   hdf_status st = pass1(h, 2, V, m, ldv, m16, W, Wd, s, false);   // side 2: tables only
   if (st != HDF_OK) return st;
-  const bool lds = m16 <= 64 && hdf::matvec_lds_bytes(m16, h->max_nq, h->prec) <= 65536;
+  const bool lds = m16 <= 64 && hdf::matvec_lds_bytes(m16, h->max_nq, h->fprec) <= 65536;
   std::vector<int> splits;
   std::vector<int64_t> slen;
   int total = 0;
@@ -991,22 +997,22 @@ static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t 
     const int64_t nc = std::min(h->chunk, h->N - c0);
     st = eval_chunk(h, c0, nc, s);
     if (st != HDF_OK) return st;
-    const void* Vc = (const char*)V + c0 * ldv * el;
+    const void* Vc = (const char*)V + c0 * ldv * h->ioel();
     double* part = (double*)h->ws_part.p + (size_t)slot * h->r * m16;
     if (lds)
       HIPCHK(hdf::launch_matvec_t_lds(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
                                       (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
                                       (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, Vc, ldv, nc, (int)m,
-                                      m16, splits[ci], slen[ci], h->r, part, h->prec, s));
+                                      m16, splits[ci], slen[ci], h->r, part, h->fprec, h->dtype, s));
     else
       HIPCHK(hdf::launch_matvec_t(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
                                   (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, h->max_s * cpl, Vc, ldv, nc,
-                                  (int)m, m16, splits[ci], slen[ci], h->r, part, h->prec, s));
+                                  (int)m, m16, splits[ci], slen[ci], h->r, part, h->fprec, h->dtype, s));
     slot += splits[ci];
   }
   if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
   HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, total, h->r, m16, (const double*)h->lam_row.p,
-                                   (double*)W.p, Wd.p, h->prec, s));
+                                   (double*)W.p, Wd.p, h->fprec, s));
   if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
   return HDF_OK;
 }
@@ -1019,14 +1025,14 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
   const void* phi = side == 1 ? h->phi2.p : h->phi.p;
   const void* qv = side == 1 ? h->q2.p : h->q.p;
   const int64_t ldn = side == 1 ? h->ldN2 : h->ldN;
-  const size_t el = h->elem();
+  const size_t el = h->felem();
   const int cpl = m16 / 16;
   const int max_nct = h->max_s * cpl;
   if (h->tiles_cpl != cpl) {
     // work items: (degree, row block, column slice), no empty slices
     std::vector<hdf::TileDev>& tiles = h->tiles_host;
     tiles.clear();
-    const int nct = hdf::matvec_col_tiles(h->prec);
+    const int nct = hdf::matvec_col_tiles(h->fprec);
     for (size_t di = 0; di < h->degs.size(); ++di)
       for (int h0 = 0; h0 < h->degs[di].nh; h0 += hdf::matvec_row_block())
         for (int ct0 = 0; ct0 < h->degs[di].s * cpl; ct0 += nct)
@@ -1078,7 +1084,7 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
       h->items_cpl = cpl;
     }
     if (side == 2) return HDF_OK;
-    if (hdf::matvec_lds_bytes(m16, h->max_nq, h->prec) <= 65536) {
+    if (hdf::matvec_lds_bytes(m16, h->max_nq, h->fprec) <= 65536) {
       int n_splits = (int)std::max<int64_t>(1, 1024 / std::max(1, h->n_groups));
       n_splits = (int)std::min<int64_t>(n_splits, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
       n_splits = (int)std::min<int64_t>(n_splits, (n + 255) / 256);
@@ -1098,10 +1104,10 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
                                       (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
                                       (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, V, ldv, n,
                                       (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
-                                      h->prec, s));
+                                      h->fprec, h->dtype, s));
       if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
       HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
-                                       (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->prec, s));
+                                       (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->fprec, s));
       if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
       return HDF_OK;
     }
@@ -1126,10 +1132,10 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
   HIPCHK(hdf::launch_matvec_t(phi, ldn, qv, ldn, (const hdf::DegDev*)h->degs_dev.p,
                               (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, max_nct, V, ldv, n,
                               (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
-                              h->prec, s));
+                              h->fprec, h->dtype, s));
   if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
   HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
-                                   (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->prec, s));
+                                   (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->fprec, s));
   if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
   return HDF_OK;
 }
@@ -1137,7 +1143,7 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
 // Pass 2 over n points of a factor (phi, q with leading dimension ld): KV = U (D W), W from pass 1.
 static hdf_status pass2(hdf_handle h, const void* phi, const void* q, int64_t ld, int64_t n, int64_t m, int m16,
                         void* KV, int64_t ldkv, hipStream_t s) {
-  const size_t el = h->elem();
+  const size_t el = h->felem();
   // few points: split the harmonic rows so that pass 2 still has >= 1024 wavefronts
   const int64_t waves = ((n + 63) / 64) * (m16 / 16);
   int nz = 1, hchunk = 0;
@@ -1150,7 +1156,7 @@ static hdf_status pass2(hdf_handle h, const void* phi, const void* q, int64_t ld
   }
   if (nz > 1) HIPCHK(h->ws_n.ensure((size_t)nz * n * m * el));
   HIPCHK(hdf::launch_matvec_n(phi, ld, q, ld, (const hdf::DegDev*)h->degs_dev.p, (int)h->degs.size(), h->max_s,
-                              h->ws_Wd.p, m16, KV, ldkv, n, (int)m, h->prec, nz > 1 ? hchunk : 0, nz,
+                              h->ws_Wd.p, m16, KV, ldkv, n, (int)m, h->fprec, h->dtype, nz > 1 ? hchunk : 0, nz,
                               nz > 1 ? h->ws_n.p : nullptr, s));
   return HDF_OK;
 }
@@ -1158,7 +1164,7 @@ static hdf_status pass2(hdf_handle h, const void* phi, const void* q, int64_t ld
 static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV,
                               int64_t ldkv, hipStream_t s) {
   const int64_t n = h->N;
-  const size_t el = h->elem();
+  const size_t el = h->ioel();
   if (h->r == 0) {
     HIPCHK(hipMemset2DAsync(KV, ldkv * el, 0, m * el, n, s));
     return HDF_OK;
@@ -1193,7 +1199,7 @@ hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv, void*
   if (!V || !KV) return fail(HDF_E_ARG, "V or KV is NULL");
   if (m < 1 || m > HDF_MAX_RHS) return fail(HDF_E_ARG, "m must be in [1, 256]");
   if (ldv < m || ldkv < m) return fail(HDF_E_ARG, "leading dimensions must be >= m");
-  const size_t el = h->elem();
+  const size_t el = h->ioel();
   const char* v0 = (const char*)V;
   const char* v1 = v0 + (((h->cross ? h->N2 : h->N) - 1) * ldv + m) * el;
   const char* k0 = (const char*)KV;
@@ -1211,11 +1217,14 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
   if (ld < m) return fail(HDF_E_ARG, "ld must be >= m");
   if (dX && lddx < h->d) return fail(HDF_E_ARG, "lddx must be >= d");
   if (h->cross) return fail(HDF_E_ARG, "hdf_backward needs a symmetric factor (hdf_build)");
+  if (dX && h->fprec != (h->dtype == 0 ? 1 : 0))
+    return fail(HDF_E_ARG, "dF/dX needs the factor in the points' type (a binary64 factor of binary32 points, "
+                           "used below tol 1e-6, has no adjoint kernel)");
   if (dX && !kAdjointKernel)
     return fail(HDF_E_DISABLED, "dF/dX is switched off (compile with -DHDF_ADJOINT_KERNEL=1): the adjoint "
                                 "kernels are withdrawn until a device memory fault seen with them is explained");
   hipStream_t s = (hipStream_t)hip_stream;
-  const size_t el = h->elem();
+  const size_t el = h->ioel(), fel = h->felem();
   if (!dlength && !dX) return HDF_OK;
   if (h->r == 0) {
     if (dlength) *dlength = 0.0;
@@ -1239,7 +1248,7 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
     hdf_status st = pass1(h, 0, h->bw_VW.p, m2, m2, m16, h->bw_GV, h->bw_GVd, s, false);
     if (st != HDF_OK) return st;
     Gv_d = h->bw_GVd.p;
-    Gw_d = (const char*)h->bw_GVd.p + m * el;
+    Gw_d = (const char*)h->bw_GVd.p + m * fel;
     gv_src = gw_src = &h->bw_GV;
     gw_col = m;
   } else {
@@ -1262,9 +1271,9 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
       HIPCHK(hipMemcpyAsync(h->adj_kinfo.p, h->adj_kinfo_host.data(),
                             h->adj_kinfo_host.size() * sizeof(hdf::KInfo), hipMemcpyHostToDevice, s));
     }
-    HIPCHK(h->adj_stream.ensure(hdf::adjoint_stream_elems((int)h->r, (int)m) * el));
+    HIPCHK(h->adj_stream.ensure(hdf::adjoint_stream_elems((int)h->r, (int)m) * fel));
     // radial rows staged in LDS per launch: at most 64 KiB (values + derivatives)
-    const int max_rows = (int)(65536 / (2 * 64 * el));
+    const int max_rows = (int)(65536 / (2 * 64 * fel));
     bool first = true;
     if (!h->ev_adj[0])
       for (auto& e : h->ev_adj) HIPCHK(hipEventCreate(&e));
@@ -1283,7 +1292,7 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
                                    (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, row0, row1,
                                    (const hdf::KInfo*)h->adj_kinfo.p, Gv_d, Gw_d, m16, (int)m,
                                    (const int32_t*)h->adj_src.p, (int)h->r, h->adj_stream.p, Wm, Vm, ld,
-                                   c0, mc, dX, lddx, first ? 0 : 1, h->prec, s));
+                                   c0, mc, dX, lddx, first ? 0 : 1, h->fprec, s));
         first = false;
       }
       di = dj;
@@ -1372,8 +1381,9 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   info->rho2_min = h->u0;
   info->rho2_max = h->u1;
   info->factor_bytes = (int64_t)((h->H + h->S) *
-                                 (h->storage == HDF_STORE_NONE ? h->ldC : h->ldN + (h->cross ? h->ldN2 : 0)) * h->elem());
+                                 (h->storage == HDF_STORE_NONE ? h->ldC : h->ldN + (h->cross ? h->ldN2 : 0)) * h->felem());
   info->storage = h->storage;
+  info->factor_precision = h->fprec == 1 ? HDF_MIXED : HDF_FP64;
   info->chunk_points = h->storage == HDF_STORE_NONE ? h->chunk : 0;
   info->t_prep_ms = h->t_prep;
   info->t_plan_ms = h->t_plan;
@@ -1434,7 +1444,7 @@ hdf_status hdf_copy_factor(hdf_handle h, void* phi_out, int64_t ld_phi, void* q_
   if (h->storage == HDF_STORE_NONE) return fail(HDF_E_ARG, "a matrix-free factor (HDF_STORE_NONE) stores no factor");
   if ((phi_out && ld_phi < h->N) || (q_out && ld_q < h->N)) return fail(HDF_E_ARG, "leading dimension < n");
   hipStream_t s = (hipStream_t)hip_stream;
-  const size_t el = h->elem();
+  const size_t el = h->felem();
   if (phi_out && h->H > 0)
     HIPCHK(hipMemcpy2DAsync(phi_out, ld_phi * el, h->phi.p, h->ldN * el, h->N * el, h->H,
                             hipMemcpyDeviceToDevice, s));
@@ -1451,7 +1461,7 @@ hdf_status hdf_copy_factor_y(hdf_handle h, void* phi_out, int64_t ld_phi, void* 
   if (!h->cross) return fail(HDF_E_ARG, "the handle is a symmetric factor (no Y side)");
   if ((phi_out && ld_phi < h->N2) || (q_out && ld_q < h->N2)) return fail(HDF_E_ARG, "leading dimension < n_y");
   hipStream_t s = (hipStream_t)hip_stream;
-  const size_t el = h->elem();
+  const size_t el = h->felem();
   if (phi_out && h->H > 0)
     HIPCHK(hipMemcpy2DAsync(phi_out, ld_phi * el, h->phi2.p, h->ldN2 * el, h->N2 * el, h->H,
                             hipMemcpyDeviceToDevice, s));

@@ -881,6 +881,8 @@ hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
     return launch_build_t<float, float>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
   if (prec == 0 && dtype == 1)
     return launch_build_t<double, double>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
+  if (prec == 0 && dtype == 0)        // binary64 factor of binary32 points (tolerances below binary32)
+    return launch_build_t<float, double>(x_soa, ldx, n, d, geo, u0, u1, tb, phi, ld_phi, q, ld_q, s);
   return hipErrorInvalidValue;
 }
 
@@ -1275,12 +1277,12 @@ __device__ __forceinline__ void load8(const T* __restrict__ row, int64_t p, int6
 // 8 consecutive points of each harmonic row (two 16-byte loads per row).
 constexpr int kMvtRowTiles = 2;
 
-template <typename T, int NCT>
+template <typename T, int NCT, typename TV>
 __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
                                               const DegDev* __restrict__ degs,
                                               const TileDev* __restrict__ tiles,
-                                              const T* __restrict__ V, int64_t ldv, int64_t n,
+                                              const TV* __restrict__ V, int64_t ldv, int64_t n,
                                               int m, int m16, int64_t split_len, int64_t rank,
                                               double* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
@@ -1340,19 +1342,19 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
       const int64_t pt = pb + t;
       const bool pv = pt < p_end;
       const int64_t ptc = pv ? pt : p_begin;
-      const T* vrow = V + ptc * ldv;
+      const TV* vrow = V + ptc * ldv;
       T b[NCT];
       // the clamped indices address valid (finite) data, so validity is
       // applied as a 0/1 factor; a select would be turned back into a branch
       const T pmask = pv ? (T)1 : (T)0;
       if (cpl == 1) {
-        const T vv = vrow[li < m ? li : 0] * (li < m ? pmask : (T)0);
+        const T vv = (T)vrow[li < m ? li : 0] * (li < m ? pmask : (T)0);
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) b[ct] = qrow[ct][ptc] * vv;
       } else {
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct)
-          b[ct] = qrow[ct][ptc] * vrow[cc[ct] < m ? cc[ct] : 0] * (cv[ct] ? pmask : (T)0);
+          b[ct] = qrow[ct][ptc] * (T)vrow[cc[ct] < m ? cc[ct] : 0] * (cv[ct] ? pmask : (T)0);
       }
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
@@ -1414,14 +1416,14 @@ __device__ __forceinline__ void lds_read8(const double* p, double (&v)[8]) {
   }
 }
 
-template <typename T, int CPL>
+template <typename T, int CPL, typename TV>
 __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int64_t ld_phi,
                                                    const T* __restrict__ q, int64_t ld_q,
                                                    const DegDev* __restrict__ degs,
                                                    const TileDev* __restrict__ items,
                                                    const int32_t* __restrict__ group_items,
                                                    const int32_t* __restrict__ group_q, int max_nq,
-                                                   const T* __restrict__ V, int64_t ldv, int64_t n,
+                                                   const TV* __restrict__ V, int64_t ldv, int64_t n,
                                                    int m, int m16, int64_t split_len, int64_t rank,
                                                    double* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
@@ -1467,7 +1469,7 @@ __global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int
       const int e = tid + 256 * j;
       const int pp = e / m16, c = e - pp * m16;
       const int64_t pt = p + pp;
-      sv[j] = (e < kMvCH * m16 && pt < p_end && c < m) ? V[pt * ldv + c] : (T)0;
+      sv[j] = (e < kMvCH * m16 && pt < p_end && c < m) ? (T)V[pt * ldv + c] : (T)0;
       const int r = e >> 5, pq = e & 31;
       sq[j] = (e < kMvCH * nq && p + pq < p_end) ? q[(int64_t)(q_lo + r) * ld_q + p + pq] : (T)0;
     }
@@ -1624,19 +1626,24 @@ hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, i
                                const DegDev* degs, const TileDev* items, const int32_t* group_items,
                                const int32_t* group_q, int n_groups, int max_nq, const void* V,
                                int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
-                               int64_t rank, double* partials, int prec, hipStream_t s) {
+                               int64_t rank, double* partials, int prec, int io, hipStream_t s) {
   if (ld_phi % 64 != 0) return hipErrorInvalidValue;   // row offsets are held in units of 64 elements
   const dim3 grid(n_splits, n_groups);
   const size_t lds = matvec_lds_bytes(m16, max_nq, prec);
-#define HDF_MVT(T, C)                                                                                        \
-  k_mv_t_lds<T, C><<<grid, 256, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, degs, items, group_items, \
-                                          group_q, max_nq, (const T*)V, ldv, n, m, m16, split_len, rank, partials)
+#define HDF_MVT(T, C, TV)                                                                                    \
+  k_mv_t_lds<T, C, TV><<<grid, 256, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, degs, items,         \
+                                              group_items, group_q, max_nq, (const TV*)V, ldv, n, m, m16,     \
+                                              split_len, rank, partials)
   // V held in registers where that keeps two wavefronts per SIMD (binary32, one column tile)
-  if (prec == 1) {
-    if (m16 == 16) HDF_MVT(float, 1);
-    else HDF_MVT(float, 0);
+  if (prec == 1 && io == 0) {
+    if (m16 == 16) HDF_MVT(float, 1, float);
+    else HDF_MVT(float, 0, float);
+  } else if (prec == 0 && io == 1) {
+    HDF_MVT(double, 0, double);
+  } else if (prec == 0 && io == 0) {
+    HDF_MVT(double, 0, float);
   } else {
-    HDF_MVT(double, 0);
+    return hipErrorInvalidValue;
   }
 #undef HDF_MVT
   return hipGetLastError();
@@ -1672,12 +1679,12 @@ __global__ void k_mv_reduce(const double* __restrict__ part, int n_splits, int64
 // With hchunk > 0 (few points, many harmonics) blockIdx.z takes the harmonic
 // rows [z hchunk, (z+1) hchunk) only and writes its share of KV to
 // part[z][n][m]; k_mv_n_sum adds the shares in z order.
-template <typename T>
+template <typename T, typename TO>
 __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
                                               const DegDev* __restrict__ degs, int n_deg,
                                               const T* __restrict__ Wd, int m16,
-                                              T* __restrict__ KV, int64_t ldkv, int64_t n, int m,
+                                              TO* __restrict__ KV, int64_t ldkv, int64_t n, int m,
                                               int hchunk, T* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
   const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
@@ -1764,28 +1771,30 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
   }
   const int c = c0 + li;
   if (c < m) {
-    T* dst = part ? part + (int64_t)blockIdx.z * n * m : KV;
-    const int64_t ld = part ? m : ldkv;
+    T* dpart = part ? part + (int64_t)blockIdx.z * n * m : nullptr;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t pt = p0 + 4 * Mfma<T>::row(g, e) + u;
-        if (pt < n) dst[pt * ld + c] = acc[u][e];
+        if (pt < n) {
+          if (dpart) dpart[pt * m + c] = acc[u][e];
+          else KV[pt * ldkv + c] = (TO)acc[u][e];
+        }
       }
   }
 }
 
-template <typename T>
+template <typename T, typename TO>
 __global__ void __launch_bounds__(256) k_mv_n_sum(const T* __restrict__ part, int nz, int64_t n, int m,
-                                                  T* __restrict__ KV, int64_t ldkv) {
+                                                  TO* __restrict__ KV, int64_t ldkv) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n * m) return;
   const int64_t pt = e / m;
   const int c = (int)(e - pt * m);
   T s = 0;
   for (int z = 0; z < nz; ++z) s += part[((int64_t)z * n + pt) * m + c];
-  KV[pt * ldkv + c] = s;
+  KV[pt * ldkv + c] = (TO)s;
 }
 
 constexpr int kMvNctF = 4;   // column tiles per item of k_mv_t, binary32
@@ -1797,18 +1806,24 @@ int matvec_col_tiles(int prec) { return prec == 1 ? kMvNctF : kMvNctD; }
 hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, const TileDev* tiles, int n_tiles, int max_nct,
                            const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
-                           int64_t split_len, int64_t rank, double* partials, int prec,
+                           int64_t split_len, int64_t rank, double* partials, int prec, int io,
                            hipStream_t s) {
   (void)max_nct;
   const dim3 grid(n_tiles, n_splits);
-  if (prec == 1)
-    k_mv_t<float, kMvNctF><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
-                                              tiles, (const float*)V, ldv, n, m, m16, split_len, rank,
-                                              partials);
+  if (prec == 1 && io == 0)
+    k_mv_t<float, kMvNctF, float><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs,
+                                                     tiles, (const float*)V, ldv, n, m, m16, split_len, rank,
+                                                     partials);
+  else if (prec == 0 && io == 1)
+    k_mv_t<double, kMvNctD, double><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
+                                                       degs, tiles, (const double*)V, ldv, n, m, m16,
+                                                       split_len, rank, partials);
+  else if (prec == 0 && io == 0)
+    k_mv_t<double, kMvNctD, float><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
+                                                      degs, tiles, (const float*)V, ldv, n, m, m16,
+                                                      split_len, rank, partials);
   else
-    k_mv_t<double, kMvNctD><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q,
-                                               degs, tiles, (const double*)V, ldv, n, m, m16,
-                                               split_len, rank, partials);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1826,24 +1841,25 @@ hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t ra
 
 hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
-                           void* KV, int64_t ldkv, int64_t n, int m, int prec, int hchunk, int nz,
+                           void* KV, int64_t ldkv, int64_t n, int m, int prec, int io, int hchunk, int nz,
                            void* part, hipStream_t s) {
   (void)max_s;
   if (nz < 1 || (nz > 1 && (hchunk <= 0 || !part))) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)(m16 / 16), (unsigned)nz);
   const int hc = nz > 1 ? hchunk : 0;
   const unsigned nb = (unsigned)((n * m + 255) / 256);
-  if (prec == 1) {
-    float* dst = nz > 1 ? (float*)part : nullptr;
-    k_mv_n<float><<<grid, 64, 0, s>>>((const float*)phi, ld_phi, (const float*)q, ld_q, degs, n_deg,
-                                      (const float*)Wd, m16, (float*)KV, ldkv, n, m, hc, dst);
-    if (nz > 1) k_mv_n_sum<float><<<nb, 256, 0, s>>>((const float*)part, nz, n, m, (float*)KV, ldkv);
-  } else {
-    double* dst = nz > 1 ? (double*)part : nullptr;
-    k_mv_n<double><<<grid, 64, 0, s>>>((const double*)phi, ld_phi, (const double*)q, ld_q, degs, n_deg,
-                                       (const double*)Wd, m16, (double*)KV, ldkv, n, m, hc, dst);
-    if (nz > 1) k_mv_n_sum<double><<<nb, 256, 0, s>>>((const double*)part, nz, n, m, (double*)KV, ldkv);
-  }
+#define HDF_MVN(T, TO)                                                                                       \
+  do {                                                                                                       \
+    T* dst = nz > 1 ? (T*)part : nullptr;                                                                    \
+    k_mv_n<T, TO><<<grid, 64, 0, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, degs, n_deg, (const T*)Wd,  \
+                                      m16, (TO*)KV, ldkv, n, m, hc, dst);                                    \
+    if (nz > 1) k_mv_n_sum<T, TO><<<nb, 256, 0, s>>>((const T*)part, nz, n, m, (TO*)KV, ldkv);               \
+  } while (0)
+  if (prec == 1 && io == 0) HDF_MVN(float, float);
+  else if (prec == 0 && io == 1) HDF_MVN(double, double);
+  else if (prec == 0 && io == 0) HDF_MVN(double, float);
+  else return hipErrorInvalidValue;
+#undef HDF_MVN
   return hipGetLastError();
 }
 

@@ -87,6 +87,9 @@ struct TileDev {
   int32_t ct0;    // first 16-wide output column tile of the slice
   int32_t pad;
 };
+// Contraction launchers: prec is the factor's storage and arithmetic type (1 = binary32,
+// 0 = binary64), io the type of V and KV (0 = float32, 1 = float64).  Supported pairs:
+// (1, 0), (0, 1) and (0, 0), the last for a binary64 factor of binary32 data.
 int matvec_row_block();          // harmonic rows per pass-1 row block
 int matvec_col_tiles(int prec);  // 16-wide column tiles per pass-1 launch slice
 
@@ -95,7 +98,7 @@ int matvec_col_tiles(int prec);  // 16-wide column tiles per pass-1 launch slice
 hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, const TileDev* tiles, int n_tiles, int max_nct,
                            const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
-                           int64_t split_len, int64_t rank, double* partials, int prec,
+                           int64_t split_len, int64_t rank, double* partials, int prec, int io,
                            hipStream_t s);
 // Pass 1 with V and the radial rows staged in LDS per workgroup.  Items are
 // (degree, 16-row tile h0, column tile ct0) with degrees contiguous; group g
@@ -107,7 +110,7 @@ hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, i
                                const DegDev* degs, const TileDev* items, const int32_t* group_items,
                                const int32_t* group_q, int n_groups, int max_nq, const void* V,
                                int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
-                               int64_t rank, double* partials, int prec, hipStream_t s);
+                               int64_t rank, double* partials, int prec, int io, hipStream_t s);
 // Reduce over splits: W[row][c] = sum_split partial (binary64) and
 // Wd[row][c] = lambda_row * W (storage type) for pass 2.
 hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t rank, int m16,
@@ -118,7 +121,7 @@ hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t ra
 // of KV in part (nz x n x m, storage type), summed in chunk order into KV
 hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
                            const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
-                           void* KV, int64_t ldkv, int64_t n, int m, int prec, int hchunk, int nz,
+                           void* KV, int64_t ldkv, int64_t n, int m, int prec, int io, int hchunk, int nz,
                            void* part, hipStream_t s);
 
 // Adjoint: dX[i] (+)= dF/dx_i for F = sum_c w_c^T U C U^T v_c, restricted to

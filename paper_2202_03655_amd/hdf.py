@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libhdf.so")
 KERNELS = {"gaussian": 0, "cauchy": 1, "matern32": 2, "matern52": 3}
 HDF_FP64, HDF_MIXED = 0, 1
 HDF_MAX_DEGREE = 60
+HDF_SPLIT_TOL = 1e-6
 STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
           -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP", -7: "HDF_E_DISABLED"}
 
@@ -46,6 +47,7 @@ class HDFInfo(ctypes.Structure):
         ("s_k", ctypes.c_int32 * (HDF_MAX_DEGREE // 2 + 1)),
         ("rank_rule", ctypes.c_int32), ("tau_bound", ctypes.c_double), ("est_error", ctypes.c_double),
         ("degree_bound", ctypes.c_int32), ("storage", ctypes.c_int32), ("chunk_points", ctypes.c_int64),
+        ("factor_precision", ctypes.c_int32),
     ]
 
 
@@ -145,6 +147,24 @@ def _dev2d(t, dtype, name):
     return t
 
 
+def _check_out(out, n, m, dtype, device):
+    """A caller-supplied output of a product: n x m, the factor's dtype and device, unit inner
+    stride (the library writes rows of m values at out + i * stride(0)); None allocates one."""
+    if out is None:
+        return torch.empty((n, m), dtype=dtype, device=device)
+    if not isinstance(out, torch.Tensor) or not out.is_cuda:
+        raise TypeError("out must be a CUDA (HIP) tensor")
+    if out.dtype != dtype:
+        raise TypeError(f"out must be {dtype}, got {out.dtype}")
+    if out.device != device:
+        raise ValueError(f"out must be on {device}, got {out.device}")
+    if out.dim() != 2 or tuple(out.shape) != (n, m):
+        raise ValueError(f"out must have shape ({n}, {m}), got {tuple(out.shape)}")
+    if out.stride(1) != 1 or out.stride(0) < m:
+        raise ValueError("out must have unit inner stride and row stride >= m")
+    return out
+
+
 class Factor:
     """Handle of a built HDF factor K ~ U D U^T (owns the library handle)."""
 
@@ -188,8 +208,7 @@ class Factor:
         if V2.shape[0] != self.n:
             raise ValueError("V must have n rows")
         m = V2.shape[1]
-        if out is None:
-            out = torch.empty((self.n, m), dtype=self.dtype, device=V2.device)
+        out = _check_out(out, self.n, m, self.dtype, V2.device)
         _check(lib().hdf_matvec(self._h, V2.data_ptr(), m, V2.stride(0), out.data_ptr(),
                                 out.stride(0), _stream()))
         return out[:, 0] if squeeze else out
@@ -232,11 +251,16 @@ class Factor:
                                   a.ctypes.data))
         return dict(index_table=table[:H], lam=lam[:S], radial_coef=coef[:ncoef], a=a, info=inf)
 
+    def factor_dtype(self):
+        """Storage type of the factor (binary64 for HDF_MIXED builds at tol <= HDF_SPLIT_TOL)."""
+        return torch.float32 if self.info()["factor_precision"] == HDF_MIXED else torch.float64
+
     def factor_parts(self):
-        """(phi, q) copies: H x n harmonics and S x n radial functions."""
+        """(phi, q) copies: H x n harmonics and S x n radial functions, in the factor's storage type."""
         inf = self.info()
-        phi = torch.empty((inf["n_harmonics"], self.n), dtype=self.dtype, device=self.device)
-        q = torch.empty((inf["n_radial"], self.n), dtype=self.dtype, device=self.device)
+        fdt = self.factor_dtype()
+        phi = torch.empty((inf["n_harmonics"], self.n), dtype=fdt, device=self.device)
+        q = torch.empty((inf["n_radial"], self.n), dtype=fdt, device=self.device)
         _check(lib().hdf_copy_factor(self._h, phi.data_ptr() if phi.numel() else None, self.n,
                                      q.data_ptr() if q.numel() else None, self.n, _stream()))
         return phi, q
@@ -279,8 +303,7 @@ class CrossFactor(Factor):
         if W2.shape[0] != self.n_y:
             raise ValueError("W must have n_y rows")
         m = W2.shape[1]
-        if out is None:
-            out = torch.empty((self.n, m), dtype=self.dtype, device=W2.device)
+        out = _check_out(out, self.n, m, self.dtype, W2.device)
         _check(lib().hdf_matvec(self._h, W2.data_ptr(), m, W2.stride(0), out.data_ptr(),
                                 out.stride(0), _stream()))
         return out[:, 0] if squeeze else out
@@ -291,8 +314,9 @@ class CrossFactor(Factor):
     def factor_parts_y(self):
         """(phi, q) copies at the Y points: H x n_y and S x n_y."""
         inf = self.info()
-        phi = torch.empty((inf["n_harmonics"], self.n_y), dtype=self.dtype, device=self.device)
-        q = torch.empty((inf["n_radial"], self.n_y), dtype=self.dtype, device=self.device)
+        fdt = self.factor_dtype()
+        phi = torch.empty((inf["n_harmonics"], self.n_y), dtype=fdt, device=self.device)
+        q = torch.empty((inf["n_radial"], self.n_y), dtype=fdt, device=self.device)
         _check(lib().hdf_copy_factor_y(self._h, phi.data_ptr() if phi.numel() else None, self.n_y,
                                        q.data_ptr() if q.numel() else None, self.n_y, _stream()))
         return phi, q

@@ -384,6 +384,26 @@ def test_guarantee_against_dense(d, name, l, tol, N):
     np.testing.assert_allclose(hdf.matvec(st, V, U, Dv), ((U * Dv) @ U.T) @ V, rtol=1e-11, atol=1e-11)
 
 
+@pytest.mark.parametrize("N,chunk", [(1001, 128), (1001, 97), (37, 1), (600, 600), (600, 10_000)])
+def test_chunked_matvec_and_passes(N, chunk):
+    """The point-chunked, matrix-free product (U re-evaluated per chunk from the radial
+    coefficients E) against the product of the assembled factor (columns Q W_s from the QR):
+    element by element, every row, for ragged last chunks, one-point chunks, one chunk and a
+    chunk longer than N.  A chunk boundary that drops, repeats or shifts rows fails here."""
+    rng = np.random.default_rng(31)
+    X = unit_ball(rng, N, 4)
+    st = hdf.build(X, "gaussian", 0.7, 1e-5)
+    U, Dv = hdf.factor(st)
+    V = rng.normal(size=(N, 3))
+    ref = hdf.matvec(st, V, U, Dv)
+    got = hdf.matvec_chunked(st, V, chunk=chunk)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.max(np.abs(ref)))
+    P = hdf.passes(st, V, chunk=chunk)
+    PU = U.T @ V
+    np.testing.assert_allclose(P, PU, rtol=0, atol=1e-12 * np.max(np.abs(PU)))
+
+
 def test_rank_vs_optimal_reported(capsys):
     rng = np.random.default_rng(8)
     X = unit_ball(rng, 1000, 3)
