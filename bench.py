@@ -181,6 +181,67 @@ def run_cross(wname, X, nq, m, precision, steps, warmup):
             "step": "hdf_build_cross + hdf_matvec"}
 
 
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+MFMA_FILE = os.path.join(ROOT, "profiles", "pmc_mfma.txt")
+
+
+def read_mfma_busy(kernel, workload):
+    """MFMA pipe busy fraction (SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x SQ_BUSY_CU_CYCLES)) from the
+    committed rocprofv3 --pmc summary, or None when the kernels changed since it was taken."""
+    if not os.path.exists(MFMA_FILE):
+        return None
+    src = kernel_source_hash()
+    for line in open(MFMA_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if len(f) >= 4 and f[0] == kernel and f[1] == workload:
+            return float(f[3]) if f[2] == src else None
+    return None
+
+
+def run_mfma_line(wname, m, reps=5):
+    """The two passes of K~V on a resident factor of workload wname with m right-hand sides (the MFMA-bound
+    regime when 2 r m flops per point exceed the ridge times the factor bytes): kernel times from HIP events
+    inside the library, algorithmic MFMA flops 2 N r m per pass against the peak of the factor's type."""
+    import numpy as np
+    import torch
+    from paper_2202_03655_amd import hdf, workloads
+    cfg = hdf_cfg(wname)
+    X = workloads.points(wname).astype(np.float32)
+    Xd = torch.tensor(X, device="cuda")
+    V = torch.tensor(workloads.rhs(len(X), m, 7).astype(np.float32), device="cuda")
+    out = torch.empty_like(V)
+    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=hdf.HDF_MIXED)
+    for _ in range(2):
+        f.matvec(V, out=out)
+    t1, t2 = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.matvec(V, out=out)
+        inf = f.info()
+        t1.append(inf["t_mv_t_ms"])
+        t2.append(inf["t_mv_n_ms"])
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t0) / reps
+    inf = f.info()
+    n, r = len(X), inf["rank"]
+    ftype = "f32" if inf["factor_precision"] == hdf.HDF_MIXED else "f64"
+    flops = 2.0 * n * r * m
+    peak = MFMA_PEAK_TFLOPS[ftype]
+    p1, p2 = sorted(t1)[len(t1) // 2], sorted(t2)[len(t2) // 2]
+    el = 4 if ftype == "f32" else 8
+    intensity = flops / ((inf["n_harmonics"] + inf["n_radial"] + m) * el * n)
+    return {"workload": wname, "rhs": m, "factor": ftype, "rank": r, "n_points": n,
+            "flop_per_byte": round(intensity, 1), "ridge_flop_per_byte": round(peak * 1e12 / 8e12, 1),
+            "matvec_ms": round(wall, 3),
+            "pass1": {"ms": round(p1, 4), "tflops": round(flops / (p1 * 1e-3) / 1e12, 1), "peak": peak,
+                      "frac": round(flops / (p1 * 1e-3) / 1e12 / peak, 4)},
+            "pass2": {"ms": round(p2, 4), "tflops": round(flops / (p2 * 1e-3) / 1e12, 1), "peak": peak,
+                      "frac": round(flops / (p2 * 1e-3) / 1e12 / peak, 4)}}
+
+
 def hdf_cfg(wname):
     from paper_2202_03655_amd import workloads
     return workloads.CONFIGS[wname]
@@ -361,6 +422,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--no-krr", action="store_true", help="skip the KRR consumer (Sec. 4.2)")
     ap.add_argument("--no-matrix-free", action="store_true", help="skip the matrix-free factor run")
+    ap.add_argument("--no-mfma-lines", action="store_true", help="skip the 64-RHS (MFMA-bound) product lines")
     ap.add_argument("--krr-only", action="store_true",
                     help="run only the KRR consumer and print its JSON object (for profiling)")
     ap.add_argument("--cross", type=int, default=0, metavar="NQ",
@@ -477,6 +539,31 @@ def main():
                               "pass2_with_eval_ms": round(rm["k_mv_n_ms"], 4),
                               "chunk_points": mi["chunk_points"], "scratch_bytes": mi["factor_bytes"],
                               "stored_factor_bytes": info["factor_bytes"], "rank": mi["rank"]}
+    # MFMA: the passes' algorithmic flops (2 N r m each) against the FP32 MFMA peak, live; the MFMA pipe
+    # busy fraction from the committed PMC summary (None once the kernels changed)
+    fl = 2.0 * N * r * m
+    ptype = "f32" if info["factor_precision"] == 1 else "f64"
+    pk = MFMA_PEAK_TFLOPS[ptype]
+    out["mfma"] = {
+        "peak_tflops": pk,
+        "pass1": {"tflops": round(fl / (res["k_mv_t_ms"] * 1e-3) / 1e12, 1),
+                  "frac": round(fl / (res["k_mv_t_ms"] * 1e-3) / 1e12 / pk, 4),
+                  "pipe_busy_pmc": read_mfma_busy("k_mv_t", args.workload)},
+        "pass2": {"tflops": round(fl / (res["k_mv_n_ms"] * 1e-3) / 1e12, 1),
+                  "frac": round(fl / (res["k_mv_n_ms"] * 1e-3) / 1e12 / pk, 4),
+                  "pipe_busy_pmc": read_mfma_busy("k_mv_n", args.workload)},
+        "gram": {"pipe_busy_pmc": read_mfma_busy("k_gram", args.workload)},
+    }
+    if not args.no_mfma_lines:
+        # 64 right-hand sides: 2 r m flops per point above the ridge times the factor bytes (MFMA-bound)
+        out["mfma_lines"] = [run_mfma_line(args.workload, 64)]
+        if args.workload != "shell6_matern52_l8":
+            out["mfma_lines"].append(run_mfma_line("shell6_matern52_l8", 64))
+        for ln in out["mfma_lines"]:
+            print(f"# m=64 {ln['workload']} ({ln['factor']} factor, {ln['flop_per_byte']} flop/B): pass 1 "
+                  f"{ln['pass1']['ms']} ms {ln['pass1']['tflops']} TF ({ln['pass1']['frac']:.2%}), pass 2 "
+                  f"{ln['pass2']['ms']} ms {ln['pass2']['tflops']} TF ({ln['pass2']['frac']:.2%})",
+                  file=sys.stderr, flush=True)
     if args.cross:
         out["cross"] = run_cross(args.workload, X, args.cross, m, args.precision, args.steps, args.warmup)
     if not args.no_krr:

@@ -214,14 +214,15 @@ struct hdf_factor {
   DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
       lam_row, moments;
   int n_tiles = 0, tiles_cpl = 0;                 // pass-1 work items for cpl = m16/16
-  // LDS-staged pass 1: items (degree, 16-row tile, column tile), groups
-  DevBuf items_dev, gitems_dev, gq_dev;
-  int items_cpl = 0, n_groups = 0, max_nq = 0;
+  // tile-major pass 1 (m16 <= 64): wave items and their workgroup groups for each cpl = m16 / 16
+  // in 1..4, built with the factor; tile_tabs holds all wave items, then all groups
+  DevBuf tile_tabs;
+  int tw_off[5] = {0, 0, 0, 0, 0}, tg_off[5] = {0, 0, 0, 0, 0}, n_tgroups[5] = {0, 0, 0, 0, 0};
+  size_t tg_base = 0;                             // byte offset of the groups in tile_tabs
   // host copies of uploaded build tables: they outlive their asynchronous uploads
   std::vector<std::vector<char>> host_keep;
   // host copies of the pass-1 tables: they outlive their asynchronous uploads
-  std::vector<hdf::TileDev> tiles_host, items_host;
-  std::vector<int32_t> gi_host, gq_host;
+  std::vector<hdf::TileDev> tiles_host;
   // matvec / adjoint workspace
   DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
   DevBuf cphi, cq;                                // matrix-free chunk scratch
@@ -315,6 +316,48 @@ void loop_order_columns(int d, int K, const std::unordered_map<uint64_t, int>& c
 static hipError_t clear_padding(void* base, int64_t rows, int64_t n, int64_t ld, size_t el, hipStream_t s) {
   if (rows <= 0 || ld <= n) return hipSuccess;
   return hipMemset2DAsync((char*)base + n * el, ld * el, 0, (ld - n) * el, rows, s);
+}
+
+// Wave items of the tile-major pass 1 for cpl = m16 / 16 (1..4): one per 16 harmonics of a kept
+// degree and range of its radial functions (nl * nct accumulator tiles at most), then groups of up
+// to kMvtWavesPerGroup consecutive items whose radial rows span at most kMvtMaxNq rows.
+static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl, std::vector<hdf::MvtWave>& tw,
+                        std::vector<hdf::MvtGroup>& tg) {
+  const int nct_t = cpl == 1 ? 1 : (cpl == 2 ? 2 : 4);
+  const int nlmax = hdf::matvec_tile_acc(fprec) / nct_t;
+  const int w_base = (int)tw.size();
+  for (const hdf::DegDev& dg : degs)
+    for (int h0 = 0; h0 < dg.nh; h0 += 16)
+      for (int l0 = 0; l0 < dg.s; l0 += nlmax) {
+        hdf::MvtWave w{};
+        w.row0 = dg.hoff + h0;
+        w.nr = std::min(16, dg.nh - h0);
+        w.qrow = dg.qoff + l0;
+        w.nl = std::min(nlmax, dg.s - l0);
+        w.ct0 = 0;
+        w.nct = cpl;
+        w.out0 = dg.roff + h0 * dg.s + l0;
+        w.s = dg.s;
+        tw.push_back(w);
+      }
+  for (size_t i = (size_t)w_base; i < tw.size();) {
+    hdf::MvtGroup gr{};
+    gr.w0 = (int32_t)(i - (size_t)w_base);
+    int lo = tw[i].qrow, hi = tw[i].qrow + tw[i].nl;
+    size_t j = i + 1;
+    while (j < tw.size() && j - i < (size_t)hdf::kMvtWavesPerGroup) {
+      const int lo2 = std::min(lo, tw[j].qrow), hi2 = std::max(hi, tw[j].qrow + tw[j].nl);
+      if (hi2 - lo2 > hdf::kMvtMaxNq) break;
+      lo = lo2;
+      hi = hi2;
+      ++j;
+    }
+    gr.nw = (int32_t)(j - i);
+    gr.q_lo = lo;
+    gr.nq = hi - lo;
+    tg.push_back(gr);
+    i = j;
+  }
 }
 
 static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
@@ -450,6 +493,22 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     HIPCHK(upload(f->q_off, qo.data(), qo.size() * 4));
     // contraction tables
     HIPCHK(upload(f->degs_dev, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev)));
+    {
+      std::vector<hdf::MvtWave> tw;
+      std::vector<hdf::MvtGroup> tg;
+      for (int cpl = 1; cpl <= 4; ++cpl) {
+        f->tw_off[cpl] = (int)tw.size();
+        f->tg_off[cpl] = (int)tg.size();
+        tile_tables(f->degs, f->fprec, cpl, tw, tg);
+        f->n_tgroups[cpl] = (int)tg.size() - f->tg_off[cpl];
+      }
+      const size_t wb = tw.size() * sizeof(hdf::MvtWave);
+      f->tg_base = (wb + 255) / 256 * 256;
+      std::vector<char> tabs(f->tg_base + tg.size() * sizeof(hdf::MvtGroup), 0);
+      std::memcpy(tabs.data(), tw.data(), wb);
+      std::memcpy(tabs.data() + f->tg_base, tg.data(), tg.size() * sizeof(hdf::MvtGroup));
+      HIPCHK(upload(f->tile_tabs, tabs.data(), tabs.size()));
+    }
     std::vector<double> lr;
     lr.reserve(f->r);
     for (size_t di = 0; di < f->degs.size(); ++di) {
@@ -949,6 +1008,29 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
 
 // Pass 1 of a matrix-free factor: per chunk, evaluate the factor, then contract it into its own range
 // of split partials; one fixed-order reduction over all chunks' partials gives W.
+// Device tables of the tile-major pass 1 for cpl = m16 / 16 (1..4), built with the factor.
+static const hdf::MvtWave* tile_waves(hdf_handle h, int cpl) {
+  return (const hdf::MvtWave*)h->tile_tabs.p + h->tw_off[cpl];
+}
+static const hdf::MvtGroup* tile_groups(hdf_handle h, int cpl) {
+  return (const hdf::MvtGroup*)((const char*)h->tile_tabs.p + h->tg_base) + h->tg_off[cpl];
+}
+
+// Splits of the tile-major pass 1 over n points: about 2048 workgroups (of G groups each), splits
+// a multiple of 128 points, partial records capped at about 96 MB.
+static void tile_splits(int64_t n, int n_groups, size_t per_split, int* n_splits, int64_t* split_len) {
+  int64_t ns = std::max<int64_t>(1, 2048 / std::max(1, n_groups));
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
+  ns = std::min<int64_t>(ns, (n + 127) / 128);
+  ns = std::max<int64_t>(ns, 1);
+  int64_t len = (n + ns - 1) / ns;
+  len = (len + 127) / 128 * 128;                 // whole rounds of the kernel's four-chunk prefetch
+  *split_len = len;
+  *n_splits = (int)((n + len - 1) / len);
+}
+
+// Pass 1 of a matrix-free factor: per chunk, evaluate the factor, then contract it into its own range
+// of split partials; one fixed-order reduction over all chunks' partials gives W.
 static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
                                 DevBuf& Wd, hipStream_t s, bool timed) {
   const size_t el = h->felem();
@@ -957,7 +1039,7 @@ static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t 
   // work items and groups as for a stored factor of chunk points
   hdf_status st = pass1(h, 2, V, m, ldv, m16, W, Wd, s, false);   // side 2: tables only
   if (st != HDF_OK) return st;
-  const bool lds = m16 <= 64 && hdf::matvec_lds_bytes(m16, h->max_nq, h->fprec) <= 65536;
+  const bool tile = m16 <= 64;
   std::vector<int> splits;
   std::vector<int64_t> slen;
   int total = 0;
@@ -965,18 +1047,15 @@ static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t 
     const int64_t nc = std::min(h->chunk, h->N - c0);
     int ns;
     int64_t len;
-    if (lds) {
-      ns = (int)std::max<int64_t>(1, 1024 / std::max(1, h->n_groups));
-      ns = (int)std::min<int64_t>(ns, (nc + 255) / 256);
-      ns = std::max(ns, 1);
-      len = ((nc + ns - 1) / ns + 31) / 32 * 32;
+    if (tile) {
+      tile_splits(nc, h->n_tgroups[cpl], per_split, &ns, &len);
     } else {
       ns = (int)std::max<int64_t>(1, 16384 / std::max<int64_t>(1, (int64_t)h->n_tiles));
       ns = (int)std::min<int64_t>(ns, (nc + 1023) / 1024);
       ns = std::max(ns, 1);
       len = ((nc + ns - 1) / ns + 15) / 16 * 16;
+      ns = (int)((nc + len - 1) / len);
     }
-    ns = (int)((nc + len - 1) / len);
     splits.push_back(ns);
     slen.push_back(len);
     total += ns;
@@ -999,11 +1078,10 @@ static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t 
     if (st != HDF_OK) return st;
     const void* Vc = (const char*)V + c0 * ldv * h->ioel();
     double* part = (double*)h->ws_part.p + (size_t)slot * h->r * m16;
-    if (lds)
-      HIPCHK(hdf::launch_matvec_t_lds(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
-                                      (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
-                                      (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, Vc, ldv, nc, (int)m,
-                                      m16, splits[ci], slen[ci], h->r, part, h->fprec, h->dtype, s));
+    if (tile)
+      HIPCHK(hdf::launch_matvec_t_tile(h->cphi.p, h->ldC, h->cq.p, h->ldC, tile_waves(h, cpl), tile_groups(h, cpl),
+                                       h->n_tgroups[cpl], splits[ci], slen[ci], Vc, ldv, nc, (int)m, m16, h->r, part,
+                                       h->fprec, h->dtype, s));
     else
       HIPCHK(hdf::launch_matvec_t(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
                                   (const hdf::TileDev*)h->tiles_dev.p, h->n_tiles, h->max_s * cpl, Vc, ldv, nc,
@@ -1046,71 +1124,27 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
   const size_t per_split = (size_t)h->r * m16 * sizeof(double);
   if (side == 2 && m16 > 64) return HDF_OK;
   if (m16 <= 64) {
-    // LDS-staged variant: B operand staged once per workgroup and chunk
-    if (h->items_cpl != cpl) {
-      std::vector<hdf::TileDev>& items = h->items_host;
-      items.clear();
-      for (size_t di = 0; di < h->degs.size(); ++di)
-        for (int h0 = 0; h0 < h->degs[di].nh; h0 += 16)
-          for (int ct = 0; ct < h->degs[di].s * cpl; ++ct) items.push_back(hdf::TileDev{(int32_t)di, h0, ct, 0});
-      // few points (a factor of a small cluster): smaller groups, so that the launch still has
-      // >= 512 workgroups; the splits over points are at most (n + 255) / 256
-      int per = hdf::matvec_items_per_group();
-      const int64_t max_splits = std::min<int64_t>((n + 255) / 256, 1024);
-      while (per > 4 && (int64_t)((items.size() + per - 1) / per) * max_splits < 512) per /= 2;
-      std::vector<int32_t>& gi = h->gi_host;
-      std::vector<int32_t>& gq = h->gq_host;
-      gi.clear();
-      gq.clear();
-      int max_nq = 0;
-      for (size_t i0 = 0; i0 < items.size(); i0 += per) {
-        const size_t i1 = std::min(items.size(), i0 + per);
-        gi.push_back((int32_t)i0);
-        const int qlo = h->degs[items[i0].deg].qoff;
-        const int qhi = h->degs[items[i1 - 1].deg].qoff + h->degs[items[i1 - 1].deg].s;
-        gq.push_back(qlo);
-        gq.push_back(qhi);
-        max_nq = std::max(max_nq, qhi - qlo);
-      }
-      gi.push_back((int32_t)items.size());
-      HIPCHK(h->items_dev.ensure(items.size() * sizeof(hdf::TileDev)));
-      HIPCHK(h->gitems_dev.ensure(gi.size() * 4));
-      HIPCHK(h->gq_dev.ensure(gq.size() * 4));
-      HIPCHK(hipMemcpyAsync(h->items_dev.p, items.data(), items.size() * sizeof(hdf::TileDev), hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(h->gitems_dev.p, gi.data(), gi.size() * 4, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(h->gq_dev.p, gq.data(), gq.size() * 4, hipMemcpyHostToDevice, s));
-      h->n_groups = (int)gi.size() - 1;
-      h->max_nq = max_nq;
-      h->items_cpl = cpl;
-    }
+    // tile-major variant: the wave items and groups of this cpl were built with the factor
     if (side == 2) return HDF_OK;
-    if (hdf::matvec_lds_bytes(m16, h->max_nq, h->fprec) <= 65536) {
-      int n_splits = (int)std::max<int64_t>(1, 1024 / std::max(1, h->n_groups));
-      n_splits = (int)std::min<int64_t>(n_splits, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
-      n_splits = (int)std::min<int64_t>(n_splits, (n + 255) / 256);
-      n_splits = std::max(n_splits, 1);
-      int64_t split_len = (n + n_splits - 1) / n_splits;
-      split_len = (split_len + 31) / 32 * 32;
-      n_splits = (int)((n + split_len - 1) / split_len);
-      HIPCHK(h->ws_part.ensure(per_split * n_splits));
-      HIPCHK(W.ensure((size_t)h->r * m16 * sizeof(double)));
-      HIPCHK(Wd.ensure((size_t)h->r * m16 * el));
-      if (timed) {
-        if (!h->ev_mv[0])
-          for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
-        HIPCHK(hipEventRecord(h->ev_mv[0], s));
-      }
-      HIPCHK(hdf::launch_matvec_t_lds(phi, ldn, qv, ldn, (const hdf::DegDev*)h->degs_dev.p,
-                                      (const hdf::TileDev*)h->items_dev.p, (const int32_t*)h->gitems_dev.p,
-                                      (const int32_t*)h->gq_dev.p, h->n_groups, h->max_nq, V, ldv, n,
-                                      (int)m, m16, n_splits, split_len, h->r, (double*)h->ws_part.p,
-                                      h->fprec, h->dtype, s));
-      if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
-      HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
-                                       (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->fprec, s));
-      if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
-      return HDF_OK;
+    int n_splits;
+    int64_t split_len;
+    tile_splits(n, h->n_tgroups[cpl], per_split, &n_splits, &split_len);
+    HIPCHK(h->ws_part.ensure(per_split * n_splits));
+    HIPCHK(W.ensure((size_t)h->r * m16 * sizeof(double)));
+    HIPCHK(Wd.ensure((size_t)h->r * m16 * el));
+    if (timed) {
+      if (!h->ev_mv[0])
+        for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
+      HIPCHK(hipEventRecord(h->ev_mv[0], s));
     }
+    HIPCHK(hdf::launch_matvec_t_tile(phi, ldn, qv, ldn, tile_waves(h, cpl), tile_groups(h, cpl), h->n_tgroups[cpl],
+                                     n_splits, split_len, V, ldv, n, (int)m, m16, h->r, (double*)h->ws_part.p,
+                                     h->fprec, h->dtype, s));
+    if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
+    HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16,
+                                     (const double*)h->lam_row.p, (double*)W.p, Wd.p, h->fprec, s));
+    if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
+    return HDF_OK;
   }
   if (side == 2) return HDF_OK;
   // about 16k wavefronts in pass 1, partial records capped at ~96 MB

@@ -1381,271 +1381,262 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
   }
 }
 
-// Pass 1 with the B operand staged in LDS.  A workgroup (4 wavefronts) owns
-// a group of up to 4 * kMvTPW work items (one 16-harmonic row tile x one
-// 16-wide output column tile each, degrees contiguous) and a range of points.
-// Per 32-point chunk it stages V (32 x m16) and the group's radial rows
-// (nq x 32) in LDS; every wavefront streams the Phi rows of its items (two
-// 16-byte loads per lane and item, in batches) and forms B = q_{k,l}(i) V[i][c]
-// from LDS.  Software pipeline: the Phi loads of the next batch (possibly the
-// first batch of the next chunk) are issued before the MFMAs of the current
-// one, and the next chunk's V and q are loaded into registers at the start of
-// a chunk and written to the other half of a double-buffered LDS area at its
-// end, so one barrier per chunk suffices.  All item accumulators stay in
-// registers for the whole point range.  Requires m16 <= 64 and nq <= 64
-// (eight staged values per thread and array).
-constexpr int kMvCH = 32;
-constexpr int kMvTPW = 16;
-constexpr int kMvStage = 8;
+// Pass 1, tile-major.  Per degree k, W_k = Phi_k (Q_k o V): every wave item
+// owns one 16-row tile of Phi_k and up to eight accumulator tiles (radial
+// function l, column tile ct), so one pair of 16-byte loads of the tile's
+// values per lane and 32-point chunk feeds 8 * nl * nct MFMAs.  MFMA K-step t
+// of a chunk takes the four points p + 8 g + t (lane group g) with
+//   A[r][g] = phi_{row0 + r}(p + 8 g + t),
+//   B[g][c] = q_l(p + 8 g + t) V[p + 8 g + t][16 ct + c],
+// B formed from the staged radial rows and V^T in LDS.  The tile's values are
+// prefetched PF chunks ahead into registers; the staged operands are double
+// buffered, with one barrier per chunk.  Every load is unconditional and in
+// bounds: chunk starts are clamped to the split's last chunk, Phi and Q rows
+// are padded by at least 63 points past n (zeros), V rows are clamped to n - 1
+// and the values of points past the split multiplied by zero.
+// Prefetch depth (chunks of the tile in flight) and occupancy per type and column tiles, chosen so
+// that the registers fit without spills: binary32 4 chunks deep at four wavefronts per SIMD
+// (<= 128 registers; three with four column tiles), binary64 2 deep at two (one column tile: eight
+// radial functions) or three.
+// Without the occupancy hint the scheduler hoists the B operands of all radial functions and
+// overflows the registers.
+template <typename T, int NCT> struct MvtPF { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
+template <typename T, int NCT> struct MvtWaves {
+  static constexpr int value = sizeof(T) == 4 ? (NCT < 4 ? 4 : 3) : (NCT == 1 ? 2 : 3);
+};
+// accumulator tiles per wavefront
+template <typename T> struct MvtAcc { static constexpr int value = sizeof(T) == 4 ? 8 : 4; };
+constexpr int kMvtCH = 32;                 // points per chunk
+constexpr int kMvtThreads = 64 * kMvtWavesPerGroup;
+constexpr int kMvtVS = kMvtCH + 4;         // padded staged row (LDS bank spread)
 
-template <typename T>
-struct MvtBatch { static constexpr int value = 2; };
 
-// Eight consecutive staged radial values (16-byte aligned in LDS) with wide LDS reads.
-__device__ __forceinline__ void lds_read8(const float* p, float (&v)[8]) {
-  const floatx4 a = *reinterpret_cast<const floatx4*>(p), b = *reinterpret_cast<const floatx4*>(p + 4);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) { v[t] = a[t]; v[4 + t] = b[t]; }
-}
-__device__ __forceinline__ void lds_read8(const double* p, double (&v)[8]) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const double2 a = *reinterpret_cast<const double2*>(p + 2 * t);
-    v[2 * t] = a[0];
-    v[2 * t + 1] = a[1];
-  }
-}
-
-template <typename T, int CPL, typename TV>
-__global__ void __launch_bounds__(256) k_mv_t_lds(const T* __restrict__ phi, int64_t ld_phi,
-                                                   const T* __restrict__ q, int64_t ld_q,
-                                                   const DegDev* __restrict__ degs,
-                                                   const TileDev* __restrict__ items,
-                                                   const int32_t* __restrict__ group_items,
-                                                   const int32_t* __restrict__ group_q, int max_nq,
-                                                   const TV* __restrict__ V, int64_t ldv, int64_t n,
-                                                   int m, int m16, int64_t split_len, int64_t rank,
-                                                   double* __restrict__ part) {
+template <typename T, typename TV, int NCT>
+__global__ void __launch_bounds__(kMvtThreads) __attribute__((amdgpu_waves_per_eu(MvtWaves<T, NCT>::value, 8)))
+k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
+                                                    const T* __restrict__ q, int64_t ld_q,
+                                                    const MvtWave* __restrict__ waves,
+                                                    const MvtGroup* __restrict__ groups, int n_groups,
+                                                    int n_splits, int64_t split_len,
+                                                    const TV* __restrict__ V, int64_t ldv, int64_t n, int m,
+                                                    int m16, int64_t rank, double* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
-  constexpr int NB = MvtBatch<T>::value;
+  constexpr int PF = MvtPF<T, NCT>::value;
+  static_assert(PF % 2 == 0, "the LDS buffer of a chunk is its slot's parity");
+  constexpr int NL = MvtAcc<T>::value / NCT;
+  constexpr int CH = kMvtCH, VS = kMvtVS;
   extern __shared__ unsigned char smem_raw[];
-  const int grp = blockIdx.y, split = blockIdx.x;
-  const int it0 = group_items[grp], it1 = group_items[grp + 1];
-  const int q_lo = group_q[2 * grp], nq = group_q[2 * grp + 1] - q_lo;
-  const int vst = m16 + 1;                        // padded V row (bank spread)
-  const int half = kMvCH * vst + max_nq * kMvCH;  // one buffer: V then q
-  T* lds = reinterpret_cast<T*>(smem_raw);        // [2][half]
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  // block b runs group gi over split sp with b = 8 (G (sp / 8) + gi) + sp % 8: the workgroups of
+  // all groups over one range of points land on one XCD (dispatch is round robin over the eight),
+  // close together in time, so V and the radial rows of the range are fetched into its L2 once
+  const int b = blockIdx.x;
+  const int rest = b >> 3;
+  const int gi = rest % n_groups;
+  const int split = ((rest / n_groups) << 3) + (b & 7);
+  if (split >= n_splits) return;                    // whole workgroup, before any barrier
+  const MvtGroup gd = groups[gi];
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, g = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: item branches stay scalar
-  const int cpl = m16 / 16;
-  // a group of up to 4 * kMvTPW items is split evenly over the four wavefronts
-  const int ipw = (it1 - it0 + 3) / 4;
-  const int my0 = it0 + wave * ipw;
-  int n_mine = it1 - my0;
-  n_mine = n_mine < 0 ? 0 : (n_mine > ipw ? ipw : n_mine);
-  // per-item descriptors resolved once: first Phi row, rows in the tile,
-  // LDS offset of its radial row, output column base
-  __shared__ int64_t d_row[4 * kMvTPW];
-  __shared__ int32_t d_nr[4 * kMvTPW], d_qr[4 * kMvTPW], d_c[4 * kMvTPW];
-  if (tid < 4 * kMvTPW && it0 + tid < it1) {
-    const TileDev it = items[it0 + tid];
-    const DegDev dg = degs[it.deg];
-    const int l = it.ct0 / cpl;
-    d_row[tid] = (int64_t)(dg.hoff + it.h0);
-    d_nr[tid] = dg.nh - it.h0;
-    d_qr[tid] = kMvCH * vst + (dg.qoff + l - q_lo) * kMvCH;
-    d_c[tid] = (it.ct0 - l * cpl) * 16;
-  }
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool active = wave < gd.nw;                 // uniform
+  const MvtWave wi = waves[gd.w0 + (active ? wave : 0)];
   const int64_t p_begin = (int64_t)split * split_len;
   const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
-  const int wbase = wave * ipw;
+  const int64_t p_last = p_begin + (p_end - 1 - p_begin) / CH * CH;   // start of the split's last chunk
+  const int half = (m16 + kMvtMaxNq + 1) * VS;      // one buffer: V^T (m16 rows), radial rows, a pad row
+  // this lane's Phi row (rows past the tile repeat its first row; their outputs are not written)
+  const T* prow = phi + (int64_t)(wi.row0 + (li < wi.nr ? li : 0)) * ld_phi + 8 * g;
 
-  // staging of chunk p: thread tid owns V entries e = tid + 256 j (< 32 m16)
-  // and q entries e = tid + 256 j (< 32 nq)
-  T sv[kMvStage], sq[kMvStage];
-  auto stage_load = [&](int64_t p) {
+  auto load_tile = [&](int64_t p, T (&a)[8]) {
+    const int64_t pc = p < p_last ? p : p_last;
+    const T* r = prow + pc;
+    if constexpr (sizeof(T) == 4) {
+      const floatx4 v0 = *reinterpret_cast<const floatx4*>(r);
+      const floatx4 v1 = *reinterpret_cast<const floatx4*>(r + 4);
 #pragma unroll
-    for (int j = 0; j < kMvStage; ++j) {
-      const int e = tid + 256 * j;
+      for (int e = 0; e < 4; ++e) { a[e] = v0[e]; a[4 + e] = v1[e]; }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const doublex2 w = *reinterpret_cast<const doublex2*>(r + 2 * h);
+        a[2 * h] = w[0];
+        a[2 * h + 1] = w[1];
+      }
+    }
+  };
+  // staging of a chunk by all threads (TPB of them): V entries e = tid + TPB j (point e / m16,
+  // column e % m16; 32 m16 / TPB per thread) and the group's radial entries e = tid + TPB j (row
+  // e / 32, point e % 32; rows past nq repeat the last one and are never read).  The loads are
+  // unconditional and in bounds and keep the raw values; the masks (points past the split,
+  // columns past m) and the choice of slot are applied when the values are written to LDS, so the
+  // compiler's load-counter waits stay exact (a select right after a load, or a branch around it,
+  // makes it wait for every load in flight).
+  constexpr int TPB = kMvtThreads;
+  constexpr int SV = (CH * 16 * NCT + TPB - 1) / TPB, SQ = CH * kMvtMaxNq / TPB;
+  const int sv_n = CH * m16 / TPB;
+  // staged values are loaded with the same look-ahead as the tile (PF chunks, rotating register
+  // slots): the load counter completes in issue order, so values loaded after the tile prefetch
+  // could only be waited for together with it
+  TV sv[PF][SV];
+  T sq[PF][SQ];
+  auto stage_load = [&](int64_t p0, TV (&sv)[SV], T (&sq)[SQ]) {
+    const int64_t p = p0 < p_last ? p0 : p_last;
+#pragma unroll
+    for (int j = 0; j < SV; ++j) {
+      const int e = tid + TPB * j;
       const int pp = e / m16, c = e - pp * m16;
       const int64_t pt = p + pp;
-      sv[j] = (e < kMvCH * m16 && pt < p_end && c < m) ? (T)V[pt * ldv + c] : (T)0;
+      const int64_t ptc = pt < n ? pt : n - 1;
+      sv[j] = V[ptc * ldv + (c < m ? c : 0)];
+    }
+#pragma unroll
+    for (int j = 0; j < SQ; ++j) {
+      const int e = tid + TPB * j;
       const int r = e >> 5, pq = e & 31;
-      sq[j] = (e < kMvCH * nq && p + pq < p_end) ? q[(int64_t)(q_lo + r) * ld_q + p + pq] : (T)0;
+      const int rc = r < gd.nq ? r : gd.nq - 1;
+      sq[j] = q[(int64_t)(gd.q_lo + rc) * ld_q + p + pq];
     }
   };
-  auto stage_store = [&](T* buf) {
+  // values of the chunk starting at p into buf; entries past the staged area go to the pad row
+  auto stage_store = [&](T* buf, int64_t p, const TV (&sv)[SV], const T (&sq)[SQ]) {
 #pragma unroll
-    for (int j = 0; j < kMvStage; ++j) {
-      const int e = tid + 256 * j;
+    for (int j = 0; j < SV; ++j) {
+      const int e = tid + TPB * j;
       const int pp = e / m16, c = e - pp * m16;
-      if (e < kMvCH * m16) buf[pp * vst + c] = sv[j];
-      if (e < kMvCH * nq) buf[kMvCH * vst + e] = sq[j];
+      const bool ok = p + pp < p_end && c < m;
+      const int at = j < sv_n ? c * VS + pp : (m16 + kMvtMaxNq) * VS + (tid & 31);
+      buf[at] = ok ? (T)sv[j] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < SQ; ++j) {
+      const int e = tid + TPB * j;
+      buf[m16 * VS + (e >> 5) * VS + (e & 31)] = sq[j];
     }
   };
-  // Phi rows of items [b0, b0 + NB) at chunk p, loaded without masks: a lane
-  // past its degree's last harmonic reads the tile's first row (its output
-  // rows are never written), an item past n_mine repeats the first item, and
-  // points past the split meet a zero B operand.  Every load is in bounds:
-  // p is a multiple of 32 below n and the rows are padded to at least the
-  // next multiple of 64 plus 64 columns.
-  // row offsets from phi (global loads, not flat) in units of 64 elements: ld_phi is a multiple of 64,
-  // and 2^32 such units exceed any device memory, so 32 bits per item suffice
-  uint32_t prow[kMvTPW];
-  // the rows of items [b0, b0 + NB) (first = false: of items [0, NB)) at chunk p; b0 is a compile-time
-  // constant, so the offsets are selected, never indexed at run time (which would keep them in scratch)
-  auto load_batch = [&](int64_t p, int b0, T (&a)[NB][8], bool first = false) {
-    const int64_t pb = p + 8 * g;
+  auto lds8 = [&](const T* p, T (&v)[8]) {
+    if constexpr (sizeof(T) == 4) {
+      const floatx4 a = *reinterpret_cast<const floatx4*>(p), b = *reinterpret_cast<const floatx4*>(p + 4);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const uint32_t ro = first ? prow[j] : prow[b0 + j];
-      const T* r = phi + (((int64_t)ro << 6) + pb);
-      if constexpr (sizeof(T) == 4) {
-        const floatx4 v0 = *reinterpret_cast<const floatx4*>(r);
-        const floatx4 v1 = *reinterpret_cast<const floatx4*>(r + 4);
+      for (int t = 0; t < 4; ++t) { v[t] = a[t]; v[4 + t] = b[t]; }
+    } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { a[j][e] = v0[e]; a[j][4 + e] = v1[e]; }
-      } else {
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const doublex2 w = *reinterpret_cast<const doublex2*>(r + 2 * h);
-          a[j][2 * h] = w[0];
-          a[j][2 * h + 1] = w[1];
-        }
+      for (int t = 0; t < 4; ++t) {
+        const double2 a = *reinterpret_cast<const double2*>(p + 2 * t);
+        v[2 * t] = a[0];
+        v[2 * t + 1] = a[1];
       }
     }
   };
 
-  Acc acc[kMvTPW];
+  Acc acc[NL][NCT];
 #pragma unroll
-  for (int i = 0; i < kMvTPW; ++i) acc[i] = Acc{0, 0, 0, 0};
-  stage_load(p_begin);
-  __syncthreads();                                // descriptors visible
-  // per-item row pointers and radial-row offsets, held in registers for the whole point range
-  int rq[kMvTPW];
+  for (int j = 0; j < NL; ++j)
 #pragma unroll
-  for (int i = 0; i < kMvTPW; ++i) {
-    const bool any = n_mine > 0;
-    const int di = wbase + (i < n_mine ? i : 0);
-    const int nr = any ? d_nr[di] : 1;
-    prow[i] = (uint32_t)((((any ? d_row[di] : 0) + (li < nr ? li : 0)) * ld_phi) >> 6);
-    rq[i] = (any ? d_qr[di] : kMvCH * vst) + 8 * g;
+    for (int ct = 0; ct < NCT; ++ct) acc[j][ct] = Acc{0, 0, 0, 0};
+  // slot j holds chunk c = j (mod PF): the tile in a[j], its staged values in sv[j], sq[j].  The
+  // chunk loop runs in whole groups of PF chunks; chunks past the split load clamped, in-bounds
+  // data and meet zero V values, so they add nothing.
+  T a[PF][8];
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    load_tile(p_begin + j * CH, a[j]);
+    stage_load(p_begin + j * CH, sv[j], sq[j]);
   }
-  stage_store(lds);
-  T a_cur[NB][8], a_nxt[NB][8];
-  if (n_mine > 0) load_batch(p_begin, 0, a_cur);
+  stage_store(lds, p_begin, sv[0], sq[0]);
+  stage_load(p_begin + PF * CH, sv[0], sq[0]);     // slot 0 next holds chunk PF
   __syncthreads();
-  int buf = 0;
-  for (int64_t p = p_begin; p < p_end; p += kMvCH) {
-    const int64_t pn = p + kMvCH;
-    const bool has_next = pn < p_end;             // uniform
-    if (has_next) stage_load(pn);
-    const T* cur = lds + buf * half;
-    // CPL > 0: this lane's V values of the chunk (points 8 g + t, column 16 cc + li), shared by the
-    // items; CPL == 0: every item reads its V values from LDS
-    T vr[CPL > 0 ? CPL : 1][8];
+  const int qr0 = wi.qrow - gd.q_lo;
+  const int64_t n_chunks = (p_end - p_begin + CH - 1) / CH;
+  const int64_t n_rounds = (n_chunks + PF - 1) / PF;
+  for (int64_t it = 0; it < n_rounds; ++it) {
 #pragma unroll
-    for (int cc = 0; cc < CPL; ++cc)
+    for (int j = 0; j < PF; ++j) {
+      const int64_t pc = p_begin + (it * PF + j) * CH;
+      const int buf = j & 1;                        // PF is even: chunk parity = slot parity
+      const T* cur = lds + buf * half;
+      if (active) {                                 // uniform
 #pragma unroll
-      for (int t = 0; t < 8; ++t) vr[cc][t] = cc < cpl ? cur[(8 * g + t) * vst + 16 * cc + li] : (T)0;
-    if (n_mine > 0) {                             // uniform
+        for (int ct = 0; ct < NCT; ++ct) {
+          if (ct < wi.nct) {                        // uniform
+            T v[8];
+            lds8(cur + (16 * (wi.ct0 + ct) + li) * VS + 8 * g, v);
 #pragma unroll
-      for (int b0 = 0; b0 < kMvTPW; b0 += NB) {
-        if (b0 < n_mine) {                        // uniform
-          // next step: the following batch of this chunk, else batch 0 of
-          // the next chunk (re-reads this chunk's first batch at the end)
-          const bool same = b0 + NB < n_mine;
-          load_batch(same ? p : (has_next ? pn : p), b0 + NB < kMvTPW ? b0 + NB : 0, a_nxt, !same);
-          if constexpr (CPL > 0) {
-            // the batch's radial values first (offsets of items past n_mine are valid), so one
-            // wait covers the LDS reads of the whole batch
-            T q8[NB][8];
+            for (int l = 0; l < NL; ++l) {
+              if (l < wi.nl) {                      // uniform
+                T q8[8];
+                lds8(cur + m16 * VS + (qr0 + l) * VS + 8 * g, q8);
 #pragma unroll
-            for (int j = 0; j < NB; ++j) lds_read8(cur + rq[b0 + j], q8[j]);
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              const int i = b0 + j;
-              if (i < n_mine) {                   // uniform
-                const int ci = CPL > 1 ? d_c[wbase + i] >> 4 : 0;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                  T v = vr[0][t];
-#pragma unroll
-                  for (int cc = 1; cc < CPL; ++cc) v = ci == cc ? vr[cc][t] : v;
-                  acc[i] = Mfma<T>::run(a_cur[j][t], q8[j][t] * v, acc[i]);
-                }
+                for (int t = 0; t < 8; ++t) acc[l][ct] = Mfma<T>::run(a[j][t], q8[t] * v[t], acc[l][ct]);
               }
             }
-          } else {
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              const int i = b0 + j;
-              if (i < n_mine) {                   // uniform
-                const T* qb = cur + rq[i];
-                const T* vb = cur + (8 * g) * vst + d_c[wbase + i] + li;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) acc[i] = Mfma<T>::run(a_cur[j][t], qb[t] * vb[t * vst], acc[i]);
-              }
-            }
+            // column tiles one after the other: hoisting the operands of all of them overflows the
+            // registers of the binary64 shapes
+            if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
           }
-#pragma unroll
-          for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int t = 0; t < 8; ++t) a_cur[j][t] = a_nxt[j][t];
         }
       }
+      load_tile(pc + PF * CH, a[j]);
+      // chunk pc + CH: its staged values (slot j + 1) go to the other buffer, and the slot is
+      // refilled with chunk pc + CH + PF CH
+      TV (&svn)[SV] = sv[(j + 1) % PF];
+      T (&sqn)[SQ] = sq[(j + 1) % PF];
+      stage_store(lds + (buf ^ 1) * half, pc + CH, svn, sqn);
+      stage_load(pc + CH + PF * CH, svn, sqn);
+      __syncthreads();
     }
-    if (has_next) stage_store(lds + (buf ^ 1) * half);
-    __syncthreads();
-    buf ^= 1;
   }
+  if (!active) return;
   double* out = part + (int64_t)split * rank * m16;
 #pragma unroll
-  for (int i = 0; i < kMvTPW; ++i) {
-    if (i < n_mine) {
-      const TileDev it = items[my0 + i];
-      const DegDev dg = degs[it.deg];
-      const int l = it.ct0 / cpl;
-      const int c = (it.ct0 - l * cpl) * 16 + li;
+  for (int l = 0; l < NL; ++l) {
+    if (l < wi.nl) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int h = it.h0 + Mfma<T>::row(g, e);
-        if (h < dg.nh) out[(int64_t)(dg.roff + h * dg.s + l) * m16 + c] = (double)acc[i][e];
+      for (int ct = 0; ct < NCT; ++ct) {
+        if (ct < wi.nct) {
+          const int c = 16 * (wi.ct0 + ct) + li;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int h = Mfma<T>::row(g, e);
+            if (h < wi.nr) out[(int64_t)(wi.out0 + h * wi.s + l) * m16 + c] = (double)acc[l][ct][e];
+          }
+        }
       }
     }
   }
 }
 
-int matvec_items_per_group() { return 4 * kMvTPW; }
-size_t matvec_lds_bytes(int m16, int nq, int prec) {
-  if (m16 > 64 || nq > 64) return SIZE_MAX;      // beyond the per-thread staging
-  return 2 * (size_t)(kMvCH * (m16 + 1) + nq * kMvCH) * (prec == 1 ? 4 : 8);
+int matvec_tile_acc(int prec) { return prec == 1 ? MvtAcc<float>::value : MvtAcc<double>::value; }
+
+size_t matvec_tile_lds_bytes(int m16, int prec) {
+  return 2 * (size_t)(m16 + kMvtMaxNq + 1) * kMvtVS * (prec == 1 ? 4 : 8);
 }
 
-hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
-                               const DegDev* degs, const TileDev* items, const int32_t* group_items,
-                               const int32_t* group_q, int n_groups, int max_nq, const void* V,
-                               int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
-                               int64_t rank, double* partials, int prec, int io, hipStream_t s) {
-  if (ld_phi % 64 != 0) return hipErrorInvalidValue;   // row offsets are held in units of 64 elements
-  const dim3 grid(n_splits, n_groups);
-  const size_t lds = matvec_lds_bytes(m16, max_nq, prec);
-#define HDF_MVT(T, C, TV)                                                                                    \
-  k_mv_t_lds<T, C, TV><<<grid, 256, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, degs, items,         \
-                                              group_items, group_q, max_nq, (const TV*)V, ldv, n, m, m16,     \
-                                              split_len, rank, partials)
-  // V held in registers where that keeps two wavefronts per SIMD (binary32, one column tile)
-  if (prec == 1 && io == 0) {
-    if (m16 == 16) HDF_MVT(float, 1, float);
-    else HDF_MVT(float, 0, float);
-  } else if (prec == 0 && io == 1) {
-    HDF_MVT(double, 0, double);
-  } else if (prec == 0 && io == 0) {
-    HDF_MVT(double, 0, float);
-  } else {
+hipError_t launch_matvec_t_tile(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                                const MvtWave* waves, const MvtGroup* groups, int n_groups, int n_splits,
+                                int64_t split_len, const void* V, int64_t ldv, int64_t n, int m, int m16,
+                                int64_t rank, double* partials, int prec, int io, hipStream_t s) {
+  if (m16 < 16 || m16 > 64 || m16 % 16 || n_groups < 1 || n_splits < 1 || split_len % kMvtCH)
     return hipErrorInvalidValue;
-  }
-#undef HDF_MVT
+  if ((int64_t)(n_splits - 1) * split_len >= n || (int64_t)n_splits * split_len < n) return hipErrorInvalidValue;
+  const int cpl = m16 / 16;
+  const size_t lds = matvec_tile_lds_bytes(m16, prec);
+  const unsigned n_blocks = (unsigned)(((n_splits + 7) / 8) * 8 * n_groups);
+#define HDF_MVTT(T, TV, NC)                                                                                   \
+  k_mv_t_tile<T, TV, NC><<<n_blocks, kMvtThreads, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, waves, groups,   \
+                                                    n_groups, n_splits, split_len, (const TV*)V, ldv, n, m,   \
+                                                    m16, rank, partials)
+#define HDF_MVTT_NCT(T, TV)                                                                                   \
+  do {                                                                                                        \
+    if (cpl == 1) HDF_MVTT(T, TV, 1);                                                                         \
+    else if (cpl == 2) HDF_MVTT(T, TV, 2);                                                                    \
+    else HDF_MVTT(T, TV, 4);                                                                                  \
+  } while (0)
+  if (prec == 1 && io == 0) HDF_MVTT_NCT(float, float);
+  else if (prec == 0 && io == 1) HDF_MVTT_NCT(double, double);
+  else if (prec == 0 && io == 0) HDF_MVTT_NCT(double, float);
+  else return hipErrorInvalidValue;
+#undef HDF_MVTT_NCT
+#undef HDF_MVTT
   return hipGetLastError();
 }
 

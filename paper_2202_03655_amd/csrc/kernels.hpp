@@ -100,17 +100,37 @@ hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64
                            const void* V, int64_t ldv, int64_t n, int m, int m16, int n_splits,
                            int64_t split_len, int64_t rank, double* partials, int prec, int io,
                            hipStream_t s);
-// Pass 1 with V and the radial rows staged in LDS per workgroup.  Items are
-// (degree, 16-row tile h0, column tile ct0) with degrees contiguous; group g
-// owns items [group_items[g], group_items[g+1]) and radial rows
-// [group_q[2g], group_q[2g+1]).  Requires matvec_lds_bytes(m16, max_nq) <= 64 KiB.
-int matvec_items_per_group();
-size_t matvec_lds_bytes(int m16, int nq, int prec);
-hipError_t launch_matvec_t_lds(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
-                               const DegDev* degs, const TileDev* items, const int32_t* group_items,
-                               const int32_t* group_q, int n_groups, int max_nq, const void* V,
-                               int64_t ldv, int64_t n, int m, int m16, int n_splits, int64_t split_len,
-                               int64_t rank, double* partials, int prec, int io, hipStream_t s);
+// Pass 1, tile-major (m16 <= 64).  A wave item is one 16-row tile of one
+// degree's harmonics with a range of its radial functions and the column
+// tiles [ct0, ct0 + nct), nl * nct <= matvec_tile_acc(prec) accumulator
+// tiles; one load of the tile's harmonic values feeds the MFMAs of all its
+// (l, column) slots.  A workgroup runs one group (up to kMvtWavesPerGroup wave items whose
+// radial rows lie in [q_lo, q_lo + nq), nq <= kMvtMaxNq) over one split of
+// split_len points (a multiple of 32; n_splits * split_len >= n >
+// (n_splits - 1) * split_len) and writes partial[split][row][c] (binary64)
+// for the rank rows of its wave items, every row once per split.
+struct MvtWave {
+  int32_t row0;   // first harmonic row of the tile (harmonic offset of the degree + h0)
+  int32_t nr;     // harmonic rows in the tile (<= 16)
+  int32_t qrow;   // radial row of the first radial function
+  int32_t nl;     // radial functions
+  int32_t ct0;    // first column tile
+  int32_t nct;    // column tiles (<= 4)
+  int32_t out0;   // rank row of (h0, first radial function)
+  int32_t s;      // s_k: rank-row stride between consecutive harmonics
+};
+constexpr int kMvtWavesPerGroup = 8;   // wavefronts per workgroup
+struct MvtGroup {
+  int32_t w0, nw;     // wave items [w0, w0 + nw), nw <= kMvtWavesPerGroup
+  int32_t q_lo, nq;   // radial rows staged in LDS
+};
+int matvec_tile_acc(int prec);     // accumulator tiles per wavefront (8 binary32, 4 binary64)
+constexpr int kMvtMaxNq = 32;      // staged radial rows per workgroup
+size_t matvec_tile_lds_bytes(int m16, int prec);
+hipError_t launch_matvec_t_tile(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
+                                const MvtWave* waves, const MvtGroup* groups, int n_groups, int n_splits,
+                                int64_t split_len, const void* V, int64_t ldv, int64_t n, int m, int m16,
+                                int64_t rank, double* partials, int prec, int io, hipStream_t s);
 // Reduce over splits: W[row][c] = sum_split partial (binary64) and
 // Wd[row][c] = lambda_row * W (storage type) for pass 2.
 hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t rank, int m16,

@@ -108,5 +108,8 @@ using std::min;
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 // the kernels apply it only to wave-uniform values, which every lane already holds
 #define __builtin_amdgcn_readfirstlane(x) (x)
+// instruction-scheduling hints of the device compiler: nothing to emulate
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+#define amdgpu_waves_per_eu(...) unused
 
 #endif
