@@ -217,6 +217,24 @@ hdf_status hdf_build_cross(const void* x, int64_t nx, int64_t ldx, const void* y
 hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv,
                       void* KV, int64_t ldkv, void* hip_stream);
 
+/* hdf_matvec for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and result as hdf_matvec, with 1 <= m <= 64 and a stored factor
+ * (HDF_STORE_FACTOR; else HDF_E_ARG).  It calls no hipMalloc / hipFree and no
+ * allocating routine, copies nothing from the host and records no events:
+ * its work buffers (split partials, U^T V, D U^T V) live in a fixed 32 MiB
+ * array per GPU inside the library, held until the process ends.  A factor
+ * whose rank r needs more than that (at least 20 r m16 bytes with m16 =
+ * 16 ceil(m / 16) for a binary32 factor, 24 r m16 for binary64) is rejected
+ * with HDF_E_INFEASIBLE (r up to about 100,000 at m <= 16, binary32); large
+ * ranks run pass 1 over fewer point splits than hdf_matvec does, so that the
+ * split partials fit.  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (different streams or host threads) race and must be serialised by the
+ * caller. */
+hdf_status hdf_matvec_noalloc(hdf_handle h, const void* V, int64_t m, int64_t ldv,
+                              void* KV, int64_t ldkv, void* hip_stream);
+
 /* Adjoint of F = sum_c w_c^T (U D U^T) v_c with the structure frozen at the
  * build (centre, radius, degree, radial basis and coefficients, ranks).
  *   Wm, Vm   device, n x m each with leading dimension ld (>= m).

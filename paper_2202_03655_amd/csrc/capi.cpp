@@ -1242,6 +1242,68 @@ hdf_status hdf_matvec(hdf_handle h, const void* V, int64_t m, int64_t ldv, void*
   return matvec_impl(h, V, m, ldv, KV, ldkv, (hipStream_t)hip_stream);
 }
 
+// The product without allocation: every work buffer (split partials, W, D W) lives in the
+// library's per-GPU scratch array, the pass-1 tables were built with the factor, and pass 2 runs
+// unsplit, so nothing is allocated and nothing is copied from the host.
+hdf_status hdf_matvec_noalloc(hdf_handle h, const void* V, int64_t m, int64_t ldv, void* KV, int64_t ldkv,
+                              void* hip_stream) {
+  g_err.clear();
+  if (!h) return fail(HDF_E_ARG, "handle is NULL");
+  if (!V || !KV) return fail(HDF_E_ARG, "V or KV is NULL");
+  if (m < 1 || m > 64) return fail(HDF_E_ARG, "hdf_matvec_noalloc takes 1 <= m <= 64");
+  if (ldv < m || ldkv < m) return fail(HDF_E_ARG, "leading dimensions must be >= m");
+  if (h->storage != HDF_STORE_FACTOR)
+    return fail(HDF_E_ARG, "hdf_matvec_noalloc needs a stored factor (HDF_STORE_FACTOR)");
+  const size_t io = h->ioel();
+  {
+    const char* v0 = (const char*)V;
+    const char* v1 = v0 + (((h->cross ? h->N2 : h->N) - 1) * ldv + m) * io;
+    const char* k0 = (const char*)KV;
+    const char* k1 = k0 + ((h->N - 1) * ldkv + m) * io;
+    if (v0 < k1 && k0 < v1) return fail(HDF_E_ARG, "V and KV overlap");
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (h->r == 0) {
+    HIPCHK(hipMemset2DAsync(KV, ldkv * io, 0, m * io, h->N, s));
+    return HDF_OK;
+  }
+  void* base = nullptr;
+  HIPCHK(hdf::scratch_address(&base));
+  const int m16 = (int)((m + 15) / 16 * 16), cpl = m16 / 16;
+  const size_t per_split = (size_t)h->r * m16 * sizeof(double);
+  auto round256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t w_bytes = round256((size_t)h->r * m16 * sizeof(double));
+  const size_t wd_bytes = round256((size_t)h->r * m16 * h->felem());
+  if (w_bytes + wd_bytes + per_split > hdf::kScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "rank %lld x %d columns needs %.3g MB of work space, above the %.3g MB scratch",
+             (long long)h->r, m16, (double)(w_bytes + wd_bytes + per_split) / 1e6, (double)hdf::kScratchBytes / 1e6);
+    return fail(HDF_E_INFEASIBLE, buf);
+  }
+  const int side = h->cross ? 1 : 0;
+  const int64_t n1 = side ? h->N2 : h->N;
+  int n_splits;
+  int64_t split_len;
+  tile_splits(n1, h->n_tgroups[cpl], per_split, &n_splits, &split_len);
+  const int max_splits = (int)((hdf::kScratchBytes - w_bytes - wd_bytes) / per_split);
+  if (n_splits > max_splits) {
+    split_len = ((n1 + max_splits - 1) / max_splits + 31) / 32 * 32;
+    n_splits = (int)((n1 + split_len - 1) / split_len);
+  }
+  double* W = (double*)base;
+  void* Wd = (char*)base + w_bytes;
+  double* part = (double*)((char*)base + w_bytes + wd_bytes);
+  HIPCHK(hdf::launch_matvec_t_tile(side ? h->phi2.p : h->phi.p, side ? h->ldN2 : h->ldN, side ? h->q2.p : h->q.p,
+                                   side ? h->ldN2 : h->ldN, tile_waves(h, cpl), tile_groups(h, cpl),
+                                   h->n_tgroups[cpl], n_splits, split_len, V, ldv, n1, (int)m, m16, h->r, part,
+                                   h->fprec, h->dtype, s));
+  HIPCHK(hdf::launch_matvec_reduce(part, n_splits, h->r, m16, (const double*)h->lam_row.p, W, Wd, h->fprec, s));
+  HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+                              (int)h->degs.size(), h->max_s, Wd, m16, KV, ldkv, h->N, (int)m, h->fprec, h->dtype, 0,
+                              1, nullptr, s));
+  return HDF_OK;
+}
+
 hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
                         double* dlength, void* dX, int64_t lddx, void* hip_stream) {
   g_err.clear();

@@ -167,4 +167,10 @@ hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, 
                           const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
                           int accumulate, int prec, hipStream_t s);
 
+// Scratch of hdf_matvec_noalloc: a fixed device array per GPU (scratch.hip).
+// scratch_address returns its device address on the current device (resolved
+// once per device); hipErrorInvalidDevice for device ordinals >= 64.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+hipError_t scratch_address(void** p);
+
 }  // namespace hdf

@@ -20,7 +20,8 @@ HDF_SPLIT_TOL = 1e-6
 STATUS = {0: "HDF_OK", -1: "HDF_E_ARG", -2: "HDF_E_DIM", -3: "HDF_E_NONFINITE",
           -4: "HDF_E_INFEASIBLE", -5: "HDF_E_OOM", -6: "HDF_E_HIP", -7: "HDF_E_DISABLED"}
 
-EXPORTS = ["hdf_build", "hdf_build_ex", "hdf_build_cross", "hdf_matvec", "hdf_backward", "hdf_info", "hdf_get_plan",
+EXPORTS = ["hdf_build", "hdf_build_ex", "hdf_build_cross", "hdf_matvec", "hdf_matvec_noalloc", "hdf_backward",
+           "hdf_info", "hdf_get_plan",
            "hdf_copy_factor", "hdf_copy_factor_y", "hdf_free", "hdf_status_string", "hdf_last_error",
            "hdf_plan_chebyshev", "hdf_plan_degree", "hdf_plan_cores", "hdf_plan_index_set",
            "hdf_plan_compress_cross", "hdf_kmeans", "hdf_kernel_matvec", "hdf_krr_create", "hdf_krr_apply",
@@ -95,6 +96,7 @@ def lib():
     L.hdf_copy_factor_y.argtypes = [vp, vp, i64, vp, i64, vp]
     L.hdf_plan_compress_cross.argtypes = [i32, vp, vp, vp, dbl, dbl, ctypes.POINTER(ctypes.c_int32), vp, vp, vp]
     L.hdf_matvec.argtypes = [vp, vp, i64, i64, vp, i64, vp]
+    L.hdf_matvec_noalloc.argtypes = [vp, vp, i64, i64, vp, i64, vp]
     L.hdf_backward.argtypes = [vp, vp, vp, i64, i64, ctypes.POINTER(dbl), vp, i64, vp]
     L.hdf_info.argtypes = [vp, ctypes.POINTER(HDFInfo)]
     L.hdf_get_plan.argtypes = [vp, vp, vp, vp, vp]
@@ -212,6 +214,20 @@ class Factor:
         _check(lib().hdf_matvec(self._h, V2.data_ptr(), m, V2.stride(0), out.data_ptr(),
                                 out.stride(0), _stream()))
         return out[:, 0] if squeeze else out
+
+    def matvec_noalloc(self, V, out):
+        """K~ V into a caller-supplied out (n x m, m <= 64) through hdf_matvec_noalloc: no device
+        allocation inside the library (its work buffers are a fixed per-GPU array)."""
+        V2 = _dev2d(V, self.dtype, "V")
+        if V2.shape[0] != self.n:
+            raise ValueError("V must have n rows")
+        m = V2.shape[1]
+        if out is None:
+            raise ValueError("out is required (nothing is allocated)")
+        out = _check_out(out, self.n, m, self.dtype, V2.device)
+        _check(lib().hdf_matvec_noalloc(self._h, V2.data_ptr(), m, V2.stride(0), out.data_ptr(), out.stride(0),
+                                        _stream()))
+        return out
 
     def backward(self, W, V, need_l=True, need_x=True):
         """(dF/dl, dF/dX) for F = sum_c w_c^T K~ v_c (structure frozen)."""

@@ -21,7 +21,8 @@ FLAGS = ["-std=c++17", "-g", "-O1", "-fPIC", "-fno-omit-frame-pointer", "-fsanit
          "-DHDF_ALLOC_CACHE=0",
          "-Wno-psabi", "-Wno-unused-value", "-I", os.path.join(HERE, "shim"), "-I", CSRC]
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "kernels.hpp", "capi.cpp", "planner.cpp", "planner.hpp",
-                                            "krr_kernels.hip", "krr_kernels.hpp", "krr.cpp", "status.hpp")] + \
+                                            "krr_kernels.hip", "krr_kernels.hpp", "krr.cpp", "status.hpp",
+                                            "scratch.hip")] + \
           [os.path.join(ROOT, "include", "hdf.h")] + \
           [os.path.join(HERE, f) for f in ("emu_hip.h", "emu_rt.cpp", "translate.py", "build.py")]
 
@@ -58,7 +59,9 @@ def build():
     open(kern, "w").write(translate(open(os.path.join(CSRC, "kernels.hip")).read()))
     kern2 = os.path.join(tmp, "krr_kernels_emu.cpp")
     open(kern2, "w").write(translate(open(os.path.join(CSRC, "krr_kernels.hip")).read(), "krr_kernels.hpp"))
-    units = [kern, kern2, os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"),
+    kern3 = os.path.join(tmp, "scratch_emu.cpp")
+    open(kern3, "w").write(translate(open(os.path.join(CSRC, "scratch.hip")).read()))
+    units = [kern, kern2, kern3, os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"),
              os.path.join(CSRC, "krr.cpp"), os.path.join(HERE, "emu_rt.cpp")]
 
     def compile_one(src):

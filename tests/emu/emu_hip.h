@@ -12,7 +12,8 @@
 #include <type_traits>
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1, hipErrorNotReady = 600 };
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101,
+       hipErrorNotReady = 600 };
 typedef struct emu_stream* hipStream_t;
 typedef struct emu_event* hipEvent_t;
 enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2 };
@@ -42,6 +43,7 @@ hipError_t hipMemGetInfo(size_t* f, size_t* t);
 hipError_t hipGetDevice(int* d);
 hipError_t hipGetLastError();
 const char* hipGetErrorString(hipError_t e);
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 void emu_flush();
 }
 
@@ -53,6 +55,16 @@ using std::isnan;
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) (&(x))
+namespace emu {
+// a file-scope device array: device memory of its own size (garbage-filled), visible to
+// hipGetSymbolAddress and to the kernels' pointer checks
+void register_symbol(void* p, size_t n);
+struct SymbolReg {
+  SymbolReg(void* p, size_t n) { register_symbol(p, n); }
+};
+}  // namespace emu
 
 struct dim3 {
   unsigned x, y, z;

@@ -395,6 +395,17 @@ void check_ptr(const char* kname, const char* what, int idx, const void* p) {
 
 }  // namespace emu
 
+namespace emu {
+// file-scope device arrays announce themselves during static initialisation, possibly before this
+// file's globals exist: they wait in a function-local list until hipGetSymbolAddress turns them into
+// device memory (garbage-filled, like an allocation)
+static std::vector<std::pair<void*, size_t>>& pending_symbols() {
+  static std::vector<std::pair<void*, size_t>> v;
+  return v;
+}
+void register_symbol(void* p, size_t n) { pending_symbols().push_back({p, n}); }
+}  // namespace emu
+
 struct emu_event { bool done = false; long long t = 0; };
 static long long g_tick = 0;
 
@@ -486,5 +497,20 @@ hipError_t hipGetLastError() { hipError_t e = emu::g_last; emu::g_last = hipSucc
 const char* hipGetErrorString(hipError_t e) { return e ? "emulated error" : "no error"; }
 void emu_flush() { emu::flush(); }
 void emu_register(void* p, size_t n) { emu::user_regions[(uintptr_t)p] = n; }
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  if (!emu::allocs.count((uintptr_t)symbol)) {
+    size_t n = 0;
+    for (auto& e : emu::pending_symbols())
+      if (e.first == symbol) n = e.second;
+    if (!n) {
+      fprintf(stderr, "EMU hipGetSymbolAddress of an unregistered symbol %p\n", symbol);
+      abort();
+    }
+    memset(const_cast<void*>(symbol), emu::g_garbage, n);
+    emu::allocs[(uintptr_t)symbol] = n;
+  }
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 long long emu_launches() { return emu::g_launches; }
 }

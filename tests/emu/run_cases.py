@@ -293,7 +293,28 @@ def case_krr():
               f"{inf['n_blocks']} blocks, ranks {inf['sum_rank']}")
 
 
-CASES = {"fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
+def case_noalloc():
+    """hdf_matvec_noalloc (work buffers in the scratch array) against hdf_matvec: two calls in a row,
+    the second smaller, binary64 and binary32 (and the binary64 factor of binary32 data)."""
+    runs = [(wl.uniform_cube(1_503, 4, 104), "gaussian", 0.7, 1e-5, 33, torch.float64),
+            (wl.unit_ball(611, 3, 101), "gaussian", 1.0, 1e-6, 5, torch.float64),
+            (wl.max_norm_one(wl.gaussian_mixture(2_049, 5, 103)).astype(np.float32), "cauchy", 1.0, 1e-4, 16,
+             torch.float32),
+            (wl.shell(801, 6, 105).astype(np.float32), "matern52", 8.0, 1e-7, 64, torch.float32)]
+    for X, kern, l, tol, m, dt in runs:
+        prec = hdf.HDF_FP64 if dt == torch.float64 else hdf.HDF_MIXED
+        f = hdf.Factor(to_dev(X, dt), kern, l, tol, precision=prec)
+        V = to_dev(wl.rhs(len(X), m, 3 + m).astype(_NP[dt]), dt)
+        ref = f.matvec(V).numpy()
+        out = dev_empty((len(X), m), dt)
+        st = hdf.lib().hdf_matvec_noalloc(f._h, V.data_ptr(), m, m, out.data_ptr(), m, None)
+        e = rel(out.numpy(), ref)
+        # pass 2 of hdf_matvec splits the harmonic rows of few points over chunks (summation order)
+        bound = 1e-5 if f.info()["factor_precision"] == hdf.HDF_MIXED else 1e-12
+        check(f"noalloc n={len(X)} m={m} {dt}", st == 0 and e <= bound, f"status {st}, {e:.2e}")
+
+
+CASES = {"noalloc": case_noalloc, "fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
          "krr": case_krr, "mfree": case_mfree}
 
 if __name__ == "__main__":

@@ -1,8 +1,9 @@
 """Translate a .hip source (kernels.hip, krr_kernels.hip) into C++ for the CPU emulation (emu_hip.h).
 
-Three mechanical rewrites, nothing else: triple-chevron launches become
+Four mechanical rewrites, nothing else: triple-chevron launches become
 emu::launch calls, __shared__ arrays become static arrays filled with garbage
-once per block, and the dynamic LDS array becomes the block's emulated LDS.
+once per block, the dynamic LDS array becomes the block's emulated LDS, and
+file-scope device arrays become host arrays registered as device memory.
 """
 import re
 import sys
@@ -22,6 +23,7 @@ template <> struct StructCheck<hdf::BuildTables> {
 
 def translate(src, header="kernels.hpp"):
     n0 = src.count("<<<")
+    hook = header == "kernels.hpp" and n0 > 0
     src, n = re.subn(r'(k_\w+(?:<[^<>;]*?>)?)<<<(.*?)>>>\(',
                      lambda m: f'emu::launch("{m.group(1)}", {m.group(2)}, {m.group(1)}, ', src)
     if n != n0:
@@ -39,10 +41,14 @@ def translate(src, header="kernels.hpp"):
             return f'static {typ} {x}; emu::garbage_once(&{x}, sizeof({x}));'
         raise ValueError(m.group(0))
     src = re.sub(r'__shared__ ([^;]*);', shared, src)
+    # file-scope device arrays: registered with the emulator as device memory of their size
+    src = re.sub(r'static __device__ (__align__\(\d+\) )?(\w[\w ]*?) (\w+)\[([^\]]+)\];',
+                 lambda m: (f'static {m.group(1) or ""}{m.group(2)} {m.group(3)}[{m.group(4)}]; '
+                            f'static emu::SymbolReg {m.group(3)}_emu_reg({m.group(3)}, sizeof({m.group(3)}));'), src)
     inc = f'#include "{header}"\n'
     if inc not in src:
         raise ValueError(f"{header} include not found")
-    if header == "kernels.hpp":
+    if hook:
         src = src.replace(inc, inc + _HOOK, 1)
     return '#define EMU_DEVICE_CODE\n' + src
 
