@@ -70,8 +70,8 @@ typedef enum {
                              exceed the memory budget (see hdf_build)        */
   HDF_E_OOM        = -5,  /* device allocation failed                        */
   HDF_E_HIP        = -6,  /* a HIP runtime call failed                       */
-  HDF_E_DISABLED   = -7   /* the requested operation is switched off in this
-                             library (see hdf_backward)                      */
+  HDF_E_DISABLED   = -7   /* reserved: an operation switched off at compile
+                             time (none is, in this version)                 */
 } hdf_status;
 
 #define HDF_MAX_DIM     8
@@ -241,12 +241,17 @@ hdf_status hdf_matvec_noalloc(hdf_handle h, const void* V, int64_t m, int64_t ld
  *   dlength  host, receives dF/dl (NULL: not computed).
  *   dX       device, n x d with leading dimension lddx (>= d), receives dF/dX
  *            (NULL: not computed); same dtype as the points.
- * One blocking synchronisation when dlength != NULL.
- * dF/dX is switched off unless the library is compiled with
- * -DHDF_ADJOINT_KERNEL=1: a request with dX != NULL returns HDF_E_DISABLED
- * before any device work.  The adjoint kernels are withdrawn until a device
- * memory fault seen in runs that called them is explained; dF/dl (pass 1 and
- * host arithmetic) is unaffected. */
+ * One blocking synchronisation (U^T V and U^T W come to the host), two the
+ * first time dF/dX is asked of a handle.  dF/dX needs a stored factor
+ * (HDF_STORE_FACTOR) whose kept degrees are 0..K; otherwise HDF_E_ARG before
+ * any device work.  It is formed from the stored factor: the stored harmonic
+ * rows are solid harmonics, homogeneous harmonic polynomials of the scaled
+ * point (Sec. 3.3 and Appendix A), and the gradient of one of degree k is a
+ * fixed linear combination of those of degree k - 1, so dF/dx_i is a product
+ * of stored rows with small coefficient matrices, plus a term in the radial
+ * derivative dq/d(rho^2), whose Chebyshev series is the derivative of the
+ * stored one.  Work space of n (2 m (d + 1)) elements of the factor's type is
+ * kept with the handle. */
 hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
                         double* dlength, void* dX, int64_t lddx, void* hip_stream);
 

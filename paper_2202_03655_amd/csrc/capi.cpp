@@ -226,11 +226,14 @@ struct hdf_factor {
   // matvec / adjoint workspace
   DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
   DevBuf cphi, cq;                                // matrix-free chunk scratch
-  // adjoint tables: row of U^T V per harmonic row in the recursion's visiting
-  // order, per-degree (s_k, first radial row), coefficient stream scratch
-  std::vector<int32_t> adj_src_host;
-  std::vector<hdf::KInfo> adj_kinfo_host;
-  DevBuf adj_src, adj_kinfo, adj_stream;
+  // adjoint (dF/dX by contractions): the loop-order row table, q' = dq/d(rho^2) rows and their
+  // coefficients, the shifted-factor degree table (harmonics of k - 1 with radial rows of k), the
+  // contraction coefficients and products; host copies outlive their asynchronous uploads
+  std::vector<int32_t> col_of_host;
+  DevBuf dq, dq_coef, adj_degs, adj_c2, adj_cs, adj_kv2, adj_kvs;
+  std::vector<hdf::DegDev> adj_degs_host;
+  int64_t r_shift = 0;
+  std::vector<char> adj_c2_host, adj_cs_host;
   hdf::BuildTables tables{};
   ~hdf_factor() {
     // the device buffers go back to the allocator cache once no enqueued work can use them
@@ -251,11 +254,6 @@ struct hdf_factor {
 
 void hdf::set_product_timing(hdf_factor* h, bool on) { h->time_products = on; }
 
-// dF/dX (k_adj_pack + k_adjoint) is compiled but not dispatched unless enabled.
-#ifndef HDF_ADJOINT_KERNEL
-#define HDF_ADJOINT_KERNEL 0
-#endif
-constexpr bool kAdjointKernel = HDF_ADJOINT_KERNEL != 0;
 
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
@@ -427,29 +425,12 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       HIPCHK(f->q2.ensure((size_t)f->S * f->ldN2 * f->felem()));
     }
     // The harmonic recurrences run up to the largest kept degree only:
-    // dropped top degrees would be evaluated and discarded by both the factor
-    // kernel and the adjoint.
+    // dropped top degrees would be evaluated and discarded.
     const int Kh = f->kept_k.back();
     // loop-order column table
     std::vector<int32_t> col_of;
     loop_order_columns(d, Kh, canon, col_of);
-    {
-      // adjoint visiting order: harmonic rows (k, h, l) as the recursion meets them
-      std::vector<int32_t> deg_of(f->H);
-      for (size_t di = 0; di < f->degs.size(); ++di)
-        for (int hh = 0; hh < f->degs[di].nh; ++hh) deg_of[f->degs[di].hoff + hh] = (int32_t)di;
-      f->adj_src_host.clear();
-      f->adj_src_host.reserve(f->r);
-      for (int32_t col : col_of) {
-        if (col < 0) continue;
-        const hdf::DegDev& dg = f->degs[deg_of[col]];
-        const int hh = col - dg.hoff;
-        for (int l = 0; l < dg.s; ++l) f->adj_src_host.push_back(dg.roff + hh * dg.s + l);
-      }
-      f->adj_kinfo_host.assign(Kh + 2, hdf::KInfo{0, 0});
-      for (size_t di = 0; di < f->degs.size(); ++di)
-        f->adj_kinfo_host[f->kept_k[di]] = hdf::KInfo{f->degs[di].s, f->degs[di].qoff};
-    }
+    f->col_of_host = col_of;                      // the adjoint's host-side harmonic evaluation
     // uploads from copies the handle keeps, so no synchronisation is needed before the
     // host vectors below go out of scope
     auto upload = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
@@ -1304,6 +1285,144 @@ hdf_status hdf_matvec_noalloc(hdf_handle h, const void* V, int64_t m, int64_t ld
   return HDF_OK;
 }
 
+// dF/dX by factor contractions (the formula above k_radial in kernels.hip): with Gv = C U^T V and
+// Gw = C U^T W (binary64, rank rows with stride gstride), the product of U' = phi q' with [Gv | Gw]
+// and of the shifted factor S_{k-1} q_k with [G^(j)T Gv | G^(j)T Gw] for every direction j, then the
+// pointwise combination.  Needs the kept degrees to be 0..K (every degree-(k-1) harmonic stored).
+static hdf_status adjoint_dx(hdf_handle h, const double* gv, const double* gw, int64_t gstride, int m,
+                             const void* Wm, const void* Vm, int64_t ld, void* dX, int64_t lddx, hipStream_t s) {
+  const int d = h->d, m2 = 2 * m, md2 = m2 * d;
+  const int Kh = h->kept_k.back();
+  const size_t fel = h->felem();
+  const int io = h->fprec == 1 ? 0 : 1;          // contraction outputs in the factor's type
+  // derivative maps of the harmonic basis: depend on d and the degrees only, kept per process
+  static std::mutex maps_mu;
+  static std::map<std::pair<int, int>, std::vector<std::vector<double>>> maps;
+  const std::vector<std::vector<double>>* G = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(maps_mu);
+    auto it = maps.find({d, Kh});
+    if (it == maps.end()) {
+      hdf::ChainCoeffs cc;
+      hdf::chain_coeffs(d, Kh, cc);
+      std::vector<int> rows_k(Kh + 1);
+      for (int k = 0; k <= Kh; ++k) rows_k[k] = h->degs[k].hoff;
+      std::vector<std::vector<double>> g;
+      hdf::harmonic_derivative_maps(d, Kh, cc, h->col_of_host.data(), (int)h->H, rows_k, g);
+      it = maps.emplace(std::make_pair(d, Kh), std::move(g)).first;
+    }
+    G = &it->second;
+  }
+  // shifted-factor degrees: harmonics of k - 1 with the radial rows and rank of degree k
+  if (h->adj_degs_host.empty() && Kh >= 1) {
+    int64_t roff = 0;
+    for (int k = 1; k <= Kh; ++k) {
+      const hdf::DegDev& dg = h->degs[k];
+      const hdf::DegDev& d1 = h->degs[k - 1];
+      hdf::DegDev e{};
+      e.hoff = d1.hoff; e.nh = d1.nh; e.qoff = dg.qoff; e.s = dg.s; e.roff = (int32_t)roff;
+      h->adj_degs_host.push_back(e);
+      roff += (int64_t)d1.nh * dg.s;
+    }
+    h->r_shift = roff;
+    HIPCHK(h->adj_degs.ensure(h->adj_degs_host.size() * sizeof(hdf::DegDev)));
+    HIPCHK(hipMemcpyAsync(h->adj_degs.p, h->adj_degs_host.data(), h->adj_degs_host.size() * sizeof(hdf::DegDev),
+                          hipMemcpyHostToDevice, s));
+  }
+  // q' = dq/d(rho^2): the derivative Chebyshev series of every radial function, scaled by dt/d(rho^2)
+  if (!h->dq.p) {
+    std::vector<double> dc;
+    for (size_t di = 0; di < h->kept_k.size(); ++di) {
+      const hdf::DegreeFactor& df = h->deg[h->kept_k[di]];
+      const int L = df.L;
+      for (int l = 0; l < df.s; ++l) {
+        const double* c = &df.E[(size_t)l * L];
+        std::vector<double> b(L + 2, 0.0);      // b_{a-1} = b_{a+1} + 2 a c_a, then b_0 / 2
+        for (int a = L - 1; a >= 1; --a) b[a - 1] = b[a + 1] + 2.0 * a * c[a];
+        b[0] *= 0.5;
+        dc.insert(dc.end(), b.begin(), b.begin() + L);
+      }
+    }
+    std::vector<char>& keep = h->adj_c2_host;   // reused below; the coefficients go first
+    keep.assign(dc.size() * fel, 0);
+    if (fel == 4)
+      for (size_t i = 0; i < dc.size(); ++i) ((float*)keep.data())[i] = (float)dc[i];
+    else
+      std::memcpy(keep.data(), dc.data(), dc.size() * 8);
+    HIPCHK(h->dq_coef.ensure(keep.size()));
+    HIPCHK(hipMemcpyAsync(h->dq_coef.p, keep.data(), keep.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h->dq.ensure((size_t)h->S * h->ldN * fel));
+    HIPCHK(hdf::launch_radial(h->x_soa.p, h->dtype, h->ldN, h->N, d, (const hdf::GeoDev*)h->geo_dev.p, h->u0,
+                              h->u1, h->tables.q_len, h->tables.q_off, h->dq_coef.p, (int)h->S, 2.0 / (h->u1 - h->u0),
+                              h->fprec, h->dq.p, h->ldN, s));
+    HIPCHK(clear_padding(h->dq.p, h->S, h->N, h->ldN, fel, s));
+    HIPCHK(hipStreamSynchronize(s));             // the coefficient copy above is read before keep is reused
+  }
+  // coefficients: C2 = [lambda gv | lambda gw] (rank x 2m), Cs = [G^(j)T C2]_j (shifted rank x 2m d)
+  const int c2s = (m2 + 15) / 16 * 16, css = (md2 + 15) / 16 * 16;
+  std::vector<double> C2((size_t)h->r * m2), Cs((size_t)std::max<int64_t>(h->r_shift, 1) * md2, 0.0);
+  for (size_t di = 0; di < h->degs.size(); ++di) {
+    const hdf::DegDev& dg = h->degs[di];
+    const hdf::DegreeFactor& df = h->deg[h->kept_k[di]];
+    for (int hh = 0; hh < dg.nh; ++hh)
+      for (int l = 0; l < dg.s; ++l) {
+        const int64_t row = dg.roff + (int64_t)hh * dg.s + l;
+        for (int c = 0; c < m; ++c) {
+          C2[row * m2 + c] = df.lam[l] * gv[row * gstride + c];
+          C2[row * m2 + m + c] = df.lam[l] * gw[row * gstride + c];
+        }
+      }
+  }
+  for (int k = 1; k <= Kh; ++k) {
+    const hdf::DegDev& dg = h->degs[k];
+    const hdf::DegDev& e = h->adj_degs_host[k - 1];
+    const int n0 = dg.nh, n1 = e.nh, sk = dg.s;
+    const std::vector<double>& gk = (*G)[k];
+    for (int j = 0; j < d; ++j)
+      for (int hp = 0; hp < n1; ++hp)
+        for (int l = 0; l < sk; ++l) {
+          double* out = &Cs[(e.roff + (int64_t)hp * sk + l) * md2 + (int64_t)j * m2];
+          for (int hh = 0; hh < n0; ++hh) {
+            const double gg = gk[((size_t)j * n0 + hh) * n1 + hp];
+            if (gg == 0.0) continue;
+            const double* in = &C2[(dg.roff + (int64_t)hh * sk + l) * m2];
+            for (int c = 0; c < m2; ++c) out[c] += gg * in[c];
+          }
+        }
+  }
+  auto pack = [&](const std::vector<double>& v, int64_t rows, int cols, int stride, std::vector<char>& dst) {
+    dst.assign((size_t)std::max<int64_t>(rows, 1) * stride * fel, 0);
+    for (int64_t r = 0; r < rows; ++r)
+      for (int c = 0; c < cols; ++c) {
+        const double x = v[r * cols + c];
+        if (fel == 4) ((float*)dst.data())[r * stride + c] = (float)x;
+        else ((double*)dst.data())[r * stride + c] = x;
+      }
+  };
+  pack(C2, h->r, m2, c2s, h->adj_c2_host);
+  pack(Cs, h->r_shift, md2, css, h->adj_cs_host);
+  HIPCHK(h->adj_c2.ensure(h->adj_c2_host.size()));
+  HIPCHK(h->adj_cs.ensure(h->adj_cs_host.size()));
+  HIPCHK(hipMemcpyAsync(h->adj_c2.p, h->adj_c2_host.data(), h->adj_c2_host.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->adj_cs.p, h->adj_cs_host.data(), h->adj_cs_host.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(h->adj_kv2.ensure((size_t)h->N * m2 * fel));
+  HIPCHK(h->adj_kvs.ensure((size_t)h->N * md2 * fel));
+  if (!h->ev_adj[0])
+    for (auto& e : h->ev_adj) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventRecord(h->ev_adj[0], s));
+  // U' [Gv | Gw] and the shifted factor times [G^(j)T Gv | G^(j)T Gw] (pass-2 kernel, one chunk)
+  HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->dq.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
+                              (int)h->degs.size(), h->max_s, h->adj_c2.p, c2s, h->adj_kv2.p, m2, h->N, m2, h->fprec,
+                              io, 0, 1, nullptr, s));
+  HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->adj_degs.p, Kh, h->max_s,
+                              h->adj_cs.p, css, h->adj_kvs.p, md2, h->N, md2, h->fprec, io, 0, 1, nullptr, s));
+  HIPCHK(hdf::launch_adj_combine(h->x_soa.p, h->dtype, h->ldN, h->N, d, (const hdf::GeoDev*)h->geo_dev.p,
+                                 h->adj_kvs.p, md2, h->adj_kv2.p, m2, Wm, Vm, ld, m, dX, lddx, h->fprec, s));
+  HIPCHK(hipEventRecord(h->ev_adj[1], s));
+  h->adj_timed = true;
+  return HDF_OK;
+}
+
 hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m, int64_t ld,
                         double* dlength, void* dX, int64_t lddx, void* hip_stream) {
   g_err.clear();
@@ -1313,14 +1432,16 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
   if (ld < m) return fail(HDF_E_ARG, "ld must be >= m");
   if (dX && lddx < h->d) return fail(HDF_E_ARG, "lddx must be >= d");
   if (h->cross) return fail(HDF_E_ARG, "hdf_backward needs a symmetric factor (hdf_build)");
-  if (dX && h->fprec != (h->dtype == 0 ? 1 : 0))
-    return fail(HDF_E_ARG, "dF/dX needs the factor in the points' type (a binary64 factor of binary32 points, "
-                           "used below tol 1e-6, has no adjoint kernel)");
-  if (dX && !kAdjointKernel)
-    return fail(HDF_E_DISABLED, "dF/dX is switched off (compile with -DHDF_ADJOINT_KERNEL=1): the adjoint "
-                                "kernels are withdrawn until a device memory fault seen with them is explained");
+  if (dX && h->storage != HDF_STORE_FACTOR)
+    return fail(HDF_E_ARG, "dF/dX needs a stored factor (HDF_STORE_FACTOR): it contracts the stored harmonics");
+  if (dX && h->r > 0)
+    for (size_t i = 0; i < h->kept_k.size(); ++i)
+      if (h->kept_k[i] != (int)i)
+        return fail(HDF_E_ARG, "dF/dX needs the kept degrees to be 0..K (a degree below the largest kept one "
+                               "was dropped, so its harmonics, the derivatives of the next degree's, are not stored)");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t el = h->ioel(), fel = h->felem();
+  (void)fel;
   if (!dlength && !dX) return HDF_OK;
   if (h->r == 0) {
     if (dlength) *dlength = 0.0;
@@ -1331,7 +1452,6 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
   // same for any m up to 16), two passes when 2m exceeds the column limit
   const bool joint = 2 * m <= HDF_MAX_RHS;
   int m16;
-  const void *Gv_d, *Gw_d;
   const DevBuf *gv_src, *gw_src;
   int64_t gw_col = 0;
   if (joint) {
@@ -1343,8 +1463,6 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
                             hipMemcpyDeviceToDevice, s));
     hdf_status st = pass1(h, 0, h->bw_VW.p, m2, m2, m16, h->bw_GV, h->bw_GVd, s, false);
     if (st != HDF_OK) return st;
-    Gv_d = h->bw_GVd.p;
-    Gw_d = (const char*)h->bw_GVd.p + m * fel;
     gv_src = gw_src = &h->bw_GV;
     gw_col = m;
   } else {
@@ -1353,48 +1471,8 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
     if (st != HDF_OK) return st;
     st = pass1(h, 0, Wm, m, ld, m16, h->bw_GW, h->bw_GWd, s, false);
     if (st != HDF_OK) return st;
-    Gv_d = h->bw_GVd.p;
-    Gw_d = h->bw_GWd.p;
     gv_src = &h->bw_GV;
     gw_src = &h->bw_GW;
-  }
-  if (dX) {
-    if (!h->adj_src.p) {
-      HIPCHK(h->adj_src.ensure(h->adj_src_host.size() * sizeof(int32_t)));
-      HIPCHK(h->adj_kinfo.ensure(h->adj_kinfo_host.size() * sizeof(hdf::KInfo)));
-      HIPCHK(hipMemcpyAsync(h->adj_src.p, h->adj_src_host.data(), h->adj_src_host.size() * sizeof(int32_t),
-                            hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(h->adj_kinfo.p, h->adj_kinfo_host.data(),
-                            h->adj_kinfo_host.size() * sizeof(hdf::KInfo), hipMemcpyHostToDevice, s));
-    }
-    HIPCHK(h->adj_stream.ensure(hdf::adjoint_stream_elems((int)h->r, (int)m) * fel));
-    // radial rows staged in LDS per launch: at most 64 KiB (values + derivatives)
-    const int max_rows = (int)(65536 / (2 * 64 * fel));
-    bool first = true;
-    if (!h->ev_adj[0])
-      for (auto& e : h->ev_adj) HIPCHK(hipEventCreate(&e));
-    HIPCHK(hipEventRecord(h->ev_adj[0], s));
-    size_t di = 0;
-    while (di < h->degs.size()) {
-      const int row0 = h->degs[di].qoff;
-      size_t dj = di;
-      while (dj < h->degs.size() && h->degs[dj].qoff + h->degs[dj].s - row0 <= max_rows) ++dj;
-      if (dj == di) return fail(HDF_E_INFEASIBLE, "radial rank of one degree exceeds the adjoint staging");
-      const int row1 = h->degs[dj - 1].qoff + h->degs[dj - 1].s;
-      const int cstep = hdf::adjoint_cols_per_launch((int)m);
-      for (int c0 = 0; c0 < m; c0 += cstep) {
-        const int mc = (int)std::min<int64_t>(cstep, m - c0);
-        HIPCHK(hdf::launch_adjoint(h->x_soa.p, h->dtype, h->ldN, h->N, h->d,
-                                   (const hdf::GeoDev*)h->geo_dev.p, h->u0, h->u1, h->tables, row0, row1,
-                                   (const hdf::KInfo*)h->adj_kinfo.p, Gv_d, Gw_d, m16, (int)m,
-                                   (const int32_t*)h->adj_src.p, (int)h->r, h->adj_stream.p, Wm, Vm, ld,
-                                   c0, mc, dX, lddx, first ? 0 : 1, h->fprec, s));
-        first = false;
-      }
-      di = dj;
-    }
-    HIPCHK(hipEventRecord(h->ev_adj[1], s));
-    h->adj_timed = true;
   }
   if (dlength) {
     // dF/dl = sum_{k,h,c} gw^T (E'_k^T dM_k/dl E'_k) gv, dM/dl from the Chebyshev
@@ -1428,14 +1506,17 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
           }
       }
     }
-    std::vector<double> gv((size_t)h->r * m16), gwbuf;
-    HIPCHK(hipMemcpyAsync(gv.data(), gv_src->p, gv.size() * 8, hipMemcpyDeviceToHost, s));
-    if (!joint) {
-      gwbuf.resize((size_t)h->r * m16);
-      HIPCHK(hipMemcpyAsync(gwbuf.data(), gw_src->p, gwbuf.size() * 8, hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    const double* gw = joint ? gv.data() + gw_col : gwbuf.data();
+  }
+  // U^T V and U^T W on the host (binary64), one synchronisation
+  std::vector<double> gv((size_t)h->r * m16), gwbuf;
+  HIPCHK(hipMemcpyAsync(gv.data(), gv_src->p, gv.size() * 8, hipMemcpyDeviceToHost, s));
+  if (!joint) {
+    gwbuf.resize((size_t)h->r * m16);
+    HIPCHK(hipMemcpyAsync(gwbuf.data(), gw_src->p, gwbuf.size() * 8, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  const double* gw = joint ? gv.data() + gw_col : gwbuf.data();
+  if (dlength) {
     double dl = 0.0;
     for (size_t dj = 0; dj < h->degs.size(); ++dj) {
       const hdf::DegDev& dg = h->degs[dj];
@@ -1452,6 +1533,10 @@ hdf_status hdf_backward(hdf_handle h, const void* Wm, const void* Vm, int64_t m,
           }
     }
     *dlength = dl;
+  }
+  if (dX) {
+    const hdf_status st = adjoint_dx(h, gv.data(), gw, m16, (int)m, Wm, Vm, ld, dX, lddx, s);
+    if (st != HDF_OK) return st;
   }
   return HDF_OK;
 }

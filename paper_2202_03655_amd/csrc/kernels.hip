@@ -887,359 +887,121 @@ hipError_t launch_build(const void* x_soa, int dtype, int64_t ldx, int64_t n, in
 }
 
 // ------------------------------------------------------------------ adjoint
-// dF/dx_i for F = sum_c w_c^T U C U^T v_c, C = diag(lambda) (structure
-// frozen).  With U[i,(k,h,l)] = S_h(xt_i) q_{k,l}(rho_i^2), xt = (x - c)/R:
+// dF/dx_i for F = sum_c w_c^T U C U^T v_c, C = diag(lambda) (structure frozen), with
+// U[i,(k,h,l)] = S_h(xt_i) q_{k,l}(rho_i^2), xt = (x - c)/R:
 //   dF/dx_i = (1/R) sum_{k,h} [ a_h(i) grad S_h(xt_i) + 2 xt_i b_h(i) S_h(xt_i) ],
 //   a_h = sum_l q_{k,l} alpha_{h,l},  b_h = sum_l q'_{k,l} alpha_{h,l},
-//   alpha_{h,l} = sum_c w_ic Gv[(k,h,l)][c] + v_ic Gw[(k,h,l)][c],
-// where Gv = C U^T V, Gw = C U^T W and q' = dq/d(rho^2).  The harmonics and
-// their gradients are recomputed in the loop order of the factor kernel,
-// forward mode: every chain level carries (P, dP/dx_j, dP/dr_j^2) through its
-// recurrence, the running prefix product carries its full gradient.
-//
-// Data access: the coefficients (Gv, Gw) are repacked beforehand into a
-// stream in the order the recursion visits the harmonics (k_adj_pack), so a
-// harmonic reads its s_k records at a running offset with no table lookup;
-// the per-degree record (s_k, first radial row) and the innermost level's
-// recurrence coefficients are fetched one iteration ahead.  The per-point
-// radial values and derivatives of the rows [row0, row1) are staged in LDS,
-// thread-major.  One wavefront per block.
-template <typename T, int D>
-struct AdjState {
-  T xt[D], r2[D];
-  T gacc[D];
-  T sacc;
-  int ptr;                                        // offset into the stream
-};
+//   alpha_{h,l}(i) = sum_c w_ic Gv[(k,h,l)][c] + v_ic Gw[(k,h,l)][c],  Gv = C U^T V, Gw = C U^T W.
+// Both terms are factor contractions: the second is the product of U' (q replaced by q' =
+// dq/d(rho^2)) with [Gv | Gw]; the first, since every partial derivative of a degree-k solid
+// harmonic is a combination of the degree k-1 ones (dS_{k,h}/dx_j = sum_h' G_k^(j)[h][h'] S_{k-1,h'}),
+// is the product of the shifted factor S_{k-1,h'} q_{k,l} with [G^(j)T Gv | G^(j)T Gw] for every j.
+// The contractions run through the pass-2 kernel; k_radial evaluates q', k_adj_combine adds up.
 
-template <typename T, int D, int MB>
-struct AdjCtx {
-  const typename Vec2<T>::type* chain;           // padded by one pair
-  const KInfo* kinfo;                             // per degree (s_k, qoff_k), padded by one
-  const T* stream;                                // padded by 4 records
-  int K, row0, row1, nrows;
-  const T* qs;                                    // LDS: [2][nrows][64]
-  int lane;
-  T wv[MB], vv[MB];
-};
-
-// Coefficients of one harmonic of degree k (record (s_k, first radial row)
-// ki): a = sum_l q_{k,l} alpha_l and bq = sum_l q'_{k,l} alpha_l over its s_k
-// stream records; advances the stream offset.  NS = s_k when known.
-template <typename T, int D, int MB, int NS>
-__device__ __forceinline__ void adj_coef_fixed(const AdjCtx<T, D, MB>& cx, const T* rec, int qr, T& a, T& bq) {
-  T cv[NS][2 * MB], q0[NS], q1[NS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j) {
-#pragma unroll
-    for (int e = 0; e < 2 * MB; ++e) cv[j][e] = rec[j * 2 * MB + e];
-    q0[j] = cx.qs[(qr + j) * 64 + cx.lane];
-    q1[j] = cx.qs[(cx.nrows + qr + j) * 64 + cx.lane];
-  }
-#pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    T alpha = 0;
-#pragma unroll
-    for (int c = 0; c < MB; ++c) alpha += cx.wv[c] * cv[j][2 * c] + cx.vv[c] * cv[j][2 * c + 1];
-    a += q0[j] * alpha;
-    bq += q1[j] * alpha;
-  }
-}
-
-template <typename T, int D, int MB>
-__device__ __forceinline__ void adj_coef(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, KInfo ki, T& a,
-                                         T& bq) {
-  a = 0;
-  bq = 0;
-  const int s = ki.s;
-  if (s == 0) return;                             // dropped degree (uniform)
-  if (ki.qoff >= cx.row0 && ki.qoff + s <= cx.row1) {
-    const T* rec = cx.stream + st.ptr;
-    const int qr = ki.qoff - cx.row0;
-    switch (s) {                                  // uniform
-      case 1: adj_coef_fixed<T, D, MB, 1>(cx, rec, qr, a, bq); break;
-      case 2: adj_coef_fixed<T, D, MB, 2>(cx, rec, qr, a, bq); break;
-      case 3: adj_coef_fixed<T, D, MB, 3>(cx, rec, qr, a, bq); break;
-      default: {
-        int l0 = 0;
-        for (; l0 + 4 <= s; l0 += 4) adj_coef_fixed<T, D, MB, 4>(cx, rec + l0 * 2 * MB, qr + l0, a, bq);
-        for (; l0 < s; ++l0) adj_coef_fixed<T, D, MB, 1>(cx, rec + l0 * 2 * MB, qr + l0, a, bq);
-      }
-    }
-  }
-  st.ptr += s * 2 * MB;
-}
-
-// Levels >= 2 of the polar chain: forward mode, the prefix and its gradient
-// passed down.
-template <typename T, int D, int MB, int LEVEL>
-struct AdjChain {
-  typedef typename Vec2<T>::type T2;
-  static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int b,
-                                             T pre, const T* gpre) {
-    const int cj = LEVEL - 1;                     // coordinate index of this level
-    const T x = st.xt[cj], rr = st.r2[cj];
-    const T2* cf = cx.chain + ((int64_t)(LEVEL - 1) * (cx.K + 1) + b) * (cx.K + 1);
-    T pm1 = 0, pxm1 = 0, prm1 = 0;                // P_{n-1} and its partials
-    T p = cf[0].x, px = 0, pr = 0;                // P_n
-    for (int nn = 0; nn <= cx.K - b; ++nn) {
-      if (nn == 1) {
-        pm1 = p; pxm1 = px; prm1 = pr;
-        p = cf[1].x * x; px = cf[1].x; pr = 0;
-      } else if (nn >= 2) {
-        const T A = cf[nn].x, B = cf[nn].y;
-        const T pn = A * x * p - B * rr * pm1;
-        const T pxn = A * (p + x * px) - B * rr * pxm1;
-        const T prn = A * x * pr - B * (pm1 + rr * prm1);
-        pm1 = p; pxm1 = px; prm1 = pr;
-        p = pn; px = pxn; pr = prn;
-      }
-      T g[D];
-      const T ppr = pre * pr;
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        T gq = gpre[q] * p;
-        if (q == cj) gq += pre * px + 2 * st.xt[q] * ppr;
-        else if (q > cj) gq += 2 * st.xt[q] * ppr;
-        g[q] = gq;
-      }
-      AdjChain<T, D, MB, LEVEL - 1>::run(st, cx, b + nn, pre * p, g);
-    }
-  }
-};
-
-// Innermost level (coordinate 0, one harmonic per step, degree k = b + nn):
-// reverse mode.  With S = pre P, grad S = gpre P + pre (e_0 dP/dx + 2 xt dP/dr),
-// the harmonic's share a grad S + 2 xt bq S sums over the loop to
-//   gpre X1 + pre (e_0 X2 + 2 xt X3)  and  2 xt pre X4,
-// X1 = sum a P, X2 = sum a dP/dx, X3 = sum a dP/dr, X4 = sum bq P, so the
-// D-vector update happens once per loop.  The recurrence pair and the degree
-// record of the next step are fetched one step ahead (both tables padded).
-template <typename T, int D, int MB>
-struct AdjChain<T, D, MB, 1> {
-  typedef typename Vec2<T>::type T2;
-  static __device__ __forceinline__ void run(AdjState<T, D>& st, const AdjCtx<T, D, MB>& cx, int b,
-                                             T pre, const T* gpre) {
-    const T x = st.xt[0], rr = st.r2[0];
-    const T2* cf = cx.chain + (int64_t)b * (cx.K + 1);
-    T X1 = 0, X2 = 0, X3 = 0, X4 = 0, a, bq;
-    // step 0: P = c0
-    T p = cf[0].x, px = 0, pr = 0;
-    KInfo k_nxt = cx.kinfo[b + 1];
-    adj_coef<T, D, MB>(st, cx, cx.kinfo[b], a, bq);
-    X1 += a * p;
-    X4 += bq * p;
-    if (b < cx.K) {
-      // step 1: P = c1 x
-      T2 c_nxt = cf[2];                           // index K + 1 - b at most: next row or pad
-      const KInfo ki = k_nxt;
-      k_nxt = cx.kinfo[b + 2];
-      T pm1 = p, pxm1 = 0, prm1 = 0;
-      p = cf[1].x * x; px = cf[1].x; pr = 0;
-      adj_coef<T, D, MB>(st, cx, ki, a, bq);
-      X1 += a * p; X2 += a * px; X4 += bq * p;
-      for (int nn = 2; nn <= cx.K - b; ++nn) {
-        const T2 c = c_nxt;
-        const KInfo kc = k_nxt;
-        c_nxt = cf[nn + 1];
-        k_nxt = cx.kinfo[b + nn + 1];
-        const T Ax = c.x * x, Brr = c.y * rr;
-        const T pn = Ax * p - Brr * pm1;
-        const T pxn = c.x * p + Ax * px - Brr * pxm1;
-        const T prn = Ax * pr - c.y * pm1 - Brr * prm1;
-        pm1 = p; pxm1 = px; prm1 = pr;
-        p = pn; px = pxn; pr = prn;
-        adj_coef<T, D, MB>(st, cx, kc, a, bq);
-        X1 += a * p; X2 += a * px; X3 += a * pr; X4 += bq * p;
-      }
-    }
-    const T pX3 = 2 * pre * X3;
-#pragma unroll
-    for (int q = 0; q < D; ++q) st.gacc[q] += gpre[q] * X1 + st.xt[q] * pX3;
-    st.gacc[0] += pre * X2;
-    st.sacc += pre * X4;
-  }
-};
-
-template <typename Tin, typename T, int D, int MB>
-__global__ void __launch_bounds__(64) k_adjoint(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n,
+// out[row][i] = scale * sum_{a < len} coef[a] T_a(t_i) for the S rows of a coefficient table (the
+// radial-function tables with derivative coefficients give q' = dq/d(rho^2)); PPT points per thread.
+template <typename Tin, typename T, int PPT>
+__global__ void __launch_bounds__(256) k_radial(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n, int d,
                                                  const GeoDev* __restrict__ geo, double u0, double u1,
-                                                 const typename Vec2<T>::type* __restrict__ chain,
-                                                 const int32_t* __restrict__ q_len,
-                                                 const int32_t* __restrict__ q_off,
-                                                 const T* __restrict__ q_coef, int K, int row0, int row1,
-                                                 const KInfo* __restrict__ kinfo,
-                                                 const T* __restrict__ stream,
-                                                 const T* __restrict__ Wm, const T* __restrict__ Vm,
-                                                 int64_t ld, int c0, int mcols,
-                                                 T* __restrict__ dX, int64_t lddx, int accumulate) {
-  extern __shared__ unsigned char smem_raw[];
-  T* qs = reinterpret_cast<T*>(smem_raw);
-  const int lane = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-  const bool valid = i < n;
-  const int64_t ii = valid ? i : 0;
-  AdjState<T, D> st;
-  double rho2 = 0.0;
-  const double Reff = geo->Reff;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    const double v = ((double)x_soa[(int64_t)j * ldx + ii] - geo->c[j]) / Reff;
-    st.xt[j] = (T)v;
-    rho2 += v * v;
-  }
-  T acc = 0;
-#pragma unroll
-  for (int j = D - 1; j >= 0; --j) {
-    acc += st.xt[j] * st.xt[j];
-    st.r2[j] = acc;
-  }
-#pragma unroll
-  for (int q = 0; q < D; ++q) st.gacc[q] = 0;
-  st.sacc = 0;
-  st.ptr = 0;
-  // radial values and d/d(rho^2) for the rows of this launch (Clenshaw)
-  const T tt = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
-  const T dt_drho2 = (T)(2.0 / (u1 - u0));
-  const int nrows = row1 - row0;
-  for (int r = 0; r < nrows; ++r) {
-    const int L = q_len[row0 + r];
-    const T* cf = q_coef + q_off[row0 + r];
-    T b1 = 0, b2 = 0, d1 = 0, d2 = 0;
-    for (int a = L - 1; a >= 1; --a) {
-      const T b0 = 2 * tt * b1 - b2 + cf[a];
-      const T d0 = 2 * b1 + 2 * tt * d1 - d2;
-      b2 = b1; b1 = b0;
-      d2 = d1; d1 = d0;
-    }
-    qs[r * 64 + lane] = tt * b1 - b2 + cf[0];
-    qs[(nrows + r) * 64 + lane] = (b1 + tt * d1 - d2) * dt_drho2;
-  }
-  AdjCtx<T, D, MB> cx;
-  cx.chain = chain; cx.kinfo = kinfo; cx.stream = stream;
-  cx.K = K; cx.row0 = row0; cx.row1 = row1; cx.nrows = nrows; cx.qs = qs; cx.lane = lane;
-#pragma unroll
-  for (int c = 0; c < MB; ++c) {
-    cx.wv[c] = (valid && c < mcols) ? Wm[ii * ld + c0 + c] : (T)0;
-    cx.vv[c] = (valid && c < mcols) ? Vm[ii * ld + c0 + c] : (T)0;
-  }
-  // azimuthal part outermost, exactly as the factor kernel
-  const T ax = st.xt[D - 2], ay = st.xt[D - 1];
-  T cr = 1, ci = 0, pcr = 0, pci = 0;             // z^mm and z^(mm-1)
-  const T inv_sqrt_2pi = (T)0.39894228040143267794, inv_sqrt_pi = (T)0.56418958354775628695;
-  for (int mm = 0; mm <= K; ++mm) {
-    if (mm > 0) {
-      pcr = cr; pci = ci;
-      const T ncr = ax * cr - ay * ci;
-      ci = ay * cr + ax * ci;
-      cr = ncr;
-    }
-    const T cm = (mm == 0) ? inv_sqrt_2pi : inv_sqrt_pi;
-    T g[D];
-#pragma unroll
-    for (int q = 0; q < D; ++q) g[q] = 0;
-    // Re z^m: d/dx = m Re z^{m-1}, d/dy = -m Im z^{m-1}
-    g[D - 2] = cm * (T)mm * pcr;
-    g[D - 1] = -cm * (T)mm * pci;
-    AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * cr, g);
-    if (mm > 0) {
-      // Im z^m: d/dx = m Im z^{m-1}, d/dy = m Re z^{m-1}
-      g[D - 2] = cm * (T)mm * pci;
-      g[D - 1] = cm * (T)mm * pcr;
-      AdjChain<T, D, MB, D - 2>::run(st, cx, mm, cm * ci, g);
-    }
-  }
-  if (valid) {
-    const T invR = (T)(1.0 / Reff);
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const T v = (st.gacc[q] + 2 * st.xt[q] * st.sacc) * invR;
-      T* o = dX + ii * lddx + q;
-      *o = accumulate ? *o + v : v;
-    }
-  }
-}
-
-// Coefficient stream of the adjoint: record j (a harmonic row (k,h,l) in the
-// visiting order, source row src_row[j] of Gv and Gw) holds, for c < MB,
-// (Gv[src][c0 + c], Gw[src][c0 + c]); columns c >= mcols and the 4 pad
-// records after the last are zero.
-template <typename T, int MB>
-__global__ void k_adj_pack(const T* __restrict__ Gv, const T* __restrict__ Gw, int m16,
-                           const int32_t* __restrict__ src_row, int nrec, int c0, int mcols,
-                           T* __restrict__ stream) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (nrec + 4) * MB) return;
-  const int j = e / MB, c = e - j * MB;
-  T gv = 0, gw = 0;
-  if (j < nrec && c < mcols) {
-    const int64_t row = (int64_t)src_row[j] * m16;
-    gv = Gv[row + c0 + c];
-    gw = Gw[row + c0 + c];
-  }
-  stream[(int64_t)j * 2 * MB + 2 * c] = gv;
-  stream[(int64_t)j * 2 * MB + 2 * c + 1] = gw;
-}
-
-int adjoint_cols_per_launch(int m) { return m <= 1 ? 1 : 4; }
-
-size_t adjoint_stream_elems(int nrec, int m) {
-  return (size_t)(nrec + 4) * 2 * adjoint_cols_per_launch(m);
-}
-
-template <typename Tin, typename T, int MB>
-static hipError_t launch_adjoint_t(const void* x_soa, int64_t ldx, int64_t n, int d, const GeoDev* geo,
-                                   double u0, double u1, const BuildTables& tb, int row0, int row1,
-                                   const KInfo* kinfo, const void* Gv, const void* Gw, int m16,
-                                   const int32_t* src_row, int nrec, void* stream, const void* Wm,
-                                   const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
-                                   int accumulate, hipStream_t s) {
+                                                 const int32_t* __restrict__ q_len, const int32_t* __restrict__ q_off,
+                                                 const T* __restrict__ coef, int S, T scale, T* __restrict__ out,
+                                                 int64_t ld_out) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * PPT;
+  if (i0 >= n) return;      // whole thread past the end (rows are padded past n)
+  T tt[PPT];
   {
-    const int tot = (nrec + 4) * MB;
-    k_adj_pack<T, MB><<<(tot + 255) / 256, 256, 0, s>>>((const T*)Gv, (const T*)Gw, m16, src_row, nrec, c0,
-                                                         mcols, (T*)stream);
+#pragma clang fp contract(off)
+    const double Reff = geo->Reff;
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int64_t i = (i0 + e < n) ? i0 + e : n - 1;
+      double rho2 = 0.0;
+      for (int j = 0; j < d; ++j) {
+        const double v = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+        rho2 = rho2 + v * v;
+      }
+      tt[e] = (T)((2.0 * rho2 - u0 - u1) / (u1 - u0));
+    }
   }
-  const dim3 grid((unsigned)((n + 63) / 64));
-  const size_t lds = (size_t)2 * (row1 - row0) * 64 * sizeof(T);
-  typedef typename Vec2<T>::type T2;
-#define ADJ_CASE(DD)                                                                                \
-  case DD:                                                                                          \
-    k_adjoint<Tin, T, DD, MB><<<grid, 64, lds, s>>>(                                                \
-        (const Tin*)x_soa, ldx, n, geo, u0, u1, (const T2*)tb.chain, tb.q_len, tb.q_off,            \
-        (const T*)tb.q_coef, tb.K, row0, row1, kinfo, (const T*)stream, (const T*)Wm, (const T*)Vm, \
-        ld, c0, mcols, (T*)dX, lddx, accumulate);                                                    \
-    break;
-  switch (d) {
-    ADJ_CASE(3)
-    ADJ_CASE(4)
-    ADJ_CASE(5)
-    ADJ_CASE(6)
-    ADJ_CASE(7)
-    ADJ_CASE(8)
-    default: return hipErrorInvalidValue;
+  for (int row = 0; row < S; ++row) {
+    const int L = q_len[row];
+    const T* cf = coef + q_off[row];
+    T b1[PPT], b2[PPT], val[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) { b1[e] = 0; b2[e] = 0; }
+    for (int a = L - 1; a >= 1; --a) {
+      const T c = cf[a];
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const T b0 = 2 * tt[e] * b1[e] - b2[e] + c;
+        b2[e] = b1[e];
+        b1[e] = b0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) val[e] = scale * (tt[e] * b1[e] - b2[e] + cf[0]);
+    store_row<T, PPT>(out + (int64_t)row * ld_out + i0, val);
   }
-#undef ADJ_CASE
+}
+
+hipError_t launch_radial(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                         double u0, double u1, const int32_t* q_len, const int32_t* q_off, const void* coef,
+                         int S, double scale, int prec, void* out, int64_t ld_out, hipStream_t s) {
+  if (S <= 0 || n <= 0) return hipSuccess;
+#define HDF_RAD(TIN, T)                                                                                      \
+  do {                                                                                                       \
+    constexpr int PPT = 16 / sizeof(T);                                                                      \
+    const unsigned nb = (unsigned)((n + 256 * PPT - 1) / (256 * PPT));                                      \
+    k_radial<TIN, T, PPT><<<nb, 256, 0, s>>>((const TIN*)x_soa, ldx, n, d, geo, u0, u1, q_len, q_off,       \
+                                             (const T*)coef, S, (T)scale, (T*)out, ld_out);                  \
+  } while (0)
+  if (prec == 1 && dtype == 0) HDF_RAD(float, float);
+  else if (prec == 0 && dtype == 1) HDF_RAD(double, double);
+  else if (prec == 0 && dtype == 0) HDF_RAD(float, double);
+  else return hipErrorInvalidValue;
+#undef HDF_RAD
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
-                          const GeoDev* geo, double u0, double u1, const BuildTables& tb,
-                          int row0, int row1, const KInfo* kinfo, const void* Gv, const void* Gw,
-                          int m16, int m, const int32_t* src_row, int nrec, void* stream, const void* Wm,
-                          const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
-                          int accumulate, int prec, hipStream_t s) {
-#define ADJ_ARGS x_soa, ldx, n, d, geo, u0, u1, tb, row0, row1, kinfo, Gv, Gw, m16, src_row, nrec, stream, \
-                 Wm, Vm, ld, c0, mcols, dX, lddx, accumulate, s
-  if (prec == 1 && dtype == 0) {
-    if (adjoint_cols_per_launch(m) == 1) return launch_adjoint_t<float, float, 1>(ADJ_ARGS);
-    return launch_adjoint_t<float, float, 4>(ADJ_ARGS);
+// dX[i][j] = (1/R) [ sum_c w_ic KS[i][j 2m + c] + v_ic KS[i][j 2m + m + c]
+//                    + 2 xt_ij (sum_c w_ic K2[i][c] + v_ic K2[i][m + c]) ]
+// KS: n x ldks (the shifted-factor products, 2m columns per direction), K2: n x ldk2.
+template <typename Tin, typename T, typename TIO>
+__global__ void __launch_bounds__(256) k_adj_combine(const Tin* __restrict__ x_soa, int64_t ldx, int64_t n, int d,
+                                                      const GeoDev* __restrict__ geo, const T* __restrict__ KS,
+                                                      int64_t ldks, const T* __restrict__ K2, int64_t ldk2,
+                                                      const TIO* __restrict__ Wm, const TIO* __restrict__ Vm,
+                                                      int64_t ld, int m, TIO* __restrict__ dX, int64_t lddx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double Reff = geo->Reff;
+  double s2 = 0.0;
+  for (int c = 0; c < m; ++c)
+    s2 += (double)Wm[i * ld + c] * (double)K2[i * ldk2 + c] + (double)Vm[i * ld + c] * (double)K2[i * ldk2 + m + c];
+  for (int j = 0; j < d; ++j) {
+    double sj = 0.0;
+    const T* ks = KS + i * ldks + (int64_t)j * 2 * m;
+    for (int c = 0; c < m; ++c) sj += (double)Wm[i * ld + c] * (double)ks[c] + (double)Vm[i * ld + c] * (double)ks[m + c];
+    const double xt = ((double)x_soa[(int64_t)j * ldx + i] - geo->c[j]) / Reff;
+    dX[i * lddx + j] = (TIO)((sj + 2.0 * xt * s2) / Reff);
   }
-  if (prec == 0 && dtype == 1) {
-    if (adjoint_cols_per_launch(m) == 1) return launch_adjoint_t<double, double, 1>(ADJ_ARGS);
-    return launch_adjoint_t<double, double, 4>(ADJ_ARGS);
-  }
-#undef ADJ_ARGS
-  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_combine(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                              const void* KS, int64_t ldks, const void* K2, int64_t ldk2, const void* Wm,
+                              const void* Vm, int64_t ld, int m, void* dX, int64_t lddx, int prec, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+#define HDF_COMB(TIN, T)                                                                                     \
+  k_adj_combine<TIN, T, TIN><<<nb, 256, 0, s>>>((const TIN*)x_soa, ldx, n, d, geo, (const T*)KS, ldks,      \
+                                                (const T*)K2, ldk2, (const TIN*)Wm, (const TIN*)Vm, ld, m,   \
+                                                (TIN*)dX, lddx)
+  if (prec == 1 && dtype == 0) HDF_COMB(float, float);
+  else if (prec == 0 && dtype == 1) HDF_COMB(double, double);
+  else if (prec == 0 && dtype == 0) HDF_COMB(float, double);
+  else return hipErrorInvalidValue;
+#undef HDF_COMB
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ matvec

@@ -144,28 +144,19 @@ hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64
                            void* KV, int64_t ldkv, int64_t n, int m, int prec, int io, int hchunk, int nz,
                            void* part, hipStream_t s);
 
-// Adjoint: dX[i] (+)= dF/dx_i for F = sum_c w_c^T U C U^T v_c, restricted to
-// the radial rows [row0, row1) (degrees whose rows lie inside) and the
-// right-hand-side columns [c0, c0 + mcols), mcols <= adjoint_cols_per_launch(m).
-// Gv = C U^T V and Gw = C U^T W (rank x m, row stride m16, storage type).
-// src_row[j], j < nrec = rank, is the row of Gv/Gw of the j-th harmonic row
-// (k, h, l) in the visiting order of the recursion; kinfo[k] = (s_k, first
-// radial row of degree k) for k <= K + 1 (s = 0 for dropped degrees and the
-// pad entry).  `stream` is scratch of adjoint_stream_elems(nrec, m) elements.
-// The chain table of `tb` must carry one pad pair.  accumulate != 0 adds
-// into dX.
-struct KInfo {
-  int32_t s;      // s_k (0: degree dropped)
-  int32_t qoff;   // first radial row of the degree
-};
-int adjoint_cols_per_launch(int m);
-size_t adjoint_stream_elems(int nrec, int m);
-hipError_t launch_adjoint(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d,
-                          const GeoDev* geo, double u0, double u1, const BuildTables& tb,
-                          int row0, int row1, const KInfo* kinfo, const void* Gv, const void* Gw,
-                          int m16, int m, const int32_t* src_row, int nrec, void* stream, const void* Wm,
-                          const void* Vm, int64_t ld, int c0, int mcols, void* dX, int64_t lddx,
-                          int accumulate, int prec, hipStream_t s);
+// Adjoint by contractions (see hdf_backward).  launch_radial evaluates S
+// Chebyshev series of t(rho^2) at every point: out[row][i] = scale * sum_a
+// coef[q_off[row] + a] T_a(t_i), a < q_len[row] (rows padded: the launch
+// writes up to the next multiple of 2 or 4 points past n).  launch_adj_combine
+// forms dX[i][j] = (1/R) [sum_c w_ic KS[i][2mj + c] + v_ic KS[i][2mj + m + c]
+// + 2 xt_ij (sum_c w_ic K2[i][c] + v_ic K2[i][m + c])].  prec: factor type
+// (1 binary32, 0 binary64); dtype: points, W, V and dX (0 float32, 1 float64).
+hipError_t launch_radial(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                         double u0, double u1, const int32_t* q_len, const int32_t* q_off, const void* coef,
+                         int S, double scale, int prec, void* out, int64_t ld_out, hipStream_t s);
+hipError_t launch_adj_combine(const void* x_soa, int dtype, int64_t ldx, int64_t n, int d, const GeoDev* geo,
+                              const void* KS, int64_t ldks, const void* K2, int64_t ldk2, const void* Wm,
+                              const void* Vm, int64_t ld, int m, void* dX, int64_t lddx, int prec, hipStream_t s);
 
 // Scratch of hdf_matvec_noalloc: a fixed device array per GPU (scratch.hip).
 // scratch_address returns its device address on the current device (resolved

@@ -393,6 +393,179 @@ void chain_coeffs(int d, int K, ChainCoeffs& out) {
   }
 }
 
+// ------------------------------------------------------------ harmonic gradients
+namespace {
+struct HGState {
+  int d, K;
+  const ChainCoeffs* cc;
+  const int32_t* col_of;
+  const double* xt;
+  double r2[8];
+  int t;
+  double* val;
+  double* grad;
+};
+
+// Chain level `level` (coordinate level - 1) from index b, prefix pre with gradient gpre.
+void hg_chain(HGState& st, int level, int b, double pre, const double* gpre) {
+  const int d = st.d, cj = level - 1;
+  const double x = st.xt[cj], rr = st.r2[cj];
+  double pm1 = 0, pxm1 = 0, prm1 = 0;
+  double p = st.cc->A[st.cc->idx(level, b, 0)], px = 0, pr = 0;
+  for (int nn = 0; nn <= st.K - b; ++nn) {
+    if (nn == 1) {
+      pm1 = p; pxm1 = px; prm1 = pr;
+      const double c1 = st.cc->A[st.cc->idx(level, b, 1)];
+      p = c1 * x; px = c1; pr = 0;
+    } else if (nn >= 2) {
+      const double A = st.cc->A[st.cc->idx(level, b, nn)], B = st.cc->B[st.cc->idx(level, b, nn)];
+      const double pn = A * x * p - B * rr * pm1;
+      const double pxn = A * (p + x * px) - B * rr * pxm1;
+      const double prn = A * x * pr - B * (pm1 + rr * prm1);
+      pm1 = p; pxm1 = px; prm1 = pr;
+      p = pn; px = pxn; pr = prn;
+    }
+    // d/dx_q of P(x_cj, r_cj^2): dP/dx on its own coordinate, 2 x_q dP/dr^2 on every q >= cj
+    double g[8];
+    for (int q = 0; q < d; ++q) {
+      double dp = 0;
+      if (q == cj) dp += px;
+      if (q >= cj) dp += 2 * st.xt[q] * pr;
+      g[q] = gpre[q] * p + pre * dp;
+    }
+    if (level == 1) {
+      const int col = st.col_of[st.t++];
+      if (col >= 0) {
+        st.val[col] = pre * p;
+        for (int q = 0; q < d; ++q) st.grad[(size_t)col * d + q] = g[q];
+      }
+    } else {
+      hg_chain(st, level - 1, b + nn, pre * p, g);
+    }
+  }
+}
+}  // namespace
+
+void harmonics_and_gradients(int d, int K, const ChainCoeffs& cc, const int32_t* col_of, const double* x,
+                             double* val, double* grad) {
+  HGState st{};
+  st.d = d; st.K = K; st.cc = &cc; st.col_of = col_of; st.xt = x; st.t = 0; st.val = val; st.grad = grad;
+  double acc = 0;
+  for (int j = d - 1; j >= 0; --j) {
+    acc += x[j] * x[j];
+    st.r2[j] = acc;
+  }
+  // azimuthal part (x_{d-2} + i x_{d-1})^m outermost, cosine branch first
+  const double ax = x[d - 2], ay = x[d - 1];
+  double cr = 1, ci = 0, pcr = 0, pci = 0;
+  const double inv_sqrt_2pi = 0.39894228040143267794, inv_sqrt_pi = 0.56418958354775628695;
+  for (int mm = 0; mm <= K; ++mm) {
+    if (mm > 0) {
+      pcr = cr; pci = ci;
+      const double ncr = ax * cr - ay * ci;
+      ci = ay * cr + ax * ci;
+      cr = ncr;
+    }
+    const double cm = mm == 0 ? inv_sqrt_2pi : inv_sqrt_pi;
+    double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    g[d - 2] = cm * mm * pcr;                  // d Re z^m / dx = m Re z^(m-1), d / dy = -m Im z^(m-1)
+    g[d - 1] = -cm * mm * pci;
+    hg_chain(st, d - 2, mm, cm * cr, g);
+    if (mm > 0) {
+      g[d - 2] = cm * mm * pci;                // d Im z^m / dx = m Im z^(m-1), d / dy = m Re z^(m-1)
+      g[d - 1] = cm * mm * pcr;
+      hg_chain(st, d - 2, mm, cm * ci, g);
+    }
+  }
+}
+
+namespace {
+uint64_t splitmix_next(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Cholesky factor and solve of a symmetric positive definite n x n system with nrhs columns (long double)
+void spd_solve(int n, std::vector<long double>& A, int nrhs, std::vector<long double>& B) {
+  for (int j = 0; j < n; ++j) {
+    long double s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    const long double djj = sqrtl(s);
+    A[(size_t)j * n + j] = djj;
+    for (int i = j + 1; i < n; ++i) {
+      long double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = t / djj;
+    }
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    for (int i = 0; i < n; ++i) {             // L y = b
+      long double t = B[(size_t)i * nrhs + c];
+      for (int k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * B[(size_t)k * nrhs + c];
+      B[(size_t)i * nrhs + c] = t / A[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {        // L^T x = y
+      long double t = B[(size_t)i * nrhs + c];
+      for (int k = i + 1; k < n; ++k) t -= A[(size_t)k * n + i] * B[(size_t)k * nrhs + c];
+      B[(size_t)i * nrhs + c] = t / A[(size_t)i * n + i];
+    }
+  }
+}
+}  // namespace
+
+void harmonic_derivative_maps(int d, int K, const ChainCoeffs& cc, const int32_t* col_of, int H,
+                              const std::vector<int>& rows_k, std::vector<std::vector<double>>& G) {
+  G.assign(K + 1, std::vector<double>());
+  int nmax = 1;
+  for (int k = 0; k <= K; ++k)
+    if (rows_k[k] >= 0) nmax = std::max(nmax, (int)index_count(d, k));
+  const int M = 2 * nmax + 32;
+  // the harmonics and gradients of every row at M points of the unit sphere
+  std::vector<double> val((size_t)M * H), grad((size_t)M * H * d);
+  uint64_t seed = 0x48444603ull;
+  const double two_pi = 6.283185307179586476925;
+  for (int p = 0; p < M; ++p) {
+    double x[8], nrm = 0;
+    for (int j = 0; j < d; ++j) {            // Box-Muller normals from 53-bit uniforms in (0, 1)
+      const double u1 = ((splitmix_next(seed) >> 11) + 0.5) * 0x1.0p-53;
+      const double u2 = ((splitmix_next(seed) >> 11) + 0.5) * 0x1.0p-53;
+      x[j] = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2);
+      nrm += x[j] * x[j];
+    }
+    nrm = std::sqrt(nrm);
+    for (int j = 0; j < d; ++j) x[j] /= nrm;
+    harmonics_and_gradients(d, K, cc, col_of, x, &val[(size_t)p * H], &grad[(size_t)p * H * d]);
+  }
+  for (int k = 1; k <= K; ++k) {
+    if (rows_k[k] < 0 || rows_k[k - 1] < 0) continue;
+    const int n0 = (int)index_count(d, k), n1 = (int)index_count(d, k - 1);
+    const int r0 = rows_k[k], r1 = rows_k[k - 1];
+    // normal equations (A^T A) X = A^T B_j with A = S_{k-1} (M x n1), B_j = dS_k/dx_j (M x n0)
+    std::vector<double> Nd((size_t)n1 * n1, 0.0), Rd((size_t)n1 * n0 * d, 0.0), gj((size_t)n0 * d);
+    for (int p = 0; p < M; ++p) {
+      const double* v = &val[(size_t)p * H];
+      const double* gr = &grad[(size_t)p * H * d];
+      for (int j = 0; j < d; ++j)
+        for (int h = 0; h < n0; ++h) gj[(size_t)j * n0 + h] = gr[(size_t)(r0 + h) * d + j];
+      for (int a = 0; a < n1; ++a) {
+        const double va = v[r1 + a];
+        double* nrow = &Nd[(size_t)a * n1];
+        for (int b = 0; b < n1; ++b) nrow[b] += va * v[r1 + b];
+        double* rrow = &Rd[(size_t)a * n0 * d];
+        for (size_t c = 0; c < gj.size(); ++c) rrow[c] += va * gj[c];
+      }
+    }
+    std::vector<long double> N(Nd.begin(), Nd.end()), R(Rd.begin(), Rd.end());
+    spd_solve(n1, N, n0 * d, R);
+    std::vector<double>& g = G[k];
+    g.assign((size_t)d * n0 * n1, 0.0);
+    for (int j = 0; j < d; ++j)
+      for (int h = 0; h < n0; ++h)
+        for (int a = 0; a < n1; ++a) g[((size_t)j * n0 + h) * n1 + a] = (double)R[(size_t)a * n0 * d + (size_t)j * n0 + h];
+  }
+}
+
 // ------------------------------------------------------------ eigen
 void jacobi_eigh(int n, double* A, double* w, double* V) {
   for (int i = 0; i < n; ++i)

@@ -133,4 +133,26 @@ struct ChainCoeffs {
 };
 void chain_coeffs(int d, int K, ChainCoeffs& out);
 
+// Solid harmonics S_h(x) of every degree <= K and their gradients at one point x
+// (d coordinates), by the same nested chain recurrences as the device factor
+// kernel, in its loop order, forward mode (each level carries P, dP/dx and
+// dP/d(r^2)).  Harmonic t of the loop order goes to row col_of[t] (skipped when
+// negative): val[row], grad[row * d + j] = dS/dx_j.
+void harmonics_and_gradients(int d, int K, const ChainCoeffs& cc, const int32_t* col_of, const double* x,
+                             double* val, double* grad);
+
+// Derivative maps of the solid harmonics: the derivative of a harmonic of
+// degree k is a harmonic polynomial of degree k - 1, so
+//   dS_{k,h}/dx_j = sum_h' G_k^(j)[h][h'] S_{k-1,h'}
+// for the orthonormal bases of degrees k and k - 1.  rows_k[k] is the first
+// row of degree k among the H rows of `col_of` (-1 if the degree is absent).
+// For every k >= 1 with both degrees present, G[k] holds d blocks of
+// |H_k| x |H_{k-1}| (j-major), fitted by least squares on points of the unit
+// sphere drawn with SplitMix64 (twice as many points as the largest |H_k|, plus
+// 32; normal equations in binary64, solved in extended precision); the fit is
+// exact up to rounding because the identity holds at every x.  The maps depend
+// on d and the degrees only, not on the data.
+void harmonic_derivative_maps(int d, int K, const ChainCoeffs& cc, const int32_t* col_of, int H,
+                              const std::vector<int>& rows_k, std::vector<std::vector<double>>& G);
+
 }  // namespace hdf

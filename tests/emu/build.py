@@ -1,9 +1,8 @@
 """Build the CPU-emulated library (libhdf_emu.so) under ASan/UBSan.
 
 The product sources (capi.cpp, planner.cpp, krr.cpp, and kernels.hip and
-krr_kernels.hip through translate.py) are compiled unchanged for the host, with the dF/dX kernels
-dispatched (-DHDF_ADJOINT_KERNEL=1) and the device-allocation cache off
-(-DHDF_ALLOC_CACHE=0: exact-size allocations keep ASan's redzones tight).  The build lands in tests/emu/_build/<hash>
+krr_kernels.hip through translate.py) are compiled unchanged for the host, with the device-allocation
+cache off (-DHDF_ALLOC_CACHE=0: exact-size allocations keep ASan's redzones tight).  The build lands in tests/emu/_build/<hash>
 and is reused while sources and flags are unchanged.
 """
 import concurrent.futures
@@ -17,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2202_03655_amd", "csrc")
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 FLAGS = ["-std=c++17", "-g", "-O1", "-fPIC", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
-         "-fno-sanitize-recover=undefined", "-ftrivial-auto-var-init=pattern", "-DHDF_ADJOINT_KERNEL=1",
+         "-fno-sanitize-recover=undefined", "-ftrivial-auto-var-init=pattern",
          "-DHDF_ALLOC_CACHE=0",
          "-Wno-psabi", "-Wno-unused-value", "-I", os.path.join(HERE, "shim"), "-I", CSRC]
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "kernels.hpp", "capi.cpp", "planner.cpp", "planner.hpp",

@@ -8,14 +8,6 @@ from oracle import harmonics, hdf as ohdf
 
 AMBIG = 1e-9
 
-# hdf_backward stays off the GPU: runs that called it (build + backward) ended
-# with a device memory fault whose cause is not yet shown.  Every kernel on
-# that path passes a CPU emulation under ASan/UBSan with guard pages, NaN-filled
-# memory, permuted thread orders and pattern-initialised locals
-# (tests/emu), so the fault is unexplained; the dF/dX kernels are switched off
-# in the library (HDF_E_DISABLED) and these tests are skipped until it is.
-BACKWARD_OFF = ("hdf_backward is kept off the GPU: runs calling it ended with an unexplained device "
-                "memory fault (dF/dX kernels switched off, HDF_E_DISABLED)")
 
 
 def to_dev(X, dtype):

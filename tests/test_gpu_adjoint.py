@@ -11,9 +11,9 @@ import torch
 
 from oracle import dense, hdf as ohdf
 from paper_2202_03655_amd import workloads as wl
-from tests.gpu_common import BACKWARD_OFF, gpu_build, oracle_for, rel_fro, to_dev
+from tests.gpu_common import gpu_build, oracle_for, rel_fro, to_dev
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason=BACKWARD_OFF)]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -45,6 +45,29 @@ def test_adjoint_fp64_matches_oracle(case):
     print(f"{name}: dl {dl:.6e} vs oracle {gl_o:.6e}")
     assert abs(dl - gl_o) <= 1e-10 * max(abs(gl_o), 1e-300)
     assert rel_fro(dX.cpu().numpy(), gx_o) <= 1e-10
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_mixed_within_tol_of_oracle(case):
+    """HDF_MIXED: binary32 points, W, V and dX; the factor is binary32 above
+    tol 1e-6 and binary64 at or below it.  dF/dl and dF/dX against the oracle
+    on the same binary32 values, within tol (relative; Frobenius for dF/dX)."""
+    name, gen, kernel, l, tol, m = case
+    X = gen().astype(np.float32)
+    st, _ = oracle_for(X, kernel, l, tol, mixed=True)
+    f, _ = gpu_build(X, kernel, l, tol, mixed=True)
+    assert f.info()["rank"] == st["r"]
+    W = wl.rhs(len(X), m, 21).astype(np.float32)
+    V = wl.rhs(len(X), m, 22).astype(np.float32)
+    dl, dX = f.backward(to_dev(W, torch.float32), to_dev(V, torch.float32))
+    W64, V64 = W.astype(np.float64), V.astype(np.float64)
+    gl_o = ohdf.grad_l(st, W64, V64)
+    gx_o = ohdf.grad_x(st, W64, V64)
+    e_l = abs(dl - gl_o) / abs(gl_o)
+    e_x = rel_fro(dX.double().cpu().numpy(), gx_o)
+    print(f"{name}: mixed (factor {'binary32' if tol > 1e-6 else 'binary64'}) dl rel {e_l:.2e}, "
+          f"dX rel {e_x:.2e} (tol {tol:g})")
+    assert e_l <= tol and e_x <= tol
 
 
 def test_adjoint_vs_dense_gradient():

@@ -17,8 +17,8 @@ import torch
 
 from oracle import hdf as ohdf
 from paper_2202_03655_amd import workloads as wl
-from tests.gpu_common import (BACKWARD_OFF, ambiguous_ranks, degree_blocks, gpu_build, oracle_for, rel_fro,
-                               to_dev, torch_contraction)
+from tests.gpu_common import (ambiguous_ranks, degree_blocks, gpu_build, oracle_for, rel_fro, to_dev,
+                               torch_contraction)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -156,7 +156,6 @@ def test_fullsize_plan_rows_and_matvec(case):
             assert np.max(np.abs(ph - Sh[k])) <= 1e-12 * max(1.0, np.max(np.abs(Sh[k])))
 
 
-@pytest.mark.skip(reason=BACKWARD_OFF)
 def test_fullsize_backward_cube4():
     """N=2e5, d=4, Gaussian l=0.7, tol 1e-5: sampled rows of K~v and of
     dF/dX against the oracle, dF/dl against the oracle's frozen-structure

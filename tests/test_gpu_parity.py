@@ -202,8 +202,10 @@ def test_error_paths():
         f.matvec(torch.zeros((63, 1), dtype=torch.float64, device="cuda"))
     with pytest.raises(hdf.HDFError):
         f.matvec(torch.zeros((64, 300), dtype=torch.float64, device="cuda"))
-    # dF/dX is switched off: refused before any device work
+    # dF/dX of a matrix-free factor (it contracts the stored harmonics) is refused before any device work
     Z = torch.zeros((64, 1), dtype=torch.float64, device="cuda")
+    fm = hdf.Factor(to_dev(np.random.default_rng(1).normal(size=(64, 3)), torch.float64), "gaussian", 1.0, 1e-3,
+                    storage="none")
     with pytest.raises(hdf.HDFError) as e:
-        f.backward(Z, Z, need_l=False, need_x=True)
-    assert e.value.status == -7
+        fm.backward(Z, Z, need_l=False, need_x=True)
+    assert e.value.status == -1
