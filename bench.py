@@ -237,9 +237,11 @@ def run_mfma_line(wname, m, reps=5):
             "flop_per_byte": round(intensity, 1), "ridge_flop_per_byte": round(peak * 1e12 / 8e12, 1),
             "matvec_ms": round(wall, 3),
             "pass1": {"ms": round(p1, 4), "tflops": round(flops / (p1 * 1e-3) / 1e12, 1), "peak": peak,
-                      "frac": round(flops / (p1 * 1e-3) / 1e12 / peak, 4)},
+                      "frac": round(flops / (p1 * 1e-3) / 1e12 / peak, 4),
+                      "pipe_busy_pmc": read_mfma_busy("k_mv_t", f"{wname}:m{m}")},
             "pass2": {"ms": round(p2, 4), "tflops": round(flops / (p2 * 1e-3) / 1e12, 1), "peak": peak,
-                      "frac": round(flops / (p2 * 1e-3) / 1e12 / peak, 4)}}
+                      "frac": round(flops / (p2 * 1e-3) / 1e12 / peak, 4),
+                      "pipe_busy_pmc": read_mfma_busy("k_mv_n", f"{wname}:m{m}")}}
 
 
 def hdf_cfg(wname):
@@ -416,13 +418,15 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 comparison path")
     ap.add_argument("--no-sampled", action="store_true", help="skip the run with the sampled degree/rank rule")
     ap.add_argument("--with-backward", action="store_true",
-                    help="add hdf_backward (dF/dl only; dF/dX is switched off in the library) to the step")
+                    help="add hdf_backward (dF/dl and dF/dX, one right-hand side) to the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--no-krr", action="store_true", help="skip the KRR consumer (Sec. 4.2)")
     ap.add_argument("--no-matrix-free", action="store_true", help="skip the matrix-free factor run")
     ap.add_argument("--no-mfma-lines", action="store_true", help="skip the 64-RHS (MFMA-bound) product lines")
+    ap.add_argument("--mfma-line", default="", metavar="WORKLOAD",
+                    help="run only the 64-RHS product of WORKLOAD and print its JSON object (for profiling)")
     ap.add_argument("--krr-only", action="store_true",
                     help="run only the KRR consumer and print its JSON object (for profiling)")
     ap.add_argument("--cross", type=int, default=0, metavar="NQ",
@@ -440,6 +444,9 @@ def main():
         return
     from paper_2202_03655_amd import hdf, workloads
     hdf.lib()
+    if args.mfma_line:
+        print(json.dumps({"mfma_line": run_mfma_line(args.mfma_line, 64)}), flush=True)
+        return
     if args.krr_only:
         kr = run_krr(max(1, args.steps))
         kr.pop("_state")
