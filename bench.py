@@ -62,7 +62,8 @@ def read_traffic(kernel, workload):
     return None
 
 
-def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule="bound", storage="factor"):
+def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule="bound", storage="factor",
+            fused=True):
     import torch
     from paper_2202_03655_amd import hdf
     cfg = hdf_cfg(wname)
@@ -76,7 +77,7 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule=
     def step():
         t0 = time.perf_counter()
         f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule,
-                       storage=storage)
+                       storage=storage, fused=fused)
         t1 = time.perf_counter()
         f.matvec(Vd, out=out)
         t2 = time.perf_counter()
@@ -115,13 +116,14 @@ def run_gpu(wname, X, V, Wm, precision, steps, warmup, with_backward, rank_rule=
     for _ in range(reps):
         t0 = time.perf_counter()
         f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule,
-                       storage=storage)
+                       storage=storage, fused=fused)
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t0)
         del f
     build_done_s = sorted(tb)[len(tb) // 2]
     # separate matvec timing on a resident factor (wall clock of the call)
-    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule, storage=storage)
+    f = hdf.Factor(Xd, cfg["kernel"], cfg["l"], cfg["tol"], precision=prec, rank_rule=rank_rule, storage=storage,
+                   fused=fused)
     for _ in range(2):
         f.matvec(Vd, out=out)
     torch.cuda.synchronize()
@@ -535,16 +537,28 @@ def main():
                                "tau": si["tau"], "tau_bound": si["tau_bound"],
                                "est_error": si["est_error"]}
     if not args.no_matrix_free:
-        # the same step with nothing stored per point: the factor is re-evaluated chunk by chunk in each pass
-        rm = run_gpu(args.workload, X, V, Wm, args.precision, args.steps, args.warmup, False, "bound", "none")
-        mi = rm["info"]
-        out["matrix_free"] = {"ms_per_step": round(rm["ms_per_step"], 3),
-                              "value": round(N / (rm["ms_per_step"] * 1e-3) / 1e6, 3),
-                              "build_ms": round(rm["build_ms"], 3), "matvec_ms": round(rm["matvec_ms"], 3),
-                              "pass1_with_eval_ms": round(rm["k_mv_t_ms"], 4),
-                              "pass2_with_eval_ms": round(rm["k_mv_n_ms"], 4),
-                              "chunk_points": mi["chunk_points"], "scratch_bytes": mi["factor_bytes"],
-                              "stored_factor_bytes": info["factor_bytes"], "rank": mi["rank"]}
+        # the same step with nothing stored per point: the factor is re-evaluated in each pass, by the
+        # fused kernels (16 points at a time in LDS) and, for comparison, chunk by chunk into a scratch
+        out["matrix_free"] = {}
+        for fused in (True, False):
+            rm = run_gpu(args.workload, X, V, Wm, args.precision, args.steps, args.warmup, False, "bound", "none",
+                         fused=fused)
+            mi = rm["info"]
+            fl = 2.0 * N * mi["rank"] * m
+            ob = {"ms_per_step": round(rm["ms_per_step"], 3),
+                  "value": round(N / (rm["ms_per_step"] * 1e-3) / 1e6, 3),
+                  "build_ms": round(rm["build_ms"], 3), "matvec_ms": round(rm["matvec_ms"], 3),
+                  "pass1_with_eval_ms": round(rm["k_mv_t_ms"], 4),
+                  "pass2_with_eval_ms": round(rm["k_mv_n_ms"], 4),
+                  "pass1_mfma_tflops": round(fl / (rm["k_mv_t_ms"] * 1e-3) / 1e12, 1),
+                  "pass2_mfma_tflops": round(fl / (rm["k_mv_n_ms"] * 1e-3) / 1e12, 1),
+                  "fused": mi["mf_fused"], "chunk_points": None if mi["mf_fused"] else mi["chunk_points"],
+                  "scratch_bytes": mi["factor_bytes"], "stored_factor_bytes": info["factor_bytes"],
+                  "stored_matvec_ms": round(res["matvec_ms"], 3), "rank": mi["rank"]}
+            out["matrix_free"]["fused" if fused else "chunked"] = ob
+            print(f"# matrix-free ({'fused' if fused else 'chunked'}): step {ob['ms_per_step']} ms, product "
+                  f"{ob['matvec_ms']} ms (stored {ob['stored_matvec_ms']} ms), pass 1 {ob['pass1_with_eval_ms']} ms, "
+                  f"pass 2 {ob['pass2_with_eval_ms']} ms", file=sys.stderr, flush=True)
     # MFMA: the passes' algorithmic flops (2 N r m each) against the FP32 MFMA peak, live; the MFMA pipe
     # busy fraction from the committed PMC summary (None once the kernels changed)
     fl = 2.0 * N * r * m

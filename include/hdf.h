@@ -123,6 +123,9 @@ typedef struct {
                                 contractions: HDF_MIXED = binary32,
                                 HDF_FP64 = binary64 (HDF_MIXED builds with
                                 tol <= HDF_SPLIT_TOL report HDF_FP64)        */
+  int32_t  mf_fused;         /* HDF_STORE_NONE: 1 if the products run the
+                                fused kernels (factor_bytes is then 0: no
+                                scratch per point); 0 otherwise             */
 } hdf_info_t;
 
 /* Build the factor (Algorithm 1, symmetric case, Remark 1).
@@ -159,10 +162,12 @@ typedef enum {
   HDF_STORE_FACTOR = 0,  /* harmonics and radial functions of all N points
                             stored once at build, (H + S) x N values        */
   HDF_STORE_NONE   = 1   /* matrix-free: nothing per point is stored; every
-                            product re-evaluates them chunk by chunk into a
-                            scratch of (H + S) x chunk values, once per pass
-                            (Sec. 3.6 cost O(N r) per product, plus the
-                            harmonic evaluation O(N H d) twice)            */
+                            pass re-evaluates the harmonics and radial
+                            functions (Sec. 3.6 cost O(N r) per product,
+                            plus the evaluation O(N H) twice): 16 points at
+                            a time inside the contraction kernels (fused),
+                            or chunk by chunk into a scratch of (H + S) x
+                            chunk values (see hdf_build_options.chunked)   */
 } hdf_storage;
 
 /* Options of hdf_build_ex; zero-initialised fields take the defaults. */
@@ -172,7 +177,11 @@ typedef struct {
   double  margin;        /* share of tol the sampled error may use, (0, 1]
                             (default 0.8)                                    */
   int32_t storage;       /* hdf_storage (default HDF_STORE_FACTOR)          */
-  int32_t pad;
+  int32_t chunked;       /* HDF_STORE_NONE: 0 (default) uses the fused
+                            evaluate-and-contract kernels when the harmonics
+                            of 16 points fit in one workgroup's LDS, else
+                            the chunk scratch; 1 always uses the chunk
+                            scratch                                          */
   int64_t chunk;         /* HDF_STORE_NONE: points per chunk, >= 64
                             (default 262144)                                 */
 } hdf_build_options;
@@ -185,9 +194,9 @@ typedef struct {
  * ||K||^2).  The estimate is not a bound: the result meets tol up to the
  * sampling error that the margin absorbs.  No additional synchronisation.
  * Under HDF_STORE_NONE the build stops before the factor evaluation and
- * factor_bytes (hdf_info) is the size of the chunk scratch; hdf_matvec and
- * hdf_backward (dF/dl) re-evaluate the factor per chunk, hdf_copy_factor
- * returns HDF_E_ARG.  The memory budget of hdf_build applies to the
+ * factor_bytes (hdf_info) is the size of the chunk scratch (0 when the
+ * fused kernels serve it); hdf_matvec and hdf_backward (dF/dl) re-evaluate
+ * the factor in every pass, hdf_copy_factor returns HDF_E_ARG.  The memory budget of hdf_build applies to the
  * scratch. */
 hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t ld,
                         hdf_kernel kernel, double lengthscale, double tol, hdf_precision prec,

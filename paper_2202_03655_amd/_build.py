@@ -30,7 +30,7 @@ def build(verbose=False):
         o = os.path.join(objdir, src + ".o")
         _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", *COMMON, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
-    for src in ("kernels.hip", "krr_kernels.hip", "scratch.hip"):
+    for src in ("kernels.hip", "krr_kernels.hip", "mf_kernels.hip", "scratch.hip"):
         o = os.path.join(objdir, src + ".o")
         out = _run([HIPCC, *DEVICE_FLAGS, *COMMON, "-c", os.path.join(CSRC, src), "-o", o])
         if verbose and out:

@@ -182,9 +182,17 @@ struct hdf_factor {
   double u0 = 0, u1 = 1, nu = 0, tail = 0, tau = 0;
   int p = 0, K = 0;
   int rank_rule = HDF_RULE_BOUND, p_bound = -1;
-  // HDF_STORE_NONE: the factor is re-evaluated per chunk of points into cphi / cq
+  // HDF_STORE_NONE: the factor is re-evaluated in every pass, either by the fused kernels (16
+  // points at a time in LDS, mf_fused) or per chunk of points into cphi / cq
   int storage = HDF_STORE_FACTOR;
   int64_t chunk = 0, ldC = 0;
+  int mf_chunked = 0;                             // option: never use the fused kernels
+  bool mf_fused = false;
+  DevBuf mf_tabs;                                 // jobs | job_off | slots1 | slot_off1 | slots2 | slot_off2
+  size_t mf_o_joff = 0, mf_o_s1 = 0, mf_o_so1 = 0, mf_o_s2 = 0, mf_o_so2 = 0;
+  int mf_g1 = 1, mf_g2 = 1, mf_nb1 = 0, mf_nb2 = 0, n_cu = 0;
+  int64_t mf_nloop = 0;
+  hdf::MfLayout mf_lay1{}, mf_lay2{};
   double tau0 = 0, est_error = -1.0;             // budget threshold, sampled estimate
   std::vector<double> a;                          // p+1 coefficients
   std::vector<std::vector<double>> cores;
@@ -358,6 +366,112 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
   }
 }
 
+// Tables of the fused matrix-free passes, packed into one upload (see MfJob, MfSlot1, MfSlot2):
+// evaluation jobs per wavefront (subtrees of one shape, four per job, spread over the wavefronts
+// by longest-first assignment of their leaf counts), then the pass-1 accumulator tiles and the
+// pass-2 steps, each cut into groups of at most kMfWaves x kMfSlots wavefront shares.
+static bool mf_tables(hdf_factor* f, std::vector<char>& out) {
+  const int d = f->d, K = f->kept_k.back();
+  auto binom = [](int64_t nn, int64_t kk) {
+    double v = 1.0;
+    for (int64_t i = 1; i <= kk; ++i) v = v * (double)(nn - kk + i) / (double)i;
+    return (int64_t)std::llround(v);
+  };
+  const int TL = d == 3 ? 1 : d - 3;              // levels run by a subtree
+  struct Task { int ms, ntop, t0, rem; };
+  std::map<int, std::vector<Task>> by_rem;
+  int64_t t = 0;
+  for (int mm = 0; mm <= K; ++mm)
+    for (int sg = 0; sg < (mm > 0 ? 2 : 1); ++sg) {
+      const int ms = sg ? -mm : mm;
+      const int top = d == 3 ? 0 : K - mm;
+      for (int ntop = 0; ntop <= top; ++ntop) {
+        const int b = mm + ntop;
+        by_rem[K - b].push_back(Task{ms, d == 3 ? 0 : ntop, (int)t, K - b});
+        t += binom(K - b + TL, TL);
+      }
+    }
+  if (t != f->mf_nloop) return false;
+  struct JobCost { hdf::MfJob j; double cost; };
+  std::vector<JobCost> jl;
+  for (auto& kv : by_rem) {
+    const std::vector<Task>& v = kv.second;
+    for (size_t i = 0; i < v.size(); i += 4) {
+      hdf::MfJob j{};
+      j.rem = kv.first;
+      j.ntask = (int)std::min<size_t>(4, v.size() - i);
+      int setup = 0;
+      for (int e = 0; e < 4; ++e) {
+        const Task& tk = v[i + (e < j.ntask ? e : 0)];
+        j.mm[e] = tk.ms; j.ntop[e] = tk.ntop; j.t0[e] = tk.t0;
+        setup = std::max(setup, std::abs(tk.ms) + tk.ntop);
+      }
+      jl.push_back(JobCost{j, (double)binom(kv.first + TL, TL) + 0.5 * setup + 4.0});
+    }
+  }
+  std::stable_sort(jl.begin(), jl.end(), [](const JobCost& a, const JobCost& b) { return a.cost > b.cost; });
+  std::vector<std::vector<hdf::MfJob>> per(hdf::kMfWaves);
+  std::vector<double> load(hdf::kMfWaves, 0.0);
+  for (const JobCost& jc : jl) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    per[w].push_back(jc.j);
+    load[w] += jc.cost;
+  }
+  std::vector<hdf::MfJob> jobs;
+  std::vector<int32_t> joff;
+  for (int w = 0; w < hdf::kMfWaves; ++w) {
+    joff.push_back((int32_t)jobs.size());
+    jobs.insert(jobs.end(), per[w].begin(), per[w].end());
+  }
+  joff.push_back((int32_t)jobs.size());
+  // contraction slots
+  std::vector<hdf::MfSlot1> s1;
+  std::vector<hdf::MfSlot2> s2;
+  for (const hdf::DegDev& dg : f->degs) {
+    for (int h0 = 0; h0 < dg.nh; h0 += 16)
+      for (int l = 0; l < dg.s; ++l) {
+        hdf::MfSlot1 x{};
+        x.row0 = dg.hoff + h0; x.qrow = dg.qoff + l; x.out0 = dg.roff + h0 * dg.s + l; x.s = dg.s;
+        x.nr = std::min(16, dg.nh - h0);
+        s1.push_back(x);
+      }
+    for (int h0 = 0; h0 < dg.nh; h0 += 4)
+      for (int l = 0; l < dg.s; ++l) {
+        hdf::MfSlot2 x{};
+        x.row0 = dg.hoff + h0; x.qrow = dg.qoff + l; x.rank0 = dg.roff + h0 * dg.s + l; x.s = dg.s;
+        x.nv = std::min(4, dg.nh - h0);
+        s2.push_back(x);
+      }
+  }
+  auto groups = [](int64_t total, int per_wave, std::vector<int32_t>& off) {
+    const int64_t cap = (int64_t)hdf::kMfWaves * per_wave;
+    const int g = (int)std::max<int64_t>(1, (total + cap - 1) / cap);
+    off.clear();
+    for (int gi = 0; gi < g; ++gi) {
+      const int64_t lo = total * gi / g, hi = total * (gi + 1) / g;
+      for (int w = 0; w <= hdf::kMfWaves; ++w) off.push_back((int32_t)(lo + (hi - lo) * w / hdf::kMfWaves));
+    }
+    return g;
+  };
+  std::vector<int32_t> so1, so2;
+  f->mf_g1 = groups((int64_t)s1.size(), hdf::kMfSlots1, so1);
+  f->mf_g2 = groups((int64_t)s2.size(), hdf::kMfSlots2, so2);
+  auto put = [&](const void* p, size_t bytes) {
+    const size_t at = (out.size() + 255) / 256 * 256;
+    out.resize(at + bytes);
+    if (bytes) std::memcpy(out.data() + at, p, bytes);
+    return at;
+  };
+  out.clear();
+  put(jobs.data(), jobs.size() * sizeof(hdf::MfJob));
+  f->mf_o_joff = put(joff.data(), joff.size() * 4);
+  f->mf_o_s1 = put(s1.data(), s1.size() * sizeof(hdf::MfSlot1));
+  f->mf_o_so1 = put(so1.data(), so1.size() * 4);
+  f->mf_o_s2 = put(s2.data(), s2.size() * sizeof(hdf::MfSlot2));
+  f->mf_o_so2 = put(so2.data(), so2.size() * 4);
+  return true;
+}
+
 static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   struct FinishTimer {
     hdf_factor* f;
@@ -398,7 +512,21 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
 
   // 5. memory budget, then the factor evaluation
   const bool mfree = f->storage == HDF_STORE_NONE;
-  const size_t fbytes = (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->felem();
+  if (mfree && f->H > 0 && !f->mf_chunked) {
+    // fused passes when the harmonics of 16 points fit in one workgroup's LDS
+    const int Kh = f->kept_k.back();
+    f->mf_nloop = 0;
+    for (int k = 0; k <= Kh; ++k) f->mf_nloop += hdf::index_count(d, k);
+    f->mf_lay1 = hdf::mf_layout(f->H, (int)f->S, f->mf_nloop, d, Kh, f->fprec, 1);
+    f->mf_lay2 = hdf::mf_layout(f->H, (int)f->S, f->mf_nloop, d, Kh, f->fprec, 2);
+    int dev = 0, max_lds = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIPCHK(hipDeviceGetAttribute(&f->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    f->mf_fused = std::max(f->mf_lay1.total, f->mf_lay2.total) <= max_lds;
+  }
+  const size_t fbytes = f->mf_fused ? 0
+                        : (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->felem();
   size_t freeb = 0, totb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totb));
   {
@@ -414,8 +542,10 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   }
   if (f->H > 0) {
     if (mfree) {
-      HIPCHK(f->cphi.ensure((size_t)f->H * f->ldC * f->felem()));
-      HIPCHK(f->cq.ensure((size_t)f->S * f->ldC * f->felem()));
+      if (!f->mf_fused) {
+        HIPCHK(f->cphi.ensure((size_t)f->H * f->ldC * f->felem()));
+        HIPCHK(f->cq.ensure((size_t)f->S * f->ldC * f->felem()));
+      }
     } else {
       HIPCHK(f->phi.ensure((size_t)f->H * f->ldN * f->felem()));
       HIPCHK(f->q.ensure((size_t)f->S * f->ldN * f->felem()));
@@ -512,7 +642,14 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
     for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
     HIPCHK(upload(f->degs_by_k, dbk.data(), dbk.size() * sizeof(hdf::DegDev)));
-    if (mfree) return HDF_OK;                   // evaluated chunk by chunk in every product
+    if (mfree) {                                // evaluated in every product
+      if (f->mf_fused) {
+        std::vector<char> tabs;
+        if (!mf_tables(f, tabs)) return fail(HDF_E_ARG, "internal: loop-order count of the fused tables");
+        HIPCHK(upload(f->mf_tabs, tabs.data(), tabs.size()));
+      }
+      return HDF_OK;
+    }
     HIPCHK(hipEventCreate(&f->ev_b0));
     HIPCHK(hipEventCreate(&f->ev_b1));
     HIPCHK(hipEventRecord(f->ev_b0, s));
@@ -588,12 +725,15 @@ hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t
   if (storage != HDF_STORE_FACTOR && storage != HDF_STORE_NONE) return fail(HDF_E_ARG, "unknown storage");
   const int64_t chunk = (opts && opts->chunk) ? opts->chunk : 262144;
   if (storage == HDF_STORE_NONE && chunk < 64) return fail(HDF_E_ARG, "chunk must be >= 64");
+  const int mf_chunked = opts ? opts->chunked : 0;
+  if (mf_chunked != 0 && mf_chunked != 1) return fail(HDF_E_ARG, "chunked must be 0 or 1");
   hipStream_t s = (hipStream_t)hip_stream;
 
   std::unique_ptr<hdf_factor> f(new hdf_factor());
   f->rank_rule = rule;
   if (storage == HDF_STORE_NONE) {
     f->storage = HDF_STORE_NONE;
+    f->mf_chunked = mf_chunked;
     f->chunk = std::min<int64_t>(chunk, n);
     f->ldC = (f->chunk + 63) / 64 * 64 + 64;
   }
@@ -1076,10 +1216,82 @@ static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t 
   return HDF_OK;
 }
 
+// Arguments of the fused matrix-free kernels.
+static hdf::MfArgs mf_args(hdf_handle h) {
+  hdf::MfArgs a{};
+  const char* base = (const char*)h->mf_tabs.p;
+  a.x_soa = h->x_soa.p; a.ldx = h->ldN; a.n = h->N; a.dtype = h->dtype; a.d = h->d;
+  a.geo = (const hdf::GeoDev*)h->geo_dev.p; a.u0 = h->u0; a.u1 = h->u1;
+  a.jobs = (const hdf::MfJob*)base; a.job_off = (const int32_t*)(base + h->mf_o_joff);
+  a.col_of = (const int32_t*)h->col_of.p; a.n_loop = h->mf_nloop;
+  a.chain = h->chain.p; a.K = h->tables.K;
+  a.q_len = (const int32_t*)h->q_len.p; a.q_off = (const int32_t*)h->q_off.p; a.q_coef = h->q_coef.p;
+  a.S = (int)h->S; a.H = h->H; a.prec = h->fprec;
+  return a;
+}
+
+// Workgroups of one fused pass that run at once on the device (occupancy x CUs), queried once.
+static int mf_resident(hdf_handle h, int pass) {
+  int& nb = pass == 1 ? h->mf_nb1 : h->mf_nb2;
+  if (!nb) nb = hdf::mf_blocks_per_cu(mf_args(h), pass, pass == 1 ? h->mf_lay1 : h->mf_lay2);
+  return std::max(1, nb) * std::max(1, h->n_cu);
+}
+
+// Pass 1 of a fused matrix-free factor: one launch over splits of the points (one workgroup per
+// resident slot), the split partials reduced as for a stored factor.
+static hdf_status pass1_fused(hdf_handle h, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W, DevBuf& Wd,
+                              hipStream_t s, bool timed) {
+  const int cpl = m16 / 16;
+  const int64_t n = h->N;
+  const int ny = h->mf_g1 * cpl;
+  int64_t ns = std::max<int64_t>(1, mf_resident(h, 1) / ny);
+  const size_t per_split = (size_t)h->r * m16 * sizeof(double);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)(256e6 / (double)per_split)));
+  ns = std::min<int64_t>(ns, (n + hdf::kMfP - 1) / hdf::kMfP);
+  const int64_t len = ((n + ns - 1) / ns + hdf::kMfP - 1) / hdf::kMfP * hdf::kMfP;
+  const int n_splits = (int)((n + len - 1) / len);
+  HIPCHK(h->ws_part.ensure(per_split * n_splits));
+  HIPCHK(W.ensure((size_t)h->r * m16 * sizeof(double)));
+  HIPCHK(Wd.ensure((size_t)h->r * m16 * h->felem()));
+  if (timed) {
+    if (!h->ev_mv[0])
+      for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(h->ev_mv[0], s));
+  }
+  const char* base = (const char*)h->mf_tabs.p;
+  HIPCHK(hdf::launch_mf_t(mf_args(h), h->mf_lay1, (const hdf::MfSlot1*)(base + h->mf_o_s1),
+                          (const int32_t*)(base + h->mf_o_so1), h->mf_g1, cpl, n_splits, len, V, ldv, (int)m, m16,
+                          h->r, (double*)h->ws_part.p, s));
+  if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
+  HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16, (const double*)h->lam_row.p,
+                                   (double*)W.p, Wd.p, h->fprec, s));
+  if (timed) HIPCHK(hipEventRecord(h->ev_mv[2], s));
+  return HDF_OK;
+}
+
+// Pass 2 of a fused matrix-free factor: KV = U (D W) over ranges of the points.
+static hdf_status pass2_fused(hdf_handle h, int64_t m, int m16, void* KV, int64_t ldkv, hipStream_t s) {
+  const int cpl = m16 / 16;
+  const int64_t n = h->N;
+  const int ny = h->mf_g2 * cpl;
+  int64_t nr = std::max<int64_t>(1, mf_resident(h, 2) / ny);
+  nr = std::min<int64_t>(nr, (n + hdf::kMfP - 1) / hdf::kMfP);
+  const int64_t len = ((n + nr - 1) / nr + hdf::kMfP - 1) / hdf::kMfP * hdf::kMfP;
+  const int n_ranges = (int)((n + len - 1) / len);
+  if (h->mf_g2 > 1) HIPCHK(h->ws_n.ensure((size_t)h->mf_g2 * n * m * h->felem()));
+  const char* base = (const char*)h->mf_tabs.p;
+  HIPCHK(hdf::launch_mf_n(mf_args(h), h->mf_lay2, (const hdf::MfSlot2*)(base + h->mf_o_s2),
+                          (const int32_t*)(base + h->mf_o_so2), h->mf_g2, cpl, n_ranges, len, h->ws_Wd.p, m16, KV,
+                          ldkv, (int)m, h->mf_g2 > 1 ? h->ws_n.p : nullptr, s));
+  return HDF_OK;
+}
+
 // side 2 (matrix-free factors): build the work-item tables only.
 static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_t ldv, int m16, DevBuf& W,
                         DevBuf& Wd, hipStream_t s, bool timed) {
-  if (h->storage == HDF_STORE_NONE && side != 2) return pass1_chunked(h, V, m, ldv, m16, W, Wd, s, timed);
+  if (h->storage == HDF_STORE_NONE && side != 2)
+    return h->mf_fused ? pass1_fused(h, V, m, ldv, m16, W, Wd, s, timed)
+                       : pass1_chunked(h, V, m, ldv, m16, W, Wd, s, timed);
   const int64_t n = side == 1 ? h->N2 : (side == 2 ? h->chunk : h->N);
   const void* phi = side == 1 ? h->phi2.p : h->phi.p;
   const void* qv = side == 1 ? h->q2.p : h->q.p;
@@ -1188,7 +1400,10 @@ static hdf_status matvec_impl(hdf_handle h, const void* V, int64_t m, int64_t ld
   const bool timed = h->time_products;
   hdf_status st = pass1(h, h->cross ? 1 : 0, V, m, ldv, m16, h->ws_W, h->ws_Wd, s, timed);
   if (st != HDF_OK) return st;
-  if (h->storage == HDF_STORE_NONE) {
+  if (h->storage == HDF_STORE_NONE && h->mf_fused) {
+    st = pass2_fused(h, m, m16, KV, ldkv, s);
+    if (st != HDF_OK) return st;
+  } else if (h->storage == HDF_STORE_NONE) {
     for (int64_t c0 = 0; c0 < n; c0 += h->chunk) {
       const int64_t nc = std::min(h->chunk, n - c0);
       st = eval_chunk(h, c0, nc, s);
@@ -1561,8 +1776,11 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
   info->center_radius = h->geo.R;
   info->rho2_min = h->u0;
   info->rho2_max = h->u1;
-  info->factor_bytes = (int64_t)((h->H + h->S) *
-                                 (h->storage == HDF_STORE_NONE ? h->ldC : h->ldN + (h->cross ? h->ldN2 : 0)) * h->felem());
+  info->factor_bytes = h->mf_fused ? 0
+                       : (int64_t)((h->H + h->S) *
+                                   (h->storage == HDF_STORE_NONE ? h->ldC : h->ldN + (h->cross ? h->ldN2 : 0)) *
+                                   h->felem());
+  info->mf_fused = h->mf_fused ? 1 : 0;
   info->storage = h->storage;
   info->factor_precision = h->fprec == 1 ? HDF_MIXED : HDF_FP64;
   info->chunk_points = h->storage == HDF_STORE_NONE ? h->chunk : 0;

@@ -158,6 +158,69 @@ hipError_t launch_adj_combine(const void* x_soa, int dtype, int64_t ldx, int64_t
                               const void* KS, int64_t ldks, const void* K2, int64_t ldk2, const void* Wm,
                               const void* Vm, int64_t ld, int m, void* dX, int64_t lddx, int prec, hipStream_t s);
 
+// Fused matrix-free passes (mf_kernels.hip).  A workgroup of kMfWaves
+// wavefronts takes kMfP points at a time: it evaluates their harmonics (the
+// factor-evaluation recurrences, split into subtrees run by 16-lane groups)
+// and radial functions into LDS and contracts them there with MFMA, so no
+// factor value reaches HBM.
+constexpr int kMfP = 16;                 // points per chunk
+constexpr int kMfWaves = 8;              // wavefronts per workgroup
+// One evaluation step of a wavefront: up to four subtrees of the harmonic
+// recursion with the same shape, one per 16-lane group (lane = point).  A
+// subtree fixes the azimuthal index and, for d >= 4, the index of chain level
+// d - 2; it runs the levels below.
+struct MfJob {
+  int32_t rem;      // K - b: the subtree's top loop runs rem + 1 times (same for the four)
+  int32_t ntask;    // subtrees in use, 1..4
+  int32_t pad[2];
+  int32_t mm[4];    // signed azimuthal index: m >= 0 the cosine branch, -m the sine branch
+  int32_t ntop[4];  // index at chain level d - 2 (d >= 4; 0 for d = 3)
+  int32_t t0[4];    // loop-order index of the subtree's first harmonic
+};
+// Pass 1: one accumulator tile of a wavefront, 16 harmonic rows of one degree with one radial
+// function: rank rows out0 + j s for j < nr.
+struct MfSlot1 {
+  int32_t row0, qrow, out0, s, nr;
+  int32_t pad[3];
+};
+// Pass 2: one MFMA step of a wavefront, harmonic rows row0 + j (j < nv <= 4) of one degree with one
+// radial function: rank rows rank0 + j s.
+struct MfSlot2 {
+  int32_t row0, qrow, rank0, s, nv;
+  int32_t pad[3];
+};
+// LDS layout (byte offsets) of a fused pass: harmonic rows (H + 16 x kMfP, the last 16 rows zero),
+// radial rows, V^T of the chunk (pass 1) or the per-wavefront partial products (pass 2), the
+// loop-order row table and the recurrence pairs.
+struct MfLayout {
+  int32_t phc, qc, aux, cmap, chain, total;
+};
+MfLayout mf_layout(int64_t H, int S, int64_t n_loop, int d, int K, int prec, int pass);
+constexpr int kMfSlots1 = 16;            // pass-1 accumulator tiles per wavefront
+constexpr int kMfSlots2 = 64;            // pass-2 steps per wavefront (their D W operands stay in registers)
+struct MfArgs {
+  const void* x_soa; int64_t ldx; int64_t n; int dtype; int d;
+  const GeoDev* geo; double u0, u1;
+  const MfJob* jobs; const int32_t* job_off;          // jobs of wavefront w: [job_off[w], job_off[w + 1])
+  const int32_t* col_of; int64_t n_loop;
+  const void* chain; int K;
+  const int32_t* q_len; const int32_t* q_off; const void* q_coef; int S; int64_t H;
+  int prec;                                           // factor type: 1 binary32, 0 binary64
+};
+// Workgroups of one fused pass that fit on a CU at once (occupancy of the kernel with its LDS).
+int mf_blocks_per_cu(const MfArgs& a, int pass, const MfLayout& lay);
+// Pass 1: partial[split][row][c] for splits of split_len points (a multiple of kMfP), rank rows of
+// slot group g (slots of wavefront w: [slot_off[9 g + w], slot_off[9 g + w + 1])), columns of tile ct;
+// grid n_splits x (n_groups cpl).
+hipError_t launch_mf_t(const MfArgs& a, const MfLayout& lay, const MfSlot1* slots, const int32_t* slot_off,
+                       int n_groups, int cpl, int n_splits, int64_t split_len, const void* V, int64_t ldv, int m,
+                       int m16, int64_t rank, double* partials, hipStream_t s);
+// Pass 2: KV = U Wd over ranges of range_len points; with n_groups > 1 each slot group writes its
+// share to part (n_groups x n x m, factor type), summed in group order into KV.
+hipError_t launch_mf_n(const MfArgs& a, const MfLayout& lay, const MfSlot2* slots, const int32_t* slot_off,
+                       int n_groups, int cpl, int n_ranges, int64_t range_len, const void* Wd, int m16, void* KV,
+                       int64_t ldkv, int m, void* part, hipStream_t s);
+
 // Scratch of hdf_matvec_noalloc: a fixed device array per GPU (scratch.hip).
 // scratch_address returns its device address on the current device (resolved
 // once per device); hipErrorInvalidDevice for device ordinals >= 64.

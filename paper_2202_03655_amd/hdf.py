@@ -48,13 +48,13 @@ class HDFInfo(ctypes.Structure):
         ("s_k", ctypes.c_int32 * (HDF_MAX_DEGREE // 2 + 1)),
         ("rank_rule", ctypes.c_int32), ("tau_bound", ctypes.c_double), ("est_error", ctypes.c_double),
         ("degree_bound", ctypes.c_int32), ("storage", ctypes.c_int32), ("chunk_points", ctypes.c_int64),
-        ("factor_precision", ctypes.c_int32),
+        ("factor_precision", ctypes.c_int32), ("mf_fused", ctypes.c_int32),
     ]
 
 
 class BuildOptions(ctypes.Structure):
     _fields_ = [("rank_rule", ctypes.c_int32), ("n_pairs", ctypes.c_int32), ("margin", ctypes.c_double),
-                ("storage", ctypes.c_int32), ("pad", ctypes.c_int32), ("chunk", ctypes.c_int64)]
+                ("storage", ctypes.c_int32), ("chunked", ctypes.c_int32), ("chunk", ctypes.c_int64)]
 
 
 RANK_RULES = {"bound": 0, "sampled": 1}
@@ -171,11 +171,12 @@ class Factor:
     """Handle of a built HDF factor K ~ U D U^T (owns the library handle)."""
 
     def __init__(self, X, kernel="gaussian", lengthscale=1.0, tol=1e-4, precision=None, rank_rule="bound",
-                 n_pairs=0, margin=0.0, storage="factor", chunk=0):
+                 n_pairs=0, margin=0.0, storage="factor", chunk=0, fused=True):
         """rank_rule "bound": p and tau from the a-priori budget (Sec. 3.5); "sampled": the tighter
         rule of the remark after Eq. bound (n_pairs sampled pairs, error kept <= margin * tol;
         0 selects the library defaults).  storage "none": matrix-free, the factor is re-evaluated
-        per chunk of `chunk` points (0: the library default) in every product."""
+        in every pass: inside the fused kernels when `fused` and the harmonics of 16 points fit in
+        LDS, else per chunk of `chunk` points (0: the library default)."""
         L = lib()
         if precision is None:
             precision = HDF_FP64 if X.dtype == torch.float64 else HDF_MIXED
@@ -189,7 +190,8 @@ class Factor:
         self.tol = float(tol)
         self.device = X.device
         h = ctypes.c_void_p()
-        opts = BuildOptions(RANK_RULES[rank_rule], int(n_pairs), float(margin), STORAGE[storage], 0, int(chunk))
+        opts = BuildOptions(RANK_RULES[rank_rule], int(n_pairs), float(margin), STORAGE[storage],
+                            0 if fused else 1, int(chunk))
         with torch.cuda.device(X.device):
             _check(L.hdf_build_ex(X.data_ptr(), 0 if dtype == torch.float32 else 1, self.n, self.d,
                                   X.stride(0), KERNELS[kernel], self.lengthscale, self.tol,

@@ -1,7 +1,7 @@
 """Build the CPU-emulated library (libhdf_emu.so) under ASan/UBSan.
 
-The product sources (capi.cpp, planner.cpp, krr.cpp, and kernels.hip and
-krr_kernels.hip through translate.py) are compiled unchanged for the host, with the device-allocation
+The product sources (capi.cpp, planner.cpp, krr.cpp, and kernels.hip,
+krr_kernels.hip, mf_kernels.hip and scratch.hip through translate.py) are compiled unchanged for the host, with the device-allocation
 cache off (-DHDF_ALLOC_CACHE=0: exact-size allocations keep ASan's redzones tight).  The build lands in tests/emu/_build/<hash>
 and is reused while sources and flags are unchanged.
 """
@@ -21,7 +21,7 @@ FLAGS = ["-std=c++17", "-g", "-O1", "-fPIC", "-fno-omit-frame-pointer", "-fsanit
          "-Wno-psabi", "-Wno-unused-value", "-I", os.path.join(HERE, "shim"), "-I", CSRC]
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "kernels.hpp", "capi.cpp", "planner.cpp", "planner.hpp",
                                             "krr_kernels.hip", "krr_kernels.hpp", "krr.cpp", "status.hpp",
-                                            "scratch.hip")] + \
+                                            "scratch.hip", "mf_kernels.hip")] + \
           [os.path.join(ROOT, "include", "hdf.h")] + \
           [os.path.join(HERE, f) for f in ("emu_hip.h", "emu_rt.cpp", "translate.py", "build.py")]
 
@@ -60,7 +60,9 @@ def build():
     open(kern2, "w").write(translate(open(os.path.join(CSRC, "krr_kernels.hip")).read(), "krr_kernels.hpp"))
     kern3 = os.path.join(tmp, "scratch_emu.cpp")
     open(kern3, "w").write(translate(open(os.path.join(CSRC, "scratch.hip")).read()))
-    units = [kern, kern2, kern3, os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"),
+    kern4 = os.path.join(tmp, "mf_kernels_emu.cpp")
+    open(kern4, "w").write(translate(open(os.path.join(CSRC, "mf_kernels.hip")).read()))
+    units = [kern, kern2, kern3, kern4, os.path.join(CSRC, "capi.cpp"), os.path.join(CSRC, "planner.cpp"),
              os.path.join(CSRC, "krr.cpp"), os.path.join(HERE, "emu_rt.cpp")]
 
     def compile_one(src):

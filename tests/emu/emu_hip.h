@@ -44,6 +44,9 @@ hipError_t hipGetDevice(int* d);
 hipError_t hipGetLastError();
 const char* hipGetErrorString(hipError_t e);
 hipError_t hipGetSymbolAddress(void** p, const void* symbol);
+typedef enum { hipDeviceAttributeMaxSharedMemoryPerBlock = 74, hipDeviceAttributeMultiprocessorCount = 63 } hipDeviceAttribute_t;
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int dev);
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* nb, const void* fn, int block, size_t shm);
 void emu_flush();
 }
 

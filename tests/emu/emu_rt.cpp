@@ -493,6 +493,14 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
 }
 hipError_t hipMemGetInfo(size_t* f, size_t* t) { *f = (size_t)200 << 30; *t = (size_t)288 << 30; return hipSuccess; }
 hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+// a small device: 4 CUs, one workgroup of a kernel at a time, the gfx950 LDS limit
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+  if (a == hipDeviceAttributeMaxSharedMemoryPerBlock) *v = 160 * 1024;
+  else if (a == hipDeviceAttributeMultiprocessorCount) *v = 4;
+  else return hipErrorInvalidValue;
+  return hipSuccess;
+}
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* nb, const void*, int, size_t) { *nb = 1; return hipSuccess; }
 hipError_t hipGetLastError() { hipError_t e = emu::g_last; emu::g_last = hipSuccess; return e; }
 const char* hipGetErrorString(hipError_t e) { return e ? "emulated error" : "no error"; }
 void emu_flush() { emu::flush(); }

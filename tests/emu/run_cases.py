@@ -212,35 +212,63 @@ def case_sampled():
 
 
 def case_mfree():
-    """Matrix-free factor (HDF_STORE_NONE): K~V per chunk against the oracle and the stored factor, on a
-    ragged chunking (three chunks, the last short), with m above the LDS-staged limit, and dF/dl."""
+    """Matrix-free factor (HDF_STORE_NONE), fused kernels and chunk scratch: K~V against the oracle and
+    the stored factor on a ragged point count (the last 16-point chunk and the last chunk of 1000 both
+    short), m = 1, 17 and 70 (five column tiles), dF/dl; then d = 5 in binary32 and a binary64 factor of
+    binary32 points through the fused kernels."""
     X = wl.unit_ball(2345, 3, 71)
     st = ohdf.build(X, "gaussian", 1.0, 1e-6)
     Xd = to_dev(X, torch.float64)
     fs = hdf.Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64)
-    fm = hdf.Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64, storage="none", chunk=1000)
-    inf = fm.info()
-    check("mfree info", inf["storage"] == 1 and inf["chunk_points"] == 1000 and inf["rank"] == st["r"],
-          f"storage {inf['storage']} chunk {inf['chunk_points']} rank {inf['rank']}")
-    for m in (1, 17, 70):
-        V = wl.rhs(2345, m, 72 + m)
-        Vd = to_dev(V, torch.float64)
-        km = fm.matvec(Vd).numpy()
-        e1 = rel(km, ohdf.matvec(st, V))
-        e2 = rel(km, fs.matvec(Vd).numpy())
-        check(f"mfree matvec m={m}", e1 <= 1e-12 and e2 <= 1e-13, f"vs oracle {e1:.2e}, vs stored {e2:.2e}")
     W = wl.rhs(2345, 2, 80)
-    V = wl.rhs(2345, 2, 81)
-    dlm, _ = fm.backward(to_dev(W, torch.float64), to_dev(V, torch.float64), need_x=False)
-    dls, _ = fs.backward(to_dev(W, torch.float64), to_dev(V, torch.float64), need_x=False)
-    check("mfree dF/dl", abs(dlm - dls) <= 1e-12 * abs(dls), f"{dlm:.12e} vs {dls:.12e}")
+    V2 = wl.rhs(2345, 2, 81)
+    dls, _ = fs.backward(to_dev(W, torch.float64), to_dev(V2, torch.float64), need_x=False)
+    for fused in (True, False):
+        tag = "fused" if fused else "chunked"
+        fm = hdf.Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64, storage="none", chunk=1000, fused=fused)
+        inf = fm.info()
+        check(f"mfree {tag} info", inf["storage"] == 1 and inf["mf_fused"] == int(fused) and inf["rank"] == st["r"]
+              and (inf["factor_bytes"] == 0) == fused,
+              f"storage {inf['storage']} fused {inf['mf_fused']} rank {inf['rank']} bytes {inf['factor_bytes']}")
+        for m in (1, 17, 70):
+            V = wl.rhs(2345, m, 72 + m)
+            Vd = to_dev(V, torch.float64)
+            km = fm.matvec(Vd).numpy()
+            e1 = rel(km, ohdf.matvec(st, V))
+            e2 = rel(km, fs.matvec(Vd).numpy())
+            check(f"mfree {tag} matvec m={m}", e1 <= 1e-12 and e2 <= 1e-13, f"vs oracle {e1:.2e}, vs stored {e2:.2e}")
+        dlm, _ = fm.backward(to_dev(W, torch.float64), to_dev(V2, torch.float64), need_x=False)
+        check(f"mfree {tag} dF/dl", abs(dlm - dls) <= 1e-12 * abs(dls), f"{dlm:.12e} vs {dls:.12e}")
     Xf = wl.uniform_cube(1013, 4, 104).astype(np.float32)
     fm32 = hdf.Factor(to_dev(Xf, torch.float32), "gaussian", 0.7, 1e-5, precision=hdf.HDF_MIXED, storage="none",
-                      chunk=300)
+                      chunk=300, fused=False)
     fs32 = hdf.Factor(to_dev(Xf, torch.float32), "gaussian", 0.7, 1e-5, precision=hdf.HDF_MIXED)
     V = wl.rhs(1013, 5, 82).astype(np.float32)
     e = rel(fm32.matvec(to_dev(V, torch.float32)).numpy(), fs32.matvec(to_dev(V, torch.float32)).numpy())
-    check("mfree mixed vs stored", e <= 1e-6, f"{e:.2e}")
+    check("mfree chunked mixed vs stored", e <= 1e-6, f"{e:.2e}")
+    # d = 5, binary32 factor, fused
+    X5 = wl.max_norm_one(wl.gaussian_mixture(1501, 5, 103)).astype(np.float32)
+    X5d = to_dev(X5, torch.float32)
+    st5 = ohdf.build(X5.astype(np.float64), "cauchy", 1.0, 1e-4)
+    f5 = hdf.Factor(X5d, "cauchy", 1.0, 1e-4, precision=hdf.HDF_MIXED, storage="none")
+    s5 = hdf.Factor(X5d, "cauchy", 1.0, 1e-4, precision=hdf.HDF_MIXED)
+    V = wl.rhs(1501, 16, 83).astype(np.float32)
+    km = f5.matvec(to_dev(V, torch.float32)).numpy().astype(np.float64)
+    e1 = rel(km, ohdf.matvec(st5, V.astype(np.float64)))
+    e2 = rel(km, s5.matvec(to_dev(V, torch.float32)).numpy())
+    check("mfree fused d=5 binary32", f5.info()["mf_fused"] == 1 and e1 <= 1e-4 and e2 <= 1e-6,
+          f"vs oracle {e1:.2e} (tol 1e-4), vs stored {e2:.2e}")
+    # binary64 factor of binary32 points (tol below the binary32 range), fused
+    X6 = wl.unit_ball(1000, 3, 101).astype(np.float32)
+    X6d = to_dev(X6, torch.float32)
+    st6 = ohdf.build(X6.astype(np.float64), "gaussian", 1.0, 1e-7)
+    f6 = hdf.Factor(X6d, "gaussian", 1.0, 1e-7, precision=hdf.HDF_MIXED, storage="none")
+    V = wl.rhs(1000, 3, 84).astype(np.float32)
+    km = f6.matvec(to_dev(V, torch.float32)).numpy().astype(np.float64)
+    e1 = rel(km, ohdf.matvec(st6, V.astype(np.float64)))
+    i6 = f6.info()
+    check("mfree fused binary64 factor", i6["mf_fused"] == 1 and i6["factor_precision"] == 0 and e1 <= 1e-7,
+          f"vs oracle {e1:.2e} (tol 1e-7), fused {i6['mf_fused']}, factor precision {i6['factor_precision']}")
 
 
 def case_krr():

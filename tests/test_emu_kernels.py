@@ -2,12 +2,13 @@
 
 A memory-safety net for the device path, not a parity claim for it (the
 GPU tests run the real library on the device).  tests/emu/translate.py
-rewrites kernels.hip and krr_kernels.hip mechanically into C++ (launches,
+rewrites kernels.hip, krr_kernels.hip, mf_kernels.hip and scratch.hip
+mechanically into C++ (launches,
 __shared__ variables, the dynamic LDS array); tests/emu/emu_rt.cpp runs every
 HIP thread as a fiber with __syncthreads, __syncthreads_count, lane shuffles
 and the 16x16x4 MFMA as collectives, and implements the HIP runtime calls of
 capi.cpp and krr.cpp on host memory.  capi.cpp, krr.cpp and planner.cpp are
-compiled unchanged, with the dF/dX kernels dispatched.  tests/emu/run_cases.py
+compiled unchanged.  tests/emu/run_cases.py
 drives the Python binding (device tensors in guarded host memory) and compares
 every result with the oracle.
 

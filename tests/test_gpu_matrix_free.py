@@ -1,14 +1,17 @@
-"""Matrix-free factor (HDF_STORE_NONE) through the C ABI.
+"""Matrix-free factor (HDF_STORE_NONE) through the C ABI, both forms: the
+fused kernels (16 points at a time evaluated and contracted in LDS) and the
+chunk scratch.
 
 The factor is the same as the stored one (the build differs only in not
 evaluating it), so K~V is checked against the oracle to the stored path's
 tolerance and against the stored path on the same device: binary64 within
-1e-12 of the oracle and 1e-13 of the stored product (the chunk-wise pass-1
-partial sums are added in another order), binary32 within 1e-6 of the
-stored product.  Chunkings: many small chunks, a ragged last chunk, one chunk
-covering all points; m = 1, 17 and 70 (past the LDS-staged pass 1); dF/dl;
-the sampled rank rule; N = 1; the headline workload at full size against
-the stored factor.
+1e-12 of the oracle and 1e-13 of the stored product (the partial sums are
+added in another order), binary32 within 1e-6 of the stored product.
+Chunkings: many small chunks, a ragged last chunk, one chunk covering all
+points; m = 1, 17, 70 and 256 (16 column tiles); dF/dl; the sampled rank
+rule; N = 1 and N below one 16-point chunk; a binary64 factor of binary32
+points; a factor whose harmonics do not fit in LDS (chunk scratch chosen);
+the headline workload at full size against the stored factor.
 """
 import numpy as np
 import pytest
@@ -32,17 +35,21 @@ def hdf():
     return h
 
 
-@pytest.mark.parametrize("chunk", [64, 1000, 4096])
-def test_fp64_against_oracle_and_stored(chunk):
+@pytest.mark.parametrize("chunk,fused", [(64, False), (1000, False), (4096, False), (0, True)])
+def test_fp64_against_oracle_and_stored(chunk, fused):
     X = wl.unit_ball(2345, 3, 71)
     st = ohdf.build(X, "gaussian", 1.0, 1e-6)
     Xd = to_dev(X, torch.float64)
     fs = hdf().Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf().HDF_FP64)
-    fm = hdf().Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf().HDF_FP64, storage="none", chunk=chunk)
+    fm = hdf().Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf().HDF_FP64, storage="none", chunk=chunk, fused=fused)
     inf = fm.info()
-    assert inf["storage"] == 1 and inf["chunk_points"] == min(chunk, 2345) and inf["rank"] == st["r"]
-    assert inf["factor_bytes"] < fs.info()["factor_bytes"] or chunk >= 2345
-    for m in (1, 17, 70):
+    assert inf["storage"] == 1 and inf["rank"] == st["r"] and inf["mf_fused"] == int(fused)
+    if fused:
+        assert inf["factor_bytes"] == 0
+    else:
+        assert inf["chunk_points"] == min(chunk, 2345)
+        assert inf["factor_bytes"] < fs.info()["factor_bytes"] or chunk >= 2345
+    for m in (1, 17, 70) + ((256,) if fused else ()):
         V = wl.rhs(2345, m, 72 + m)
         Vd = to_dev(V, torch.float64)
         km = fm.matvec(Vd).cpu().numpy()
@@ -69,6 +76,82 @@ def test_mixed_and_dl_and_sampled():
     assert rel_fro(sm.matvec(V).cpu().numpy(), ss.matvec(V).cpu().numpy()) <= 1e-6
 
 
+@pytest.mark.parametrize("fused", [True, False])
+def test_mixed_against_stored_and_dl(fused):
+    h = hdf()
+    Xf = wl.uniform_cube(5013, 4, 104).astype(np.float32)
+    Xd = to_dev(Xf, torch.float32)
+    fs = h.Factor(Xd, "gaussian", 0.7, 1e-5, precision=h.HDF_MIXED)
+    fm = h.Factor(Xd, "gaussian", 0.7, 1e-5, precision=h.HDF_MIXED, storage="none", chunk=2048, fused=fused)
+    assert fm.info()["mf_fused"] == int(fused)
+    for m in (3, 16, 40):
+        V = to_dev(wl.rhs(5013, m, 90 + m).astype(np.float32), torch.float32)
+        e = rel_fro(fm.matvec(V).cpu().numpy(), fs.matvec(V).cpu().numpy())
+        print(f"fused={fused} m={m}: matrix-free vs stored {e:.2e}")
+        assert e <= 1e-6
+    W = to_dev(wl.rhs(5013, 4, 83).astype(np.float32), torch.float32)
+    V = to_dev(wl.rhs(5013, 4, 84).astype(np.float32), torch.float32)
+    dlm, _ = fm.backward(W, V, need_x=False)
+    dls, _ = fs.backward(W, V, need_x=False)
+    assert abs(dlm - dls) <= 1e-6 * abs(dls)
+
+
+def test_fused_binary64_factor_of_binary32_points():
+    """tol 1e-7 under HDF_MIXED: binary64 factor, binary32 data, fused kernels; against the oracle on
+    the same binary32 values within tol, and the stored factor within 1e-12."""
+    h = hdf()
+    Xf = wl.unit_ball(3001, 3, 101).astype(np.float32)
+    st = ohdf.build(Xf.astype(np.float64), "gaussian", 1.0, 1e-7)
+    Xd = to_dev(Xf, torch.float32)
+    fm = h.Factor(Xd, "gaussian", 1.0, 1e-7, precision=h.HDF_MIXED, storage="none")
+    fs = h.Factor(Xd, "gaussian", 1.0, 1e-7, precision=h.HDF_MIXED)
+    inf = fm.info()
+    assert inf["mf_fused"] == 1 and inf["factor_precision"] == h.HDF_FP64 and inf["rank"] == st["r"]
+    V = wl.rhs(3001, 5, 85).astype(np.float32)
+    km = fm.matvec(to_dev(V, torch.float32)).cpu().numpy().astype(np.float64)
+    e1 = rel_fro(km, ohdf.matvec(st, V.astype(np.float64)))
+    e2 = rel_fro(km, fs.matvec(to_dev(V, torch.float32)).cpu().numpy().astype(np.float64))
+    print(f"binary64 factor, fused: vs oracle {e1:.2e}, vs stored {e2:.2e}")
+    assert e1 <= 1e-7 and e2 <= 1e-7
+
+
+def test_fused_d5_and_too_large_for_lds():
+    """d = 5 binary32 through the fused kernels against the oracle (within tol) and the stored product;
+    d = 6 binary64 with 2,000+ harmonics, whose 16-point tile does not fit in LDS: the chunk scratch is
+    chosen and still matches."""
+    h = hdf()
+    X5 = wl.max_norm_one(wl.gaussian_mixture(2003, 5, 103)).astype(np.float32)
+    st5 = ohdf.build(X5.astype(np.float64), "cauchy", 1.0, 1e-4)
+    X5d = to_dev(X5, torch.float32)
+    f5 = h.Factor(X5d, "cauchy", 1.0, 1e-4, precision=h.HDF_MIXED, storage="none")
+    s5 = h.Factor(X5d, "cauchy", 1.0, 1e-4, precision=h.HDF_MIXED)
+    assert f5.info()["mf_fused"] == 1
+    V = wl.rhs(2003, 16, 86).astype(np.float32)
+    km = f5.matvec(to_dev(V, torch.float32)).cpu().numpy().astype(np.float64)
+    e1 = rel_fro(km, ohdf.matvec(st5, V.astype(np.float64)))
+    e2 = rel_fro(km, s5.matvec(to_dev(V, torch.float32)).cpu().numpy().astype(np.float64))
+    print(f"d=5 fused: vs oracle {e1:.2e}, vs stored {e2:.2e}")
+    assert e1 <= 1e-4 and e2 <= 1e-6
+    X6 = wl.shell(801, 6, 105)
+    st6 = ohdf.build(X6, "matern52", 8.0, 1e-7)
+    f6 = h.Factor(to_dev(X6, torch.float64), "matern52", 8.0, 1e-7, precision=h.HDF_FP64, storage="none")
+    assert f6.info()["mf_fused"] == 0 and f6.info()["factor_bytes"] > 0
+    V = wl.rhs(801, 2, 87)
+    assert rel_fro(f6.matvec(to_dev(V, torch.float64)).cpu().numpy(), ohdf.matvec(st6, V)) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 7, 16, 17, 33])
+def test_fused_tiny_point_counts(n):
+    """Fewer points than one 16-point chunk, exactly one, and ragged tails of one point."""
+    h = hdf()
+    X = wl.unit_ball(n, 3, 200 + n)
+    st = ohdf.build(X, "gaussian", 1.0, 1e-6)
+    f = h.Factor(to_dev(X, torch.float64), "gaussian", 1.0, 1e-6, precision=h.HDF_FP64, storage="none")
+    assert f.info()["mf_fused"] == int(st["r"] > 0)
+    V = wl.rhs(n, 3, 300 + n)
+    assert rel_fro(f.matvec(to_dev(V, torch.float64)).cpu().numpy(), ohdf.matvec(st, V)) <= 1e-12
+
+
 def test_edges_and_errors():
     h = hdf()
     X = wl.unit_ball(1, 3, 3)
@@ -89,13 +172,16 @@ def test_full_size_headline_against_stored():
     X = wl.points("gmm5_cauchy_1e-4").astype(np.float32)
     Xd = to_dev(X, torch.float32)
     fs = h.Factor(Xd, "cauchy", 1.0, 1e-4, precision=h.HDF_MIXED)
-    fm = h.Factor(Xd, "cauchy", 1.0, 1e-4, precision=h.HDF_MIXED, storage="none")
     V = to_dev(wl.rhs(len(X), 16, 7).astype(np.float32), torch.float32)
-    a = fm.matvec(V).cpu().numpy().astype(np.float64)
     b = fs.matvec(V).cpu().numpy().astype(np.float64)
-    e = rel_fro(a, b)
-    ifm, ifs = fm.info(), fs.info()
-    print(f"matrix-free vs stored: {e:.2e}; scratch {ifm['factor_bytes'] / 1e6:.0f} MB vs stored "
-          f"{ifs['factor_bytes'] / 1e6:.0f} MB; pass 1 {ifm['t_mv_t_ms']:.3f} ms, pass 2 {ifm['t_mv_n_ms']:.3f} ms")
-    assert ifm["rank"] == ifs["rank"]
-    assert e <= 2e-6
+    ifs = fs.info()
+    for fused in (True, False):
+        fm = h.Factor(Xd, "cauchy", 1.0, 1e-4, precision=h.HDF_MIXED, storage="none", fused=fused)
+        a = fm.matvec(V).cpu().numpy().astype(np.float64)
+        e = rel_fro(a, b)
+        ifm = fm.info()
+        print(f"matrix-free ({'fused' if fused else 'chunked'}) vs stored: {e:.2e}; scratch "
+              f"{ifm['factor_bytes'] / 1e6:.0f} MB vs stored {ifs['factor_bytes'] / 1e6:.0f} MB; pass 1 "
+              f"{ifm['t_mv_t_ms']:.3f} ms, pass 2 {ifm['t_mv_n_ms']:.3f} ms", flush=True)
+        assert ifm["rank"] == ifs["rank"] and ifm["mf_fused"] == int(fused)
+        assert e <= 2e-6
