@@ -125,7 +125,11 @@ typedef struct {
                                 tol <= HDF_SPLIT_TOL report HDF_FP64)        */
   int32_t  mf_fused;         /* HDF_STORE_NONE: 1 if the products run the
                                 fused kernels (factor_bytes is then 0: no
-                                scratch per point); 0 otherwise             */
+                                scratch per point), 2 if they run their
+                                double-buffered form (half of the
+                                wavefronts evaluate the next 16 points while
+                                the others contract the current ones);
+                                0 otherwise                                 */
 } hdf_info_t;
 
 /* Build the factor (Algorithm 1, symmetric case, Remark 1).

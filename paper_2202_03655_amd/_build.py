@@ -1,4 +1,5 @@
 """Builds the HIP shared library libhdf.so in-tree (gfx950)."""
+import concurrent.futures
 import os
 import subprocess
 
@@ -25,17 +26,22 @@ def build(verbose=False):
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds = []
     for src in ("planner.cpp", "capi.cpp", "krr.cpp"):
         o = os.path.join(objdir, src + ".o")
-        _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", *COMMON, "-c", os.path.join(CSRC, src), "-o", o])
-        objs.append(o)
-    for src in ("kernels.hip", "krr_kernels.hip", "mf_kernels.hip", "scratch.hip"):
+        cmds.append((o, [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", *COMMON, "-c",
+                         os.path.join(CSRC, src), "-o", o]))
+    for src in ("mf_kernels.hip", "kernels.hip", "krr_kernels.hip", "scratch.hip"):
         o = os.path.join(objdir, src + ".o")
-        out = _run([HIPCC, *DEVICE_FLAGS, *COMMON, "-c", os.path.join(CSRC, src), "-o", o])
-        if verbose and out:
-            print(out)
-        objs.append(o)
+        cmds.append((o, [HIPCC, *DEVICE_FLAGS, *COMMON, "-c", os.path.join(CSRC, src), "-o", o]))
+    # the translation units are independent: compile them concurrently
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        outs = list(ex.map(lambda c: _run(c[1]), cmds))
+    if verbose:
+        for out in outs:
+            if out:
+                print(out)
+    objs = [o for o, _ in cmds]
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE_FLAGS, "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -189,9 +189,13 @@ struct hdf_factor {
   int mf_chunked = 0;                             // option: never use the fused kernels
   bool mf_fused = false;
   DevBuf mf_tabs;                                 // jobs | job_off | slots1 | slot_off1 | slots2 | slot_off2
-  size_t mf_o_joff = 0, mf_o_s1 = 0, mf_o_so1 = 0, mf_o_s2 = 0, mf_o_so2 = 0;
-  int mf_g1 = 1, mf_g2 = 1, mf_nb1 = 0, mf_nb2 = 0, n_cu = 0;
-  int64_t mf_nloop = 0;
+  size_t mf_o_joff = 0, mf_o_s1 = 0, mf_o_so1 = 0, mf_o_s2 = 0, mf_o_so2 = 0, mf_o_r1 = 0, mf_o_r2 = 0, mf_o_bt = 0;
+  int mf_ntasks = 0;
+  int mf_g1 = 1, mf_g2 = 1, mf_nb1 = 0, mf_nb2 = 0, n_cu = 0, mf_nr1 = 0, mf_nr2 = 0;
+  int64_t mf_nloop = 0, mf_nqc = 0, mf_t1 = 0, mf_t2 = 0;
+  int mf_spad = 0, mf_lpad = 0;
+  bool mf_spec = false;
+  size_t mf_o_qm = 0;
   hdf::MfLayout mf_lay1{}, mf_lay2{};
   double tau0 = 0, est_error = -1.0;             // budget threshold, sampled estimate
   std::vector<double> a;                          // p+1 coefficients
@@ -370,52 +374,99 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
 // evaluation jobs per wavefront (subtrees of one shape, four per job, spread over the wavefronts
 // by longest-first assignment of their leaf counts), then the pass-1 accumulator tiles and the
 // pass-2 steps, each cut into groups of at most kMfWaves x kMfSlots wavefront shares.
-static bool mf_tables(hdf_factor* f, std::vector<char>& out) {
+static bool mf_tables(hdf_factor* f, const std::vector<int32_t>& col_of, std::vector<char>& out) {
   const int d = f->d, K = f->kept_k.back();
   auto binom = [](int64_t nn, int64_t kk) {
     double v = 1.0;
     for (int64_t i = 1; i <= kk; ++i) v = v * (double)(nn - kk + i) / (double)i;
     return (int64_t)std::llround(v);
   };
-  const int TL = d == 3 ? 1 : d - 3;              // levels run by a subtree
-  struct Task { int ms, ntop, t0, rem; };
-  std::map<int, std::vector<Task>> by_rem;
+  const int TL = d == 3 ? 1 : d - 3;              // levels below a subtree's prefix
+  // subtrees (enumeration order: m ascending, cosine before sine, then the level d-2 index), listed
+  // by base b = m + (level d-2 index) with their first loop-order harmonic
+  std::vector<std::vector<std::pair<int, int>>> by_b(K + 1);
   int64_t t = 0;
+  int id = 0;
   for (int mm = 0; mm <= K; ++mm)
     for (int sg = 0; sg < (mm > 0 ? 2 : 1); ++sg) {
-      const int ms = sg ? -mm : mm;
       const int top = d == 3 ? 0 : K - mm;
-      for (int ntop = 0; ntop <= top; ++ntop) {
+      for (int ntop = 0; ntop <= top; ++ntop, ++id) {
         const int b = mm + ntop;
-        by_rem[K - b].push_back(Task{ms, d == 3 ? 0 : ntop, (int)t, K - b});
+        by_b[b].push_back({id, (int)t});
         t += binom(K - b + TL, TL);
       }
     }
-  if (t != f->mf_nloop) return false;
-  struct JobCost { hdf::MfJob j; double cost; };
-  std::vector<JobCost> jl;
-  for (auto& kv : by_rem) {
-    const std::vector<Task>& v = kv.second;
-    for (size_t i = 0; i < v.size(); i += 4) {
-      hdf::MfJob j{};
-      j.rem = kv.first;
-      j.ntask = (int)std::min<size_t>(4, v.size() - i);
-      int setup = 0;
-      for (int e = 0; e < 4; ++e) {
-        const Task& tk = v[i + (e < j.ntask ? e : 0)];
-        j.mm[e] = tk.ms; j.ntop[e] = tk.ntop; j.t0[e] = tk.t0;
-        setup = std::max(setup, std::abs(tk.ms) + tk.ntop);
-      }
-      jl.push_back(JobCost{j, (double)binom(kv.first + TL, TL) + 0.5 * setup + 4.0});
-    }
+  if (t != f->mf_nloop || id != (d == 3 ? 2 * K + 1 : (K + 1) * (K + 1))) return false;
+  std::vector<int32_t> btab;
+  std::vector<int> bstart(K + 1);
+  for (int b = 0; b <= K; ++b) {
+    bstart[b] = (int)btab.size() / 2;
+    for (auto& e : by_b[b]) { btab.push_back(e.first); btab.push_back(e.second); }
   }
-  std::stable_sort(jl.begin(), jl.end(), [](const JobCost& a, const JobCost& b) { return a.cost > b.cost; });
+  // jobs: one per base, split (level d-3 ranges, then subtree lists in multiples of four) while the
+  // largest exceeds an eighth of the total; cost = per pass over the shared levels, the harmonics
+  // below times (recurrence + one product and store per subtree in the lane group), plus the level
+  // d-3 steps
+  auto below = [&](int b, int n) -> int64_t { return d >= 5 ? binom(K - b - n + d - 4, d - 4) : (int64_t)(K - b + 1); };
+  auto cost = [&](const hdf::MfJob& j) {
+    int64_t leaves = 0;
+    const int nhi = d >= 5 ? j.n_hi : 0;
+    for (int n = d >= 5 ? j.n_lo : 0; n <= nhi; ++n) leaves += below(j.b, n);
+    const int per_grp = (j.ntask + 3) / 4;
+    double c = 0.0;
+    for (int kb = 0; kb < per_grp; kb += 4) {
+      const int nb = std::min(4, per_grp - kb);
+      c += (double)leaves * (5.0 + 2.0 * nb) + (d >= 5 ? 5.0 * (nhi + 1) : 0.0) + 8.0;
+    }
+    return c;
+  };
+  std::vector<hdf::MfJob> jl;
+  for (int b = 0; b <= K; ++b) {
+    hdf::MfJob j{};
+    j.b = b; j.n_lo = 0; j.n_hi = d >= 5 ? K - b : 0; j.off = 0;
+    j.task0 = bstart[b]; j.ntask = (int)by_b[b].size();
+    jl.push_back(j);
+  }
+  for (int guard = 0; guard < 256 && (int)jl.size() < 128; ++guard) {
+    double total = 0.0;
+    size_t imax = 0;
+    for (size_t i = 0; i < jl.size(); ++i) {
+      total += cost(jl[i]);
+      if (cost(jl[i]) > cost(jl[imax])) imax = i;
+    }
+    hdf::MfJob j = jl[imax];
+    if (cost(j) <= 1.05 * total / hdf::kMfWaves) break;
+    hdf::MfJob a2 = j, b2 = j;
+    if (d >= 5 && j.n_hi > j.n_lo) {
+      int64_t all = 0, acc = 0;
+      for (int n = j.n_lo; n <= j.n_hi; ++n) all += below(j.b, n);
+      int cut = j.n_lo;
+      while (cut < j.n_hi && 2 * (acc + below(j.b, cut)) <= all) acc += below(j.b, cut++);
+      if (cut == j.n_lo) acc += below(j.b, cut++);
+      a2.n_hi = cut - 1;
+      b2.n_lo = cut;
+      b2.off = j.off + (int32_t)acc;
+    } else if (j.ntask > 4) {
+      const int first = std::max(4, (j.ntask / 2 + 3) / 4 * 4);
+      if (first >= j.ntask) break;
+      a2.ntask = first;
+      b2.task0 = j.task0 + first;
+      b2.ntask = j.ntask - first;
+    } else {
+      break;
+    }
+    jl[imax] = a2;
+    jl.push_back(b2);
+  }
+  std::vector<std::pair<double, hdf::MfJob>> jc;
+  for (auto& j : jl) jc.push_back({cost(j), j});
+  std::stable_sort(jc.begin(), jc.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
   std::vector<std::vector<hdf::MfJob>> per(hdf::kMfWaves);
   std::vector<double> load(hdf::kMfWaves, 0.0);
-  for (const JobCost& jc : jl) {
+  for (auto& e : jc) {
     const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    per[w].push_back(jc.j);
-    load[w] += jc.cost;
+    per[w].push_back(e.second);
+    load[w] += e.first;
   }
   std::vector<hdf::MfJob> jobs;
   std::vector<int32_t> joff;
@@ -424,38 +475,74 @@ static bool mf_tables(hdf_factor* f, std::vector<char>& out) {
     jobs.insert(jobs.end(), per[w].begin(), per[w].end());
   }
   joff.push_back((int32_t)jobs.size());
-  // contraction slots
+  // contraction slots; their harmonics by loop-order row (rows past a degree's end: the zero pad row)
+  std::vector<int32_t> loop_row((size_t)f->H, -1);
+  for (size_t tt = 0; tt < col_of.size(); ++tt)
+    if (col_of[tt] >= 0) loop_row[(size_t)col_of[tt]] = (int32_t)tt;
+  for (int32_t v : loop_row)
+    if (v < 0) return false;
+  const int32_t zero_row = (int32_t)f->mf_nloop;
   std::vector<hdf::MfSlot1> s1;
   std::vector<hdf::MfSlot2> s2;
+  std::vector<int32_t> r1, r2;
   for (const hdf::DegDev& dg : f->degs) {
     for (int h0 = 0; h0 < dg.nh; h0 += 16)
       for (int l = 0; l < dg.s; ++l) {
         hdf::MfSlot1 x{};
-        x.row0 = dg.hoff + h0; x.qrow = dg.qoff + l; x.out0 = dg.roff + h0 * dg.s + l; x.s = dg.s;
+        x.row0 = (int32_t)r1.size(); x.qrow = dg.qoff + l; x.out0 = dg.roff + h0 * dg.s + l; x.s = dg.s;
         x.nr = std::min(16, dg.nh - h0);
+        for (int j = 0; j < 16; ++j) r1.push_back(j < x.nr ? loop_row[(size_t)(dg.hoff + h0 + j)] : zero_row);
+        r1.push_back(x.qrow);
         s1.push_back(x);
       }
     for (int h0 = 0; h0 < dg.nh; h0 += 4)
       for (int l = 0; l < dg.s; ++l) {
         hdf::MfSlot2 x{};
-        x.row0 = dg.hoff + h0; x.qrow = dg.qoff + l; x.rank0 = dg.roff + h0 * dg.s + l; x.s = dg.s;
+        x.row0 = (int32_t)r2.size(); x.qrow = dg.qoff + l; x.rank0 = dg.roff + h0 * dg.s + l; x.s = dg.s;
         x.nv = std::min(4, dg.nh - h0);
+        for (int j = 0; j < 4; ++j) r2.push_back(j < x.nv ? loop_row[(size_t)(dg.hoff + h0 + j)] : zero_row);
+        r2.push_back(x.qrow);
         s2.push_back(x);
       }
   }
-  auto groups = [](int64_t total, int per_wave, std::vector<int32_t>& off) {
-    const int64_t cap = (int64_t)hdf::kMfWaves * per_wave;
+  if ((int64_t)s1.size() != f->mf_t1 || (int64_t)s2.size() != f->mf_t2) return false;
+  // groups of kMfWaves wavefront lists; each list is padded to whole blocks with slots that add
+  // nothing (rows: the zero row; pass 1: out0 = -1; pass 2: nv = 0)
+  auto groups = [&](auto& slots, std::vector<int32_t>& rows, int stride, int per_wave, int block, auto pad_slot,
+                    std::vector<int32_t>& off) {
+    using S = typename std::decay<decltype(slots)>::type::value_type;
+    const int64_t total = (int64_t)slots.size();
+    const int64_t cap = (int64_t)hdf::kMfWaves * (per_wave - block + 1);   // room for the padding
     const int g = (int)std::max<int64_t>(1, (total + cap - 1) / cap);
+    std::vector<S> ps;
+    std::vector<int32_t> pr;
     off.clear();
     for (int gi = 0; gi < g; ++gi) {
       const int64_t lo = total * gi / g, hi = total * (gi + 1) / g;
-      for (int w = 0; w <= hdf::kMfWaves; ++w) off.push_back((int32_t)(lo + (hi - lo) * w / hdf::kMfWaves));
+      for (int w = 0; w < hdf::kMfWaves; ++w) {
+        off.push_back((int32_t)ps.size());
+        const int64_t a = lo + (hi - lo) * w / hdf::kMfWaves, b = lo + (hi - lo) * (w + 1) / hdf::kMfWaves;
+        for (int64_t i = a; i < b; ++i) {
+          ps.push_back(slots[(size_t)i]);
+          pr.insert(pr.end(), rows.begin() + i * stride, rows.begin() + (i + 1) * stride);
+        }
+        while ((ps.size() - (size_t)off.back()) % (size_t)block) {
+          ps.push_back(pad_slot());
+          for (int e = 0; e < stride; ++e) pr.push_back(e + 1 < stride ? zero_row : 0);
+        }
+      }
+      off.push_back((int32_t)ps.size());
     }
+    slots.swap(ps);
+    rows.swap(pr);
     return g;
   };
   std::vector<int32_t> so1, so2;
-  f->mf_g1 = groups((int64_t)s1.size(), hdf::kMfSlots1, so1);
-  f->mf_g2 = groups((int64_t)s2.size(), hdf::kMfSlots2, so2);
+  f->mf_g1 = groups(s1, r1, 17, hdf::kMfSlots1, hdf::kMfBlock1, [] { hdf::MfSlot1 x{}; x.out0 = -1; return x; }, so1);
+  f->mf_g2 = groups(s2, r2, 5, hdf::kMfSlots2, hdf::kMfBlock2, [] { hdf::MfSlot2 x{}; x.nv = 0; return x; }, so2);
+  if ((int64_t)r1.size() > f->mf_nr1 || (int64_t)r2.size() > f->mf_nr2) return false;   // the LDS layout's room
+  f->mf_nr1 = (int)r1.size();
+  f->mf_nr2 = (int)r2.size();
   auto put = [&](const void* p, size_t bytes) {
     const size_t at = (out.size() + 255) / 256 * 256;
     out.resize(at + bytes);
@@ -469,6 +556,26 @@ static bool mf_tables(hdf_factor* f, std::vector<char>& out) {
   f->mf_o_so1 = put(so1.data(), so1.size() * 4);
   f->mf_o_s2 = put(s2.data(), s2.size() * sizeof(hdf::MfSlot2));
   f->mf_o_so2 = put(so2.data(), so2.size() * 4);
+  f->mf_o_r1 = put(r1.data(), r1.size() * 4);
+  f->mf_o_r2 = put(r2.data(), r2.size() * 4);
+  f->mf_o_bt = put(btab.data(), btab.size() * 4);
+  {
+    // radial coefficient matrix S_pad x L_pad in the factor's type
+    std::vector<double> qm((size_t)f->mf_spad * f->mf_lpad, 0.0);
+    int row = 0;
+    for (size_t di = 0; di < f->kept_k.size(); ++di) {
+      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
+      for (int l = 0; l < df.s; ++l, ++row)
+        for (int aa = 0; aa < df.L; ++aa) qm[(size_t)row * f->mf_lpad + aa] = df.E[(size_t)l * df.L + aa];
+    }
+    if (f->fprec == 1) {
+      std::vector<float> qf(qm.begin(), qm.end());
+      f->mf_o_qm = put(qf.data(), qf.size() * 4);
+    } else {
+      f->mf_o_qm = put(qm.data(), qm.size() * 8);
+    }
+  }
+  f->mf_ntasks = id;
   return true;
 }
 
@@ -517,13 +624,41 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     const int Kh = f->kept_k.back();
     f->mf_nloop = 0;
     for (int k = 0; k <= Kh; ++k) f->mf_nloop += hdf::index_count(d, k);
-    f->mf_lay1 = hdf::mf_layout(f->H, (int)f->S, f->mf_nloop, d, Kh, f->fprec, 1);
-    f->mf_lay2 = hdf::mf_layout(f->H, (int)f->S, f->mf_nloop, d, Kh, f->fprec, 2);
+    int64_t t1 = 0, t2 = 0;
+    for (const hdf::DegDev& dg : f->degs) {
+      t1 += (int64_t)((dg.nh + 15) / 16) * dg.s;
+      t2 += (int64_t)((dg.nh + 3) / 4) * dg.s;
+    }
+    // row-table entries, with room for the padding of every wavefront list to whole blocks
+    auto padded = [](int64_t t, int per_wave, int block) {
+      const int64_t cap = (int64_t)hdf::kMfWaves * (per_wave - block + 1);
+      const int64_t g = std::max<int64_t>(1, (t + cap - 1) / cap);
+      return t + g * hdf::kMfWaves * (block - 1);
+    };
+    f->mf_nr1 = (int)(17 * padded(t1, hdf::kMfSlots1, hdf::kMfBlock1));
+    f->mf_nr2 = (int)(5 * padded(t2, hdf::kMfSlots2, hdf::kMfBlock2));
+    f->mf_t1 = t1;
+    f->mf_t2 = t2;
+    int lmax = 1;
+    for (size_t di = 0; di < f->kept_k.size(); ++di) lmax = std::max(lmax, f->deg[f->kept_k[di]].L);
+    f->mf_spad = (int)((f->S + 15) / 16 * 16);
+    f->mf_lpad = (lmax + 3) / 4 * 4;
+    f->mf_nqc = (int64_t)f->mf_spad * f->mf_lpad;
+    const int64_t ntasks = d == 3 ? 2 * Kh + 1 : (int64_t)(Kh + 1) * (Kh + 1);
+    auto lays = [&](bool spec) {
+      f->mf_lay1 = hdf::mf_layout(f->mf_nloop, (int)f->S, f->mf_nr1, f->mf_nqc, ntasks, d, Kh, f->fprec, 1, spec);
+      f->mf_lay2 = hdf::mf_layout(f->mf_nloop, (int)f->S, f->mf_nr2, f->mf_nqc, ntasks, d, Kh, f->fprec, 2, spec);
+    };
     int dev = 0, max_lds = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     HIPCHK(hipDeviceGetAttribute(&f->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    f->mf_fused = std::max(f->mf_lay1.total, f->mf_lay2.total) <= max_lds;
+    // the wavefront-specialised kernels (binary32) when their double buffers fit, else the plain ones
+    lays(true);
+    f->mf_spec = f->fprec == 1 && std::max(f->mf_lay1.total, f->mf_lay2.total) <= max_lds;
+    if (!f->mf_spec) lays(false);
+    f->mf_fused = std::max(f->mf_lay1.total, f->mf_lay2.total) <= max_lds && f->mf_nloop < 65535 &&
+                  f->mf_lpad <= 4 * hdf::kMfMaxKs;
   }
   const size_t fbytes = f->mf_fused ? 0
                         : (size_t)(f->H + f->S) * (mfree ? f->ldC : f->ldN + (f->cross ? f->ldN2 : 0)) * f->felem();
@@ -645,7 +780,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     if (mfree) {                                // evaluated in every product
       if (f->mf_fused) {
         std::vector<char> tabs;
-        if (!mf_tables(f, tabs)) return fail(HDF_E_ARG, "internal: loop-order count of the fused tables");
+        if (!mf_tables(f, col_of, tabs)) return fail(HDF_E_ARG, "internal: inconsistent fused-pass tables");
         HIPCHK(upload(f->mf_tabs, tabs.data(), tabs.size()));
       }
       return HDF_OK;
@@ -1223,17 +1358,18 @@ static hdf::MfArgs mf_args(hdf_handle h) {
   a.x_soa = h->x_soa.p; a.ldx = h->ldN; a.n = h->N; a.dtype = h->dtype; a.d = h->d;
   a.geo = (const hdf::GeoDev*)h->geo_dev.p; a.u0 = h->u0; a.u1 = h->u1;
   a.jobs = (const hdf::MfJob*)base; a.job_off = (const int32_t*)(base + h->mf_o_joff);
-  a.col_of = (const int32_t*)h->col_of.p; a.n_loop = h->mf_nloop;
+  a.btab = (const int32_t*)(base + h->mf_o_bt); a.n_tasks = h->mf_ntasks;
+  a.n_loop = h->mf_nloop;
   a.chain = h->chain.p; a.K = h->tables.K;
-  a.q_len = (const int32_t*)h->q_len.p; a.q_off = (const int32_t*)h->q_off.p; a.q_coef = h->q_coef.p;
-  a.S = (int)h->S; a.H = h->H; a.prec = h->fprec;
+  a.qmat = base + h->mf_o_qm; a.S = (int)h->S; a.S_pad = h->mf_spad; a.L_pad = h->mf_lpad;
+  a.H = h->H; a.prec = h->fprec;
   return a;
 }
 
 // Workgroups of one fused pass that run at once on the device (occupancy x CUs), queried once.
 static int mf_resident(hdf_handle h, int pass) {
   int& nb = pass == 1 ? h->mf_nb1 : h->mf_nb2;
-  if (!nb) nb = hdf::mf_blocks_per_cu(mf_args(h), pass, pass == 1 ? h->mf_lay1 : h->mf_lay2);
+  if (!nb) nb = hdf::mf_blocks_per_cu(mf_args(h), pass, pass == 1 ? h->mf_lay1 : h->mf_lay2, h->mf_spec);
   return std::max(1, nb) * std::max(1, h->n_cu);
 }
 
@@ -1259,9 +1395,9 @@ static hdf_status pass1_fused(hdf_handle h, const void* V, int64_t m, int64_t ld
     HIPCHK(hipEventRecord(h->ev_mv[0], s));
   }
   const char* base = (const char*)h->mf_tabs.p;
-  HIPCHK(hdf::launch_mf_t(mf_args(h), h->mf_lay1, (const hdf::MfSlot1*)(base + h->mf_o_s1),
-                          (const int32_t*)(base + h->mf_o_so1), h->mf_g1, cpl, n_splits, len, V, ldv, (int)m, m16,
-                          h->r, (double*)h->ws_part.p, s));
+  HIPCHK(hdf::launch_mf_t(mf_args(h), h->mf_lay1, h->mf_spec, (const hdf::MfSlot1*)(base + h->mf_o_s1),
+                          (const int32_t*)(base + h->mf_o_so1), (const int32_t*)(base + h->mf_o_r1), h->mf_nr1,
+                          h->mf_g1, cpl, n_splits, len, V, ldv, (int)m, m16, h->r, (double*)h->ws_part.p, s));
   if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
   HIPCHK(hdf::launch_matvec_reduce((const double*)h->ws_part.p, n_splits, h->r, m16, (const double*)h->lam_row.p,
                                    (double*)W.p, Wd.p, h->fprec, s));
@@ -1280,9 +1416,10 @@ static hdf_status pass2_fused(hdf_handle h, int64_t m, int m16, void* KV, int64_
   const int n_ranges = (int)((n + len - 1) / len);
   if (h->mf_g2 > 1) HIPCHK(h->ws_n.ensure((size_t)h->mf_g2 * n * m * h->felem()));
   const char* base = (const char*)h->mf_tabs.p;
-  HIPCHK(hdf::launch_mf_n(mf_args(h), h->mf_lay2, (const hdf::MfSlot2*)(base + h->mf_o_s2),
-                          (const int32_t*)(base + h->mf_o_so2), h->mf_g2, cpl, n_ranges, len, h->ws_Wd.p, m16, KV,
-                          ldkv, (int)m, h->mf_g2 > 1 ? h->ws_n.p : nullptr, s));
+  HIPCHK(hdf::launch_mf_n(mf_args(h), h->mf_lay2, h->mf_spec, (const hdf::MfSlot2*)(base + h->mf_o_s2),
+                          (const int32_t*)(base + h->mf_o_so2), (const int32_t*)(base + h->mf_o_r2), h->mf_nr2,
+                          h->mf_g2, cpl, n_ranges, len, h->ws_Wd.p, m16, KV, ldkv, (int)m,
+                          h->mf_g2 > 1 ? h->ws_n.p : nullptr, s));
   return HDF_OK;
 }
 
@@ -1780,7 +1917,7 @@ hdf_status hdf_info(hdf_handle h, hdf_info_t* info) {
                        : (int64_t)((h->H + h->S) *
                                    (h->storage == HDF_STORE_NONE ? h->ldC : h->ldN + (h->cross ? h->ldN2 : 0)) *
                                    h->felem());
-  info->mf_fused = h->mf_fused ? 1 : 0;
+  info->mf_fused = h->mf_fused ? (h->mf_spec ? 2 : 1) : 0;
   info->storage = h->storage;
   info->factor_precision = h->fprec == 1 ? HDF_MIXED : HDF_FP64;
   info->chunk_points = h->storage == HDF_STORE_NONE ? h->chunk : 0;

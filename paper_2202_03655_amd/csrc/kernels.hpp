@@ -165,61 +165,76 @@ hipError_t launch_adj_combine(const void* x_soa, int dtype, int64_t ldx, int64_t
 // factor value reaches HBM.
 constexpr int kMfP = 16;                 // points per chunk
 constexpr int kMfWaves = 8;              // wavefronts per workgroup
-// One evaluation step of a wavefront: up to four subtrees of the harmonic
-// recursion with the same shape, one per 16-lane group (lane = point).  A
-// subtree fixes the azimuthal index and, for d >= 4, the index of chain level
-// d - 2; it runs the levels below.
+// One evaluation job of a wavefront.  A subtree of the harmonic recursion
+// fixes the azimuthal index m (cosine or sine branch) and, for d >= 4, the
+// index of chain level d - 2; its base b is their sum.  Subtrees of one base
+// share every value below their prefixes, so a job runs the shared levels of
+// base b once per point (lane = point) and writes the harmonics of a list of
+// its subtrees (16-lane group g takes every fourth).  For d >= 5 a job covers
+// the level d - 3 indices [n_lo, n_hi] only.
 struct MfJob {
-  int32_t rem;      // K - b: the subtree's top loop runs rem + 1 times (same for the four)
-  int32_t ntask;    // subtrees in use, 1..4
+  int32_t b;        // base
+  int32_t n_lo, n_hi;
+  int32_t off;      // loop-order offset of the job's first harmonic within each of its subtrees
+  int32_t task0;    // first entry of the job's subtrees in the per-base list (btab)
+  int32_t ntask;    // subtrees of the job
   int32_t pad[2];
-  int32_t mm[4];    // signed azimuthal index: m >= 0 the cosine branch, -m the sine branch
-  int32_t ntop[4];  // index at chain level d - 2 (d >= 4; 0 for d = 3)
-  int32_t t0[4];    // loop-order index of the subtree's first harmonic
 };
-// Pass 1: one accumulator tile of a wavefront, 16 harmonic rows of one degree with one radial
-// function: rank rows out0 + j s for j < nr.
+// Pass 1: one accumulator tile of a wavefront, 16 harmonics of one degree with one radial function
+// (slot i: loop-order rows rows[17 i .. 17 i + 15], radial row rows[17 i + 16]): rank rows
+// out0 + j s for j < nr.
 struct MfSlot1 {
   int32_t row0, qrow, out0, s, nr;
   int32_t pad[3];
 };
-// Pass 2: one MFMA step of a wavefront, harmonic rows row0 + j (j < nv <= 4) of one degree with one
-// radial function: rank rows rank0 + j s.
+// Pass 2: one MFMA step of a wavefront, harmonics j < nv <= 4 of one degree with one radial function
+// (slot i: loop-order rows rows[5 i .. 5 i + 3], radial row rows[5 i + 4]): rank rows rank0 + j s.
 struct MfSlot2 {
   int32_t row0, qrow, rank0, s, nv;
   int32_t pad[3];
 };
-// LDS layout (byte offsets) of a fused pass: harmonic rows (H + 16 x kMfP, the last 16 rows zero),
-// radial rows, V^T of the chunk (pass 1) or the per-wavefront partial products (pass 2), the
-// loop-order row table and the recurrence pairs.
+// LDS layout (byte offsets) of a fused pass: harmonic rows in loop order ((n_loop + 1) x kMfP,
+// the last row zero), radial rows, V^T of the chunk (pass 1) or the per-wavefront partial
+// products (pass 2), the slots' row table (n_rows 16-bit indices), the radial coefficients, the
+// level d-2 recurrence pairs, two buffers of subtree prefixes (n_tasks x kMfP each) and the
+// per-base subtree list.
 struct MfLayout {
-  int32_t phc, qc, aux, cmap, chain, total;
+  int32_t phc, qc, aux, rtab, qcoef, ctop, ptab, ptab_len, btab, total;
+  int32_t phc_len, qc_len, aux_len;   // values per buffer of the chunk data (two buffers when spec)
 };
-MfLayout mf_layout(int64_t H, int S, int64_t n_loop, int d, int K, int prec, int pass);
+// spec: the wavefront-specialised kernels (2 kMfWaves wavefronts, the chunk data double-buffered)
+MfLayout mf_layout(int64_t n_loop, int S, int64_t n_rows, int64_t n_qcoef, int64_t n_tasks, int d, int K, int prec,
+                   int pass, bool spec);
 constexpr int kMfSlots1 = 16;            // pass-1 accumulator tiles per wavefront
 constexpr int kMfSlots2 = 64;            // pass-2 steps per wavefront (their D W operands stay in registers)
+// A wavefront's slot list is padded to whole blocks (pass 1: padding slots have out0 = -1; pass 2:
+// nv = 0) so that the kernels test the list length once per block.
+constexpr int kMfBlock1 = 4;
+constexpr int kMfBlock2 = 8;
+constexpr int kMfMaxKs = 8;              // radial coefficients per row <= 4 kMfMaxKs (p / 2 + 1 <= 31)
 struct MfArgs {
   const void* x_soa; int64_t ldx; int64_t n; int dtype; int d;
   const GeoDev* geo; double u0, u1;
   const MfJob* jobs; const int32_t* job_off;          // jobs of wavefront w: [job_off[w], job_off[w + 1])
-  const int32_t* col_of; int64_t n_loop;
-  const void* chain; int K;
-  const int32_t* q_len; const int32_t* q_off; const void* q_coef; int S; int64_t H;
+  const int32_t* btab; int n_tasks;                   // subtrees by base: (subtree index, first harmonic)
+  int64_t n_loop;                                     // harmonics of the recursion (degrees <= K)
+  const void* chain; int K;                           // recurrence pairs, as for the factor evaluation
+  const void* qmat; int S, S_pad, L_pad; int64_t H;   // radial coefficients, S_pad x L_pad (factor type)
   int prec;                                           // factor type: 1 binary32, 0 binary64
 };
 // Workgroups of one fused pass that fit on a CU at once (occupancy of the kernel with its LDS).
-int mf_blocks_per_cu(const MfArgs& a, int pass, const MfLayout& lay);
+int mf_blocks_per_cu(const MfArgs& a, int pass, const MfLayout& lay, bool spec);
 // Pass 1: partial[split][row][c] for splits of split_len points (a multiple of kMfP), rank rows of
 // slot group g (slots of wavefront w: [slot_off[9 g + w], slot_off[9 g + w + 1])), columns of tile ct;
-// grid n_splits x (n_groups cpl).
-hipError_t launch_mf_t(const MfArgs& a, const MfLayout& lay, const MfSlot1* slots, const int32_t* slot_off,
-                       int n_groups, int cpl, int n_splits, int64_t split_len, const void* V, int64_t ldv, int m,
-                       int m16, int64_t rank, double* partials, hipStream_t s);
+// grid n_splits x (n_groups cpl).  rows: the slots' loop-order rows (n_rows entries).
+hipError_t launch_mf_t(const MfArgs& a, const MfLayout& lay, bool spec, const MfSlot1* slots, const int32_t* slot_off,
+                       const int32_t* rows, int n_rows, int n_groups, int cpl, int n_splits, int64_t split_len,
+                       const void* V, int64_t ldv, int m, int m16, int64_t rank, double* partials, hipStream_t s);
 // Pass 2: KV = U Wd over ranges of range_len points; with n_groups > 1 each slot group writes its
 // share to part (n_groups x n x m, factor type), summed in group order into KV.
-hipError_t launch_mf_n(const MfArgs& a, const MfLayout& lay, const MfSlot2* slots, const int32_t* slot_off,
-                       int n_groups, int cpl, int n_ranges, int64_t range_len, const void* Wd, int m16, void* KV,
-                       int64_t ldkv, int m, void* part, hipStream_t s);
+hipError_t launch_mf_n(const MfArgs& a, const MfLayout& lay, bool spec, const MfSlot2* slots, const int32_t* slot_off,
+                       const int32_t* rows, int n_rows, int n_groups, int cpl, int n_ranges, int64_t range_len,
+                       const void* Wd, int m16, void* KV, int64_t ldkv, int m, void* part, hipStream_t s);
 
 // Scratch of hdf_matvec_noalloc: a fixed device array per GPU (scratch.hip).
 // scratch_address returns its device address on the current device (resolved

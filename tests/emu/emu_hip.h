@@ -82,6 +82,7 @@ extern Fiber* cur;
 extern dim3 g_blockIdx, g_blockDim, g_gridDim;
 const dim3& tidx();
 void syncthreads();
+void syncthreads_at(const void* site);   // a barrier whose call sites count as one (see mf_kernels.hip)
 unsigned char* dyn_smem();
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));

@@ -130,6 +130,14 @@ __attribute__((noinline)) void syncthreads() {
   to_main();
 }
 
+// A barrier reached from different call sites that the kernel declares to be one barrier (the two
+// roles of a wavefront-specialised kernel): the site is the given tag; counts must still agree.
+void syncthreads_at(const void* site) {
+  cur->site = site;
+  cur->state = BARRIER;
+  to_main();
+}
+
 // __syncthreads_count: a barrier that also counts the threads with p != 0
 static int g_count_acc = 0;
 int syncthreads_count(int p) {

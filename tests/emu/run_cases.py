@@ -227,7 +227,7 @@ def case_mfree():
         tag = "fused" if fused else "chunked"
         fm = hdf.Factor(Xd, "gaussian", 1.0, 1e-6, precision=hdf.HDF_FP64, storage="none", chunk=1000, fused=fused)
         inf = fm.info()
-        check(f"mfree {tag} info", inf["storage"] == 1 and inf["mf_fused"] == int(fused) and inf["rank"] == st["r"]
+        check(f"mfree {tag} info", inf["storage"] == 1 and bool(inf["mf_fused"]) == fused and inf["rank"] == st["r"]
               and (inf["factor_bytes"] == 0) == fused,
               f"storage {inf['storage']} fused {inf['mf_fused']} rank {inf['rank']} bytes {inf['factor_bytes']}")
         for m in (1, 17, 70):
@@ -246,6 +246,24 @@ def case_mfree():
     V = wl.rhs(1013, 5, 82).astype(np.float32)
     e = rel(fm32.matvec(to_dev(V, torch.float32)).numpy(), fs32.matvec(to_dev(V, torch.float32)).numpy())
     check("mfree chunked mixed vs stored", e <= 1e-6, f"{e:.2e}")
+    # binary32 factors small enough for the double-buffered kernels (d = 3 and d = 5)
+    for dd, n, l, tol in ((3, 2345, 1.0, 1e-5), (5, 1501, 3.0, 1e-4)):
+        Xs = wl.unit_ball(n, dd, 400 + dd).astype(np.float32)
+        sts = ohdf.build(Xs.astype(np.float64), "gaussian", l, tol)
+        fs_ = hdf.Factor(to_dev(Xs, torch.float32), "gaussian", l, tol, precision=hdf.HDF_MIXED, storage="none")
+        ss_ = hdf.Factor(to_dev(Xs, torch.float32), "gaussian", l, tol, precision=hdf.HDF_MIXED)
+        for m in (2, 17):
+            V = wl.rhs(n, m, 95 + dd + m).astype(np.float32)
+            km = fs_.matvec(to_dev(V, torch.float32)).numpy().astype(np.float64)
+            e1 = rel(km, ohdf.matvec(sts, V.astype(np.float64)))
+            e2 = rel(km, ss_.matvec(to_dev(V, torch.float32)).numpy())
+            check(f"mfree fused double-buffered d={dd} m={m} binary32", fs_.info()["mf_fused"] == 2 and e1 <= tol
+                  and e2 <= 1e-6, f"vs oracle {e1:.2e} (tol {tol:g}), vs stored {e2:.2e}, mode {fs_.info()['mf_fused']}")
+        W = wl.rhs(n, 2, 97).astype(np.float32)
+        V = wl.rhs(n, 2, 98).astype(np.float32)
+        dlm, _ = fs_.backward(to_dev(W, torch.float32), to_dev(V, torch.float32), need_x=False)
+        dls, _ = ss_.backward(to_dev(W, torch.float32), to_dev(V, torch.float32), need_x=False)
+        check(f"mfree fused double-buffered d={dd} dF/dl", abs(dlm - dls) <= 1e-5 * abs(dls), f"{dlm:.7e} vs {dls:.7e}")
     # d = 5, binary32 factor, fused
     X5 = wl.max_norm_one(wl.gaussian_mixture(1501, 5, 103)).astype(np.float32)
     X5d = to_dev(X5, torch.float32)
@@ -269,6 +287,16 @@ def case_mfree():
     i6 = f6.info()
     check("mfree fused binary64 factor", i6["mf_fused"] == 1 and i6["factor_precision"] == 0 and e1 <= 1e-7,
           f"vs oracle {e1:.2e} (tol 1e-7), fused {i6['mf_fused']}, factor precision {i6['factor_precision']}")
+    # d = 4, 6, 7, 8 (two or more shared levels below a subtree's prefix for d >= 6), binary64
+    for dd, n, l, tol in ((4, 1201, 0.9, 1e-6), (6, 700, 2.0, 1e-5), (7, 500, 2.5, 1e-4), (8, 400, 3.0, 1e-4)):
+        Xd_ = wl.unit_ball(n, dd, 300 + dd)
+        st_ = ohdf.build(Xd_, "gaussian", l, tol)
+        f_ = hdf.Factor(to_dev(Xd_, torch.float64), "gaussian", l, tol, precision=hdf.HDF_FP64, storage="none")
+        V = wl.rhs(n, 3, 90 + dd)
+        e1 = rel(f_.matvec(to_dev(V, torch.float64)).numpy(), ohdf.matvec(st_, V))
+        inf_ = f_.info()
+        check(f"mfree fused d={dd} binary64", inf_["mf_fused"] == 1 and inf_["rank"] == st_["r"] and e1 <= 1e-12,
+              f"vs oracle {e1:.2e}, p {inf_['degree_p']}, H {inf_['n_harmonics']}, fused {inf_['mf_fused']}")
 
 
 def case_krr():

@@ -13,9 +13,8 @@ namespace emu {
 template <> struct StructCheck<hdf::MfArgs> {
   static void run(const char* k, int i, const hdf::MfArgs& a) {
     check_ptr(k, "a.x_soa", i, a.x_soa); check_ptr(k, "a.geo", i, a.geo); check_ptr(k, "a.jobs", i, a.jobs);
-    check_ptr(k, "a.job_off", i, a.job_off); check_ptr(k, "a.col_of", i, a.col_of);
-    check_ptr(k, "a.chain", i, a.chain); check_ptr(k, "a.q_len", i, a.q_len);
-    check_ptr(k, "a.q_off", i, a.q_off); check_ptr(k, "a.q_coef", i, a.q_coef);
+    check_ptr(k, "a.job_off", i, a.job_off); check_ptr(k, "a.btab", i, a.btab); check_ptr(k, "a.chain", i, a.chain);
+    check_ptr(k, "a.qmat", i, a.qmat);
   }
 };
 template <> struct StructCheck<hdf::BuildTables> {
