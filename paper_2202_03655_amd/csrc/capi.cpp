@@ -330,26 +330,63 @@ static hipError_t clear_padding(void* base, int64_t rows, int64_t n, int64_t ld,
 
 // Wave items of the tile-major pass 1 for cpl = m16 / 16 (1..4): one per 16 harmonics of a kept
 // degree and range of its radial functions (nl * nct accumulator tiles at most), then groups of up
-// to kMvtWavesPerGroup consecutive items whose radial rows span at most kMvtMaxNq rows.
+// to kMvtWavesPerGroup items whose radial rows span at most kMvtMaxNq rows.
+//
+// Every item loads the same bytes (its 16 rows of the harmonics) while its MFMA work grows with its
+// radial functions, and the low degrees have the most of them.  The waves of a group synchronise
+// once per chunk and waves w and w + 4 share a SIMD, so the busiest SIMD of a group sets the pace
+// of its chunk loop.  When all radial rows fit one group's staging, the items are therefore placed
+// by hdf::place_wave_items (for one column tile, after cutting them to at most kMvtSplitAcc radial
+// functions) so that the waves of each SIMD and the groups carry about equal numbers of tiles.
+// Otherwise the groups are runs of consecutive items.
+constexpr int kMvtSplitAcc = 3;
 static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl, std::vector<hdf::MvtWave>& tw,
                         std::vector<hdf::MvtGroup>& tg) {
   const int nct_t = cpl == 1 ? 1 : (cpl == 2 ? 2 : 4);
   const int nlmax = hdf::matvec_tile_acc(fprec) / nct_t;
+  int q_min = 1 << 30, q_max = 0;
+  for (const hdf::DegDev& dg : degs)
+    if (dg.nh > 0 && dg.s > 0) {
+      q_min = std::min(q_min, dg.qoff);
+      q_max = std::max(q_max, dg.qoff + dg.s);
+    }
+  const bool spread = q_max - q_min <= hdf::kMvtMaxNq;
+  const int nl_cap = spread && nct_t == 1 ? std::min(nlmax, kMvtSplitAcc) : nlmax;
   const int w_base = (int)tw.size();
   for (const hdf::DegDev& dg : degs)
     for (int h0 = 0; h0 < dg.nh; h0 += 16)
-      for (int l0 = 0; l0 < dg.s; l0 += nlmax) {
+      for (int l0 = 0; l0 < dg.s; l0 += nl_cap) {
         hdf::MvtWave w{};
         w.row0 = dg.hoff + h0;
         w.nr = std::min(16, dg.nh - h0);
         w.qrow = dg.qoff + l0;
-        w.nl = std::min(nlmax, dg.s - l0);
+        w.nl = std::min(nl_cap, dg.s - l0);
         w.ct0 = 0;
         w.nct = cpl;
         w.out0 = dg.roff + h0 * dg.s + l0;
         w.s = dg.s;
         tw.push_back(w);
       }
+  const int n_items = (int)tw.size() - w_base;
+  std::vector<int> loads(n_items), order, nw;
+  for (int i = 0; i < n_items; ++i) loads[i] = tw[w_base + i].nl * nct_t;
+  if (spread && n_items > hdf::kMvtWavesPerGroup &&
+      hdf::place_wave_items(loads, hdf::kMvtWavesPerGroup, 4, order, nw)) {
+    std::vector<hdf::MvtWave> placed;
+    for (int i : order) placed.push_back(tw[w_base + i]);
+    std::copy(placed.begin(), placed.end(), tw.begin() + w_base);
+    int w0 = 0;
+    for (int g : nw) {
+      hdf::MvtGroup gr{};
+      gr.w0 = w0;
+      gr.nw = g;
+      gr.q_lo = q_min;
+      gr.nq = q_max - q_min;
+      tg.push_back(gr);
+      w0 += g;
+    }
+    return;
+  }
   for (size_t i = (size_t)w_base; i < tw.size();) {
     hdf::MvtGroup gr{};
     gr.w0 = (int32_t)(i - (size_t)w_base);
@@ -1272,10 +1309,10 @@ static const hdf::MvtGroup* tile_groups(hdf_handle h, int cpl) {
   return (const hdf::MvtGroup*)((const char*)h->tile_tabs.p + h->tg_base) + h->tg_off[cpl];
 }
 
-// Splits of the tile-major pass 1 over n points: about 2048 workgroups (of G groups each), splits
-// a multiple of 128 points, partial records capped at about 96 MB.
+// Splits of the tile-major pass 1 over n points: about 1024 workgroups (of G groups each; two run
+// at once on a CU), splits a multiple of 128 points, partial records capped at about 96 MB.
 static void tile_splits(int64_t n, int n_groups, size_t per_split, int* n_splits, int64_t* split_len) {
-  int64_t ns = std::max<int64_t>(1, 2048 / std::max(1, n_groups));
+  int64_t ns = std::max<int64_t>(1, 1024 / std::max(1, n_groups));
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)(96e6 / (double)per_split)));
   ns = std::min<int64_t>(ns, (n + 127) / 128);
   ns = std::max<int64_t>(ns, 1);

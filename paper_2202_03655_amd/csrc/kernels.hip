@@ -1226,8 +1226,8 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
       }
     }
   };
-  // staging of a chunk by all threads (TPB of them): V entries e = tid + TPB j (point e / m16,
-  // column e % m16; 32 m16 / TPB per thread) and the group's radial entries e = tid + TPB j (row
+  // staging of a chunk by all threads (TPB of them): V entries e = tid + TPB j < 32 m16 (point
+  // e / m16, column e % m16) and the group's radial entries e = tid + TPB j (row
   // e / 32, point e % 32; rows past nq repeat the last one and are never read).  The loads are
   // unconditional and in bounds and keep the raw values; the masks (points past the split,
   // columns past m) and the choice of slot are applied when the values are written to LDS, so the
@@ -1235,7 +1235,7 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   // makes it wait for every load in flight).
   constexpr int TPB = kMvtThreads;
   constexpr int SV = (CH * 16 * NCT + TPB - 1) / TPB, SQ = CH * kMvtMaxNq / TPB;
-  const int sv_n = CH * m16 / TPB;
+  const int sv_n = CH * m16;                         // staged V entries per chunk
   // staged values are loaded with the same look-ahead as the tile (PF chunks, rotating register
   // slots): the load counter completes in issue order, so values loaded after the tile prefetch
   // could only be waited for together with it
@@ -1266,7 +1266,7 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
       const int e = tid + TPB * j;
       const int pp = e / m16, c = e - pp * m16;
       const bool ok = p + pp < p_end && c < m;
-      const int at = j < sv_n ? c * VS + pp : (m16 + kMvtMaxNq) * VS + (tid & 31);
+      const int at = e < sv_n ? c * VS + pp : (m16 + kMvtMaxNq) * VS + (tid & 31);
       buf[at] = ok ? (T)sv[j] : (T)0;
     }
 #pragma unroll

@@ -1165,4 +1165,51 @@ double tune_threshold(int kind, double l, int d, double N, double u0, double u1,
   if (err) *err = e;
   return tau;
 }
+
+bool place_wave_items(const std::vector<int>& loads, int wg, int ns, std::vector<int>& order,
+                      std::vector<int>& nw) {
+  const int n = (int)loads.size();
+  if (n < 1 || wg < 1 || ns < 1 || wg % ns) return false;
+  for (int v : loads)
+    if (v < 1) return false;
+  const int G = (n + wg - 1) / wg;
+  nw.assign(G, wg);
+  for (int miss = wg * G - n, g = G - 1; miss > 0; --miss) {
+    --nw[g];
+    g = g == 0 ? G - 1 : g - 1;
+  }
+  // bin (g, sm): the waves sm, sm + ns, ... < nw[g] of group g
+  std::vector<int> cap(G * ns), bin_load(G * ns, 0), grp_load(G, 0);
+  for (int g = 0; g < G; ++g)
+    for (int sm = 0; sm < ns; ++sm) cap[g * ns + sm] = sm < nw[g] ? (nw[g] - sm + ns - 1) / ns : 0;
+  std::vector<int> by_load(n);
+  for (int i = 0; i < n; ++i) by_load[i] = i;
+  std::stable_sort(by_load.begin(), by_load.end(), [&](int a, int b) { return loads[a] > loads[b]; });
+  std::vector<std::vector<int>> bin(G * ns);
+  for (int i : by_load) {
+    int best = -1;
+    for (int bi = 0; bi < G * ns; ++bi) {
+      if ((int)bin[bi].size() >= cap[bi]) continue;
+      if (best < 0 || bin_load[bi] < bin_load[best] ||
+          (bin_load[bi] == bin_load[best] && grp_load[bi / ns] < grp_load[best / ns]))
+        best = bi;
+    }
+    if (best < 0) return false;
+    bin[best].push_back(i);
+    bin_load[best] += loads[i];
+    grp_load[best / ns] += loads[i];
+  }
+  order.clear();
+  std::vector<char> seen(n, 0);
+  for (int g = 0; g < G; ++g)
+    for (int w = 0; w < nw[g]; ++w) {
+      const std::vector<int>& b = bin[g * ns + w % ns];
+      const size_t j = (size_t)(w / ns);
+      if (j >= b.size() || seen[b[j]]) return false;
+      seen[b[j]] = 1;
+      order.push_back(b[j]);
+    }
+  return (int)order.size() == n;
+}
+
 }  // namespace hdf

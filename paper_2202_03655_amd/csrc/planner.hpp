@@ -92,6 +92,14 @@ void compress_degree_cross(int k, int L, const SqrtFactor& fx, const SqrtFactor&
 
 // The kernel-matrix threshold tau of the Frobenius-form error budget; N is
 // the side of the kernel matrix (sqrt(N_x N_y) for a rectangular one).
+// Placement of work items of unequal weight (loads[i] > 0) into workgroups of at most wg
+// waves, wave w of a workgroup running on SIMD w % ns: ceil(n / wg) groups, the wg G - n missing
+// waves taken one per group from the last groups first, and the items, heaviest first, each given
+// to the SIMD of a group with a free wave and the smallest load so far (then the group with the
+// smallest load).  order receives the items wave by wave, groups after one another; nw the waves
+// of each group.  Returns false (outputs unspecified) if the inputs admit no placement.
+bool place_wave_items(const std::vector<int>& loads, int wg, int ns, std::vector<int>& order,
+                      std::vector<int>& nw);
 double tau_threshold(double tol, double nu, double N, int d, int p);
 
 // Tighter degree and rank selection (remark after Eq. bound).  The relative
