@@ -227,10 +227,12 @@ struct hdf_factor {
       lam_row, moments;
   int n_tiles = 0, tiles_cpl = 0;                 // pass-1 work items for cpl = m16/16
   // tile-major pass 1 (m16 <= 64): wave items and their workgroup groups for each cpl = m16 / 16
-  // in 1..4, built with the factor; tile_tabs holds all wave items, then all groups
+  // in 1..4, built with the factor; tile_tabs holds all wave items, then all groups, then the
+  // rank-row table
   DevBuf tile_tabs;
   int tw_off[5] = {0, 0, 0, 0, 0}, tg_off[5] = {0, 0, 0, 0, 0}, n_tgroups[5] = {0, 0, 0, 0, 0};
   size_t tg_base = 0;                             // byte offset of the groups in tile_tabs
+  size_t rr_base = 0;                             // byte offset of the rank-row table in tile_tabs
   // host copies of uploaded build tables: they outlive their asynchronous uploads
   std::vector<std::vector<char>> host_keep;
   // host copies of the pass-1 tables: they outlive their asynchronous uploads
@@ -335,15 +337,21 @@ static hipError_t clear_padding(void* base, int64_t rows, int64_t n, int64_t ld,
 // Every item loads the same bytes (its 16 rows of the harmonics) while its MFMA work grows with its
 // radial functions, and the low degrees have the most of them.  The waves of a group synchronise
 // once per chunk and waves w and w + 4 share a SIMD, so the busiest SIMD of a group sets the pace
-// of its chunk loop.  When all radial rows fit one group's staging, the items are therefore placed
-// by hdf::place_wave_items (for one column tile, after cutting them to at most kMvtSplitAcc radial
-// functions) so that the waves of each SIMD and the groups carry about equal numbers of tiles.
-// Otherwise the groups are runs of consecutive items.
+// of its chunk loop.  When all radial rows fit one group's staging:
+//  - the harmonics of a degree that do not fill a 16-row tile (a degree's last rows, or all of a
+//    degree with fewer than 16) are not padded: their rank rows (harmonic, radial function) are
+//    pooled over the degrees and cut into rank-row items of 16 rows (MvtRankRow), one accumulator
+//    tile per column tile, instead of a partly empty tile per radial function;
+//  - items of one column tile are cut to at most kMvtSplitAcc radial functions;
+//  - hdf::place_wave_items places the items so that the waves of each SIMD and the groups carry
+//    about equal numbers of accumulator tiles.
+// Otherwise the groups are runs of consecutive items.  rr receives the rank-row table (the same for
+// every cpl).
 constexpr int kMvtSplitAcc = 3;
 static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl, std::vector<hdf::MvtWave>& tw,
-                        std::vector<hdf::MvtGroup>& tg) {
+                        std::vector<hdf::MvtGroup>& tg, std::vector<hdf::MvtRankRow>& rr) {
   const int nct_t = cpl == 1 ? 1 : (cpl == 2 ? 2 : 4);
-  const int nlmax = hdf::matvec_tile_acc(fprec) / nct_t;
+  const int nlmax = hdf::matvec_tile_nl(fprec, nct_t);
   int q_min = 1 << 30, q_max = 0;
   for (const hdf::DegDev& dg : degs)
     if (dg.nh > 0 && dg.s > 0) {
@@ -353,12 +361,19 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
   const bool spread = q_max - q_min <= hdf::kMvtMaxNq;
   const int nl_cap = spread && nct_t == 1 ? std::min(nlmax, kMvtSplitAcc) : nlmax;
   const int w_base = (int)tw.size();
+  std::vector<hdf::MvtRankRow> pool;
   for (const hdf::DegDev& dg : degs)
-    for (int h0 = 0; h0 < dg.nh; h0 += 16)
+    for (int h0 = 0; h0 < dg.nh; h0 += 16) {
+      const int nr = std::min(16, dg.nh - h0);
+      if (spread && nr < 16) {
+        for (int h = h0; h < dg.nh; ++h)
+          for (int l = 0; l < dg.s; ++l) pool.push_back(hdf::MvtRankRow{dg.hoff + h, dg.qoff + l, dg.roff + h * dg.s + l, 0});
+        continue;
+      }
       for (int l0 = 0; l0 < dg.s; l0 += nl_cap) {
         hdf::MvtWave w{};
         w.row0 = dg.hoff + h0;
-        w.nr = std::min(16, dg.nh - h0);
+        w.nr = nr;
         w.qrow = dg.qoff + l0;
         w.nl = std::min(nl_cap, dg.s - l0);
         w.ct0 = 0;
@@ -367,11 +382,31 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
         w.s = dg.s;
         tw.push_back(w);
       }
+    }
+  if (!pool.empty()) {
+    if (rr.empty()) rr = pool;
+    for (size_t r0 = 0; r0 < pool.size(); r0 += 16) {
+      hdf::MvtWave w{};
+      w.row0 = (int32_t)r0;
+      w.nr = (int32_t)std::min<size_t>(16, pool.size() - r0);
+      w.qrow = -1;
+      w.nl = 1;
+      w.ct0 = 0;
+      w.nct = cpl;
+      tw.push_back(w);
+    }
+  }
   const int n_items = (int)tw.size() - w_base;
   std::vector<int> loads(n_items), order, nw;
-  for (int i = 0; i < n_items; ++i) loads[i] = tw[w_base + i].nl * nct_t;
-  if (spread && n_items > hdf::kMvtWavesPerGroup &&
-      hdf::place_wave_items(loads, hdf::kMvtWavesPerGroup, 4, order, nw)) {
+  for (int i = 0; i < n_items; ++i) loads[i] = std::max(1, tw[w_base + i].nl) * cpl;
+  if (spread) {
+    // every group stages all radial rows (rank-row items draw on any of them)
+    if (!hdf::place_wave_items(loads, hdf::kMvtWavesPerGroup, 4, order, nw)) {
+      order.resize(n_items);
+      for (int i = 0; i < n_items; ++i) order[i] = i;
+      nw.clear();
+      for (int i = 0; i < n_items; i += hdf::kMvtWavesPerGroup) nw.push_back(std::min(hdf::kMvtWavesPerGroup, n_items - i));
+    }
     std::vector<hdf::MvtWave> placed;
     for (int i : order) placed.push_back(tw[w_base + i]);
     std::copy(placed.begin(), placed.end(), tw.begin() + w_base);
@@ -779,17 +814,22 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     {
       std::vector<hdf::MvtWave> tw;
       std::vector<hdf::MvtGroup> tg;
+      std::vector<hdf::MvtRankRow> rr;
       for (int cpl = 1; cpl <= 4; ++cpl) {
         f->tw_off[cpl] = (int)tw.size();
         f->tg_off[cpl] = (int)tg.size();
-        tile_tables(f->degs, f->fprec, cpl, tw, tg);
+        tile_tables(f->degs, f->fprec, cpl, tw, tg, rr);
         f->n_tgroups[cpl] = (int)tg.size() - f->tg_off[cpl];
       }
+      if (rr.empty()) rr.push_back(hdf::MvtRankRow{0, 0, 0, 0});   // never read: no rank-row items
       const size_t wb = tw.size() * sizeof(hdf::MvtWave);
       f->tg_base = (wb + 255) / 256 * 256;
-      std::vector<char> tabs(f->tg_base + tg.size() * sizeof(hdf::MvtGroup), 0);
+      const size_t gb = tg.size() * sizeof(hdf::MvtGroup);
+      f->rr_base = (f->tg_base + gb + 255) / 256 * 256;
+      std::vector<char> tabs(f->rr_base + rr.size() * sizeof(hdf::MvtRankRow), 0);
       std::memcpy(tabs.data(), tw.data(), wb);
-      std::memcpy(tabs.data() + f->tg_base, tg.data(), tg.size() * sizeof(hdf::MvtGroup));
+      std::memcpy(tabs.data() + f->tg_base, tg.data(), gb);
+      std::memcpy(tabs.data() + f->rr_base, rr.data(), rr.size() * sizeof(hdf::MvtRankRow));
       HIPCHK(upload(f->tile_tabs, tabs.data(), tabs.size()));
     }
     std::vector<double> lr;
@@ -1305,6 +1345,9 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
 static const hdf::MvtWave* tile_waves(hdf_handle h, int cpl) {
   return (const hdf::MvtWave*)h->tile_tabs.p + h->tw_off[cpl];
 }
+static const hdf::MvtRankRow* tile_rank_rows(hdf_handle h) {
+  return (const hdf::MvtRankRow*)((const char*)h->tile_tabs.p + h->rr_base);
+}
 static const hdf::MvtGroup* tile_groups(hdf_handle h, int cpl) {
   return (const hdf::MvtGroup*)((const char*)h->tile_tabs.p + h->tg_base) + h->tg_off[cpl];
 }
@@ -1372,8 +1415,9 @@ static hdf_status pass1_chunked(hdf_handle h, const void* V, int64_t m, int64_t 
     const void* Vc = (const char*)V + c0 * ldv * h->ioel();
     double* part = (double*)h->ws_part.p + (size_t)slot * h->r * m16;
     if (tile)
-      HIPCHK(hdf::launch_matvec_t_tile(h->cphi.p, h->ldC, h->cq.p, h->ldC, tile_waves(h, cpl), tile_groups(h, cpl),
-                                       h->n_tgroups[cpl], splits[ci], slen[ci], Vc, ldv, nc, (int)m, m16, h->r, part,
+      HIPCHK(hdf::launch_matvec_t_tile(h->cphi.p, h->ldC, h->cq.p, h->ldC, tile_waves(h, cpl), tile_rank_rows(h),
+                                       tile_groups(h, cpl), h->n_tgroups[cpl], splits[ci], slen[ci], Vc, ldv, nc,
+                                       (int)m, m16, h->r, part,
                                        h->fprec, h->dtype, s));
     else
       HIPCHK(hdf::launch_matvec_t(h->cphi.p, h->ldC, h->cq.p, h->ldC, (const hdf::DegDev*)h->degs_dev.p,
@@ -1504,7 +1548,8 @@ static hdf_status pass1(hdf_handle h, int side, const void* V, int64_t m, int64_
         for (auto& e : h->ev_mv) HIPCHK(hipEventCreate(&e));
       HIPCHK(hipEventRecord(h->ev_mv[0], s));
     }
-    HIPCHK(hdf::launch_matvec_t_tile(phi, ldn, qv, ldn, tile_waves(h, cpl), tile_groups(h, cpl), h->n_tgroups[cpl],
+    HIPCHK(hdf::launch_matvec_t_tile(phi, ldn, qv, ldn, tile_waves(h, cpl), tile_rank_rows(h), tile_groups(h, cpl),
+                                     h->n_tgroups[cpl],
                                      n_splits, split_len, V, ldv, n, (int)m, m16, h->r, (double*)h->ws_part.p,
                                      h->fprec, h->dtype, s));
     if (timed) HIPCHK(hipEventRecord(h->ev_mv[1], s));
@@ -1664,7 +1709,7 @@ hdf_status hdf_matvec_noalloc(hdf_handle h, const void* V, int64_t m, int64_t ld
   void* Wd = (char*)base + w_bytes;
   double* part = (double*)((char*)base + w_bytes + wd_bytes);
   HIPCHK(hdf::launch_matvec_t_tile(side ? h->phi2.p : h->phi.p, side ? h->ldN2 : h->ldN, side ? h->q2.p : h->q.p,
-                                   side ? h->ldN2 : h->ldN, tile_waves(h, cpl), tile_groups(h, cpl),
+                                   side ? h->ldN2 : h->ldN, tile_waves(h, cpl), tile_rank_rows(h), tile_groups(h, cpl),
                                    h->n_tgroups[cpl], n_splits, split_len, V, ldv, n1, (int)m, m16, h->r, part,
                                    h->fprec, h->dtype, s));
   HIPCHK(hdf::launch_matvec_reduce(part, n_splits, h->r, m16, (const double*)h->lam_row.p, W, Wd, h->fprec, s));

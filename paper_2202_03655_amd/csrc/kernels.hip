@@ -1148,9 +1148,10 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
 // function l, column tile ct), so one pair of 16-byte loads of the tile's
 // values per lane and 32-point chunk feeds 8 * nl * nct MFMAs.  MFMA K-step t
 // of a chunk takes the four points p + 8 g + t (lane group g) with
-//   A[r][g] = phi_{row0 + r}(p + 8 g + t),
-//   B[g][c] = q_l(p + 8 g + t) V[p + 8 g + t][16 ct + c],
-// B formed from the staged radial rows and V^T in LDS.  The tile's values are
+//   A[r][g] = phi_{row0 + r}(p + 8 g + t) q_l(p + 8 g + t),
+//   B[g][c] = V[p + 8 g + t][16 ct + c],
+// A formed from the tile's values and the staged radial rows, B from V^T in LDS.  A rank-row item
+// (MvtRankRow) takes row r's harmonic and radial row from its own table entry.  The tile's values are
 // prefetched PF chunks ahead into registers; the staged operands are double
 // buffered, with one barrier per chunk.  Every load is unconditional and in
 // bounds: chunk starts are clamped to the split's last chunk, Phi and Q rows
@@ -1166,8 +1167,11 @@ template <typename T, int NCT> struct MvtPF { static constexpr int value = sizeo
 template <typename T, int NCT> struct MvtWaves {
   static constexpr int value = sizeof(T) == 4 ? (NCT < 4 ? 4 : 3) : (NCT == 1 ? 2 : 3);
 };
-// accumulator tiles per wavefront
-template <typename T> struct MvtAcc { static constexpr int value = sizeof(T) == 4 ? 8 : 4; };
+// radial functions per wave item (accumulator tiles per wavefront: NL * NCT); binary32 with two
+// column tiles keeps three, the registers of four spill
+template <typename T, int NCT> struct MvtNL {
+  static constexpr int value = sizeof(T) == 4 ? (NCT == 2 ? 3 : 8 / NCT) : 4 / NCT;
+};
 constexpr int kMvtCH = 32;                 // points per chunk
 constexpr int kMvtThreads = 64 * kMvtWavesPerGroup;
 constexpr int kMvtVS = kMvtCH + 4;         // padded staged row (LDS bank spread)
@@ -1178,6 +1182,7 @@ __global__ void __launch_bounds__(kMvtThreads) __attribute__((amdgpu_waves_per_e
 k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
                                                     const T* __restrict__ q, int64_t ld_q,
                                                     const MvtWave* __restrict__ waves,
+                                                    const MvtRankRow* __restrict__ rrows,
                                                     const MvtGroup* __restrict__ groups, int n_groups,
                                                     int n_splits, int64_t split_len,
                                                     const TV* __restrict__ V, int64_t ldv, int64_t n, int m,
@@ -1185,7 +1190,7 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   typedef typename Mfma<T>::V Acc;
   constexpr int PF = MvtPF<T, NCT>::value;
   static_assert(PF % 2 == 0, "the LDS buffer of a chunk is its slot's parity");
-  constexpr int NL = MvtAcc<T>::value / NCT;
+  constexpr int NL = MvtNL<T, NCT>::value;
   constexpr int CH = kMvtCH, VS = kMvtVS;
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -1206,8 +1211,16 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
   const int64_t p_last = p_begin + (p_end - 1 - p_begin) / CH * CH;   // start of the split's last chunk
   const int half = (m16 + kMvtMaxNq + 1) * VS;      // one buffer: V^T (m16 rows), radial rows, a pad row
-  // this lane's Phi row (rows past the tile repeat its first row; their outputs are not written)
-  const T* prow = phi + (int64_t)(wi.row0 + (li < wi.nr ? li : 0)) * ld_phi + 8 * g;
+  // this lane's Phi row and first staged radial row (rows past the tile repeat its first row; their
+  // outputs are not written); a rank-row item gives each lane its own pair
+  const bool rank_item = wi.qrow < 0;               // uniform
+  int hrow = wi.row0 + (li < wi.nr ? li : 0), qlane = wi.qrow - gd.q_lo;
+  if (rank_item) {
+    const MvtRankRow rr = rrows[wi.row0 + (li < wi.nr ? li : 0)];
+    hrow = rr.hrow;
+    qlane = rr.qrow - gd.q_lo;
+  }
+  const T* prow = phi + (int64_t)hrow * ld_phi + 8 * g;
 
   auto load_tile = [&](int64_t p, T (&a)[8]) {
     const int64_t pc = p < p_last ? p : p_last;
@@ -1307,7 +1320,6 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   stage_store(lds, p_begin, sv[0], sq[0]);
   stage_load(p_begin + PF * CH, sv[0], sq[0]);     // slot 0 next holds chunk PF
   __syncthreads();
-  const int qr0 = wi.qrow - gd.q_lo;
   const int64_t n_chunks = (p_end - p_begin + CH - 1) / CH;
   const int64_t n_rounds = (n_chunks + PF - 1) / PF;
   for (int64_t it = 0; it < n_rounds; ++it) {
@@ -1317,23 +1329,27 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
       const int buf = j & 1;                        // PF is even: chunk parity = slot parity
       const T* cur = lds + buf * half;
       if (active) {                                 // uniform
+        // radial function outermost: the A operands (tile values times the radial row) are formed
+        // once and serve every column tile
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          if (ct < wi.nct) {                        // uniform
-            T v[8];
-            lds8(cur + (16 * (wi.ct0 + ct) + li) * VS + 8 * g, v);
+        for (int l = 0; l < NL; ++l) {
+          if (l < wi.nl) {                          // uniform
+            T av[8];
+            lds8(cur + m16 * VS + (qlane + l) * VS + 8 * g, av);
 #pragma unroll
-            for (int l = 0; l < NL; ++l) {
-              if (l < wi.nl) {                      // uniform
-                T q8[8];
-                lds8(cur + m16 * VS + (qr0 + l) * VS + 8 * g, q8);
+            for (int t = 0; t < 8; ++t) av[t] *= a[j][t];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) acc[l][ct] = Mfma<T>::run(a[j][t], q8[t] * v[t], acc[l][ct]);
+            for (int ct = 0; ct < NCT; ++ct) {
+              if (ct < wi.nct) {                    // uniform
+                T v[8];
+                lds8(cur + (16 * (wi.ct0 + ct) + li) * VS + 8 * g, v);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) acc[l][ct] = Mfma<T>::run(av[t], v[t], acc[l][ct]);
               }
+              // column tiles one after the other: hoisting the operands of all of them overflows
+              // the registers of the binary64 shapes and of binary32 with two column tiles
+              if constexpr (sizeof(T) == 8 || NCT == 2) __builtin_amdgcn_sched_barrier(0);
             }
-            // column tiles one after the other: hoisting the operands of all of them overflows the
-            // registers of the binary64 shapes
-            if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
@@ -1349,6 +1365,20 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   }
   if (!active) return;
   double* out = part + (int64_t)split * rank * m16;
+  if (rank_item) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      if (ct < wi.nct) {
+        const int c = 16 * (wi.ct0 + ct) + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = Mfma<T>::row(g, e);
+          if (r < wi.nr) out[(int64_t)rrows[wi.row0 + r].out * m16 + c] = (double)acc[0][ct][e];
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
     if (l < wi.nl) {
@@ -1367,14 +1397,18 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   }
 }
 
-int matvec_tile_acc(int prec) { return prec == 1 ? MvtAcc<float>::value : MvtAcc<double>::value; }
+int matvec_tile_nl(int prec, int nct) {
+  if (prec == 1) return nct == 1 ? MvtNL<float, 1>::value : (nct == 2 ? MvtNL<float, 2>::value : MvtNL<float, 4>::value);
+  return nct == 1 ? MvtNL<double, 1>::value : (nct == 2 ? MvtNL<double, 2>::value : MvtNL<double, 4>::value);
+}
 
 size_t matvec_tile_lds_bytes(int m16, int prec) {
   return 2 * (size_t)(m16 + kMvtMaxNq + 1) * kMvtVS * (prec == 1 ? 4 : 8);
 }
 
 hipError_t launch_matvec_t_tile(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
-                                const MvtWave* waves, const MvtGroup* groups, int n_groups, int n_splits,
+                                const MvtWave* waves, const MvtRankRow* rank_rows, const MvtGroup* groups,
+                                int n_groups, int n_splits,
                                 int64_t split_len, const void* V, int64_t ldv, int64_t n, int m, int m16,
                                 int64_t rank, double* partials, int prec, int io, hipStream_t s) {
   if (m16 < 16 || m16 > 64 || m16 % 16 || n_groups < 1 || n_splits < 1 || split_len % kMvtCH)
@@ -1384,7 +1418,8 @@ hipError_t launch_matvec_t_tile(const void* phi, int64_t ld_phi, const void* q, 
   const size_t lds = matvec_tile_lds_bytes(m16, prec);
   const unsigned n_blocks = (unsigned)(((n_splits + 7) / 8) * 8 * n_groups);
 #define HDF_MVTT(T, TV, NC)                                                                                   \
-  k_mv_t_tile<T, TV, NC><<<n_blocks, kMvtThreads, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, waves, groups,   \
+  k_mv_t_tile<T, TV, NC><<<n_blocks, kMvtThreads, lds, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, waves,          \
+                                                    rank_rows, groups,                                        \
                                                     n_groups, n_splits, split_len, (const TV*)V, ldv, n, m,   \
                                                     m16, rank, partials)
 #define HDF_MVTT_NCT(T, TV)                                                                                   \

@@ -101,10 +101,10 @@ hipError_t launch_matvec_t(const void* phi, int64_t ld_phi, const void* q, int64
                            int64_t split_len, int64_t rank, double* partials, int prec, int io,
                            hipStream_t s);
 // Pass 1, tile-major (m16 <= 64).  A wave item is one 16-row tile of one
-// degree's harmonics with a range of its radial functions and the column
-// tiles [ct0, ct0 + nct), nl * nct <= matvec_tile_acc(prec) accumulator
-// tiles; one load of the tile's harmonic values feeds the MFMAs of all its
-// (l, column) slots.  A workgroup runs one group (up to kMvtWavesPerGroup wave items whose
+// degree's harmonics with a range of nl <= matvec_tile_nl(prec, NCT) of its
+// radial functions and the column tiles [ct0, ct0 + nct) (NCT = 1, 2 or 4
+// column tiles per launch); one load of the tile's harmonic values feeds the
+// MFMAs of all its (l, column) slots.  A workgroup runs one group (up to kMvtWavesPerGroup wave items whose
 // radial rows lie in [q_lo, q_lo + nq), nq <= kMvtMaxNq) over one split of
 // split_len points (a multiple of 32; n_splits * split_len >= n >
 // (n_splits - 1) * split_len) and writes partial[split][row][c] (binary64)
@@ -119,16 +119,28 @@ struct MvtWave {
   int32_t out0;   // rank row of (h0, first radial function)
   int32_t s;      // s_k: rank-row stride between consecutive harmonics
 };
+// A wave item with qrow < 0 is a rank-row item (nl = 1): its rows are the rank rows
+// [row0, row0 + nr) of the rank-row table (nr <= 16), each a (harmonic row, radial row, output
+// row) triple, so rows of different degrees and radial functions share one tile.  Row r of its
+// tile is phi_{hrow}(x) q_{qrow}(x), its output row out.
+struct MvtRankRow {
+  int32_t hrow;   // harmonic row in phi
+  int32_t qrow;   // radial row in q
+  int32_t out;    // rank row of the result
+  int32_t pad;
+};
 constexpr int kMvtWavesPerGroup = 8;   // wavefronts per workgroup
 struct MvtGroup {
   int32_t w0, nw;     // wave items [w0, w0 + nw), nw <= kMvtWavesPerGroup
   int32_t q_lo, nq;   // radial rows staged in LDS
 };
-int matvec_tile_acc(int prec);     // accumulator tiles per wavefront (8 binary32, 4 binary64)
+// radial functions per wave item for column-tile count nct (1, 2 or 4) of the launch
+int matvec_tile_nl(int prec, int nct);
 constexpr int kMvtMaxNq = 32;      // staged radial rows per workgroup
 size_t matvec_tile_lds_bytes(int m16, int prec);
 hipError_t launch_matvec_t_tile(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
-                                const MvtWave* waves, const MvtGroup* groups, int n_groups, int n_splits,
+                                const MvtWave* waves, const MvtRankRow* rank_rows, const MvtGroup* groups,
+                                int n_groups, int n_splits,
                                 int64_t split_len, const void* V, int64_t ldv, int64_t n, int m, int m16,
                                 int64_t rank, double* partials, int prec, int io, hipStream_t s);
 // Reduce over splits: W[row][c] = sum_split partial (binary64) and
