@@ -1264,12 +1264,23 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
       const int64_t ptc = pt < n ? pt : n - 1;
       sv[j] = V[ptc * ldv + (c < m ? c : 0)];
     }
-#pragma unroll
-    for (int j = 0; j < SQ; ++j) {
-      const int e = tid + TPB * j;
+    if constexpr (SQ == 2) {
+      // two consecutive points of one radial row per thread, one 2-vector load
+      const int e = 2 * tid;
       const int r = e >> 5, pq = e & 31;
       const int rc = r < gd.nq ? r : gd.nq - 1;
-      sq[j] = q[(int64_t)(gd.q_lo + rc) * ld_q + p + pq];
+      typedef T T2 __attribute__((ext_vector_type(2)));
+      const T2 w = *reinterpret_cast<const T2*>(q + (int64_t)(gd.q_lo + rc) * ld_q + p + pq);
+      sq[0] = w[0];
+      sq[1] = w[1];
+    } else {
+#pragma unroll
+      for (int j = 0; j < SQ; ++j) {
+        const int e = tid + TPB * j;
+        const int r = e >> 5, pq = e & 31;
+        const int rc = r < gd.nq ? r : gd.nq - 1;
+        sq[j] = q[(int64_t)(gd.q_lo + rc) * ld_q + p + pq];
+      }
     }
   };
   // values of the chunk starting at p into buf; entries past the staged area go to the pad row
@@ -1282,10 +1293,19 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
       const int at = e < sv_n ? c * VS + pp : (m16 + kMvtMaxNq) * VS + (tid & 31);
       buf[at] = ok ? (T)sv[j] : (T)0;
     }
+    if constexpr (SQ == 2) {
+      typedef T T2 __attribute__((ext_vector_type(2)));
+      T2 w;
+      w[0] = sq[0];
+      w[1] = sq[1];
+      const int e = 2 * tid;
+      *reinterpret_cast<T2*>(buf + m16 * VS + (e >> 5) * VS + (e & 31)) = w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < SQ; ++j) {
-      const int e = tid + TPB * j;
-      buf[m16 * VS + (e >> 5) * VS + (e & 31)] = sq[j];
+      for (int j = 0; j < SQ; ++j) {
+        const int e = tid + TPB * j;
+        buf[m16 * VS + (e >> 5) * VS + (e & 31)] = sq[j];
+      }
     }
   };
   auto lds8 = [&](const T* p, T (&v)[8]) {
