@@ -1152,18 +1152,20 @@ __global__ void __launch_bounds__(64) k_mv_t(const T* __restrict__ phi, int64_t 
 //   B[g][c] = V[p + 8 g + t][16 ct + c],
 // A formed from the tile's values and the staged radial rows, B from V^T in LDS.  A rank-row item
 // (MvtRankRow) takes row r's harmonic and radial row from its own table entry.  The tile's values are
-// prefetched PF chunks ahead into registers; the staged operands are double
-// buffered, with one barrier per chunk.  Every load is unconditional and in
-// bounds: chunk starts are clamped to the split's last chunk, Phi and Q rows
-// are padded by at least 63 points past n (zeros), V rows are clamped to n - 1
-// and the values of points past the split multiplied by zero.
+// prefetched PF chunks ahead into registers; the staged operands (V^T and the
+// radial rows) are staged for two chunks at a time into double-buffered LDS,
+// with one barrier per such unit.  Every load is unconditional and in
+// bounds: chunk and unit starts are clamped to the split's last chunk and
+// unit, Phi and Q rows are padded by at least 63 points past n (zeros), V rows
+// are clamped to n - 1 and the values of points past the split multiplied by
+// zero.
 // Prefetch depth (chunks of the tile in flight) and occupancy per type and column tiles, chosen so
-// that the registers fit without spills: binary32 4 chunks deep at four wavefronts per SIMD
-// (<= 128 registers; three with four column tiles), binary64 2 deep at two (one column tile: eight
-// radial functions) or three.
-// Without the occupancy hint the scheduler hoists the B operands of all radial functions and
+// that the registers fit without spills: binary32 with one column tile 4 chunks deep at four
+// wavefronts per SIMD (<= 128 registers), otherwise 2 deep (binary32: four wavefronts, three with
+// four column tiles; binary64: two with one column tile, three with more).
+// Without the occupancy hint the scheduler hoists the operands of all radial functions and
 // overflows the registers.
-template <typename T, int NCT> struct MvtPF { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
+template <typename T, int NCT> struct MvtPF { static constexpr int value = sizeof(T) == 4 && NCT == 1 ? 4 : 2; };
 template <typename T, int NCT> struct MvtWaves {
   static constexpr int value = sizeof(T) == 4 ? (NCT < 4 ? 4 : 3) : (NCT == 1 ? 2 : 3);
 };
@@ -1172,9 +1174,11 @@ template <typename T, int NCT> struct MvtWaves {
 template <typename T, int NCT> struct MvtNL {
   static constexpr int value = sizeof(T) == 4 ? (NCT == 2 ? 3 : 8 / NCT) : 4 / NCT;
 };
-constexpr int kMvtCH = 32;                 // points per chunk
+constexpr int kMvtCH = 32;                 // points per chunk (MFMA K-steps of one tile load)
+constexpr int kMvtSP = 2;                  // chunks per staged unit (one barrier per unit)
+constexpr int kMvtSpan = kMvtSP * kMvtCH;  // points per staged unit
 constexpr int kMvtThreads = 64 * kMvtWavesPerGroup;
-constexpr int kMvtVS = kMvtCH + 4;         // padded staged row (LDS bank spread)
+constexpr int kMvtVS = kMvtSpan + 4;       // padded staged row (LDS bank spread)
 
 
 template <typename T, typename TV, int NCT>
@@ -1191,7 +1195,9 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   constexpr int PF = MvtPF<T, NCT>::value;
   static_assert(PF % 2 == 0, "the LDS buffer of a chunk is its slot's parity");
   constexpr int NL = MvtNL<T, NCT>::value;
-  constexpr int CH = kMvtCH, VS = kMvtVS;
+  constexpr int CH = kMvtCH, VS = kMvtVS, SP = kMvtSP, SPAN = kMvtSpan;
+  static_assert(PF % SP == 0, "whole staged units in flight");
+  constexpr int PS = PF / SP;                       // staged units in flight
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   // block b runs group gi over split sp with b = 8 (G (sp / 8) + gi) + sp % 8: the workgroups of
@@ -1210,6 +1216,7 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   const int64_t p_begin = (int64_t)split * split_len;
   const int64_t p_end = (p_begin + split_len < n) ? p_begin + split_len : n;
   const int64_t p_last = p_begin + (p_end - 1 - p_begin) / CH * CH;   // start of the split's last chunk
+  const int64_t u_last = p_begin + (p_end - 1 - p_begin) / SPAN * SPAN;   // ... and of its last unit
   const int half = (m16 + kMvtMaxNq + 1) * VS;      // one buffer: V^T (m16 rows), radial rows, a pad row
   // this lane's Phi row and first staged radial row (rows past the tile repeat its first row; their
   // outputs are not written); a rank-row item gives each lane its own pair
@@ -1239,73 +1246,66 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
       }
     }
   };
-  // staging of a chunk by all threads (TPB of them): V entries e = tid + TPB j < 32 m16 (point
-  // e / m16, column e % m16) and the group's radial entries e = tid + TPB j (row
-  // e / 32, point e % 32; rows past nq repeat the last one and are never read).  The loads are
-  // unconditional and in bounds and keep the raw values; the masks (points past the split,
-  // columns past m) and the choice of slot are applied when the values are written to LDS, so the
-  // compiler's load-counter waits stay exact (a select right after a load, or a branch around it,
-  // makes it wait for every load in flight).
+  // staging of a unit (SPAN = 64 points, two chunks) by all threads (TPB of them): V entries
+  // e = tid + TPB j < 64 m16 (point e / m16, column e % m16) and the group's radial entries, SQ
+  // consecutive points of one row per thread (row SQ tid / 64; rows past nq repeat the last one and
+  // are never read).  The loads are unconditional and in bounds and keep the raw values; the masks
+  // (points past the split, columns past m) and the choice of slot are applied when the values are
+  // written to LDS, so the compiler's load-counter waits stay exact (a select right after a load,
+  // or a branch around it, makes it wait for every load in flight).
   constexpr int TPB = kMvtThreads;
-  constexpr int SV = (CH * 16 * NCT + TPB - 1) / TPB, SQ = CH * kMvtMaxNq / TPB;
-  const int sv_n = CH * m16;                         // staged V entries per chunk
-  // staged values are loaded with the same look-ahead as the tile (PF chunks, rotating register
-  // slots): the load counter completes in issue order, so values loaded after the tile prefetch
-  // could only be waited for together with it
-  TV sv[PF][SV];
-  T sq[PF][SQ];
+  constexpr int SV = (SPAN * 16 * NCT + TPB - 1) / TPB, SQ = SPAN * kMvtMaxNq / TPB;
+  static_assert(SQ == 2 || SQ == 4, "radial staging: two or four consecutive points per thread");
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  const int sv_n = SPAN * m16;                       // staged V entries per unit
+  // e / m16 for the staged entries e < 4096 as (e * inv16) >> 20: exact for m16 <= 64 (the error
+  // of the rounded-up reciprocal stays below 2^-8 < 1 / m16)
+  const uint32_t inv16 = ((1u << 20) + (uint32_t)m16 - 1) / (uint32_t)m16;
+  static_assert(TPB * SV <= 4096, "staged entry index range of the reciprocal division");
+  // staged values are loaded with the same look-ahead as the tile (PF chunks = PS units, rotating
+  // register slots): the load counter completes in issue order, so values loaded after the tile
+  // prefetch could only be waited for together with it
+  TV sv[PS][SV];
+  T sq[PS][SQ];
   auto stage_load = [&](int64_t p0, TV (&sv)[SV], T (&sq)[SQ]) {
-    const int64_t p = p0 < p_last ? p0 : p_last;
+    const int64_t p = p0 < u_last ? p0 : u_last;
 #pragma unroll
     for (int j = 0; j < SV; ++j) {
       const int e = tid + TPB * j;
-      const int pp = e / m16, c = e - pp * m16;
+      const int pp = (int)(((uint32_t)e * inv16) >> 20), c = e - pp * m16;
       const int64_t pt = p + pp;
       const int64_t ptc = pt < n ? pt : n - 1;
       sv[j] = V[ptc * ldv + (c < m ? c : 0)];
     }
-    if constexpr (SQ == 2) {
-      // two consecutive points of one radial row per thread, one 2-vector load
-      const int e = 2 * tid;
-      const int r = e >> 5, pq = e & 31;
-      const int rc = r < gd.nq ? r : gd.nq - 1;
-      typedef T T2 __attribute__((ext_vector_type(2)));
-      const T2 w = *reinterpret_cast<const T2*>(q + (int64_t)(gd.q_lo + rc) * ld_q + p + pq);
-      sq[0] = w[0];
-      sq[1] = w[1];
-    } else {
+    const int e = SQ * tid;
+    const int r = e / SPAN, pq = e % SPAN;
+    const int rc = r < gd.nq ? r : gd.nq - 1;
+    const T* src = q + (int64_t)(gd.q_lo + rc) * ld_q + p + pq;
 #pragma unroll
-      for (int j = 0; j < SQ; ++j) {
-        const int e = tid + TPB * j;
-        const int r = e >> 5, pq = e & 31;
-        const int rc = r < gd.nq ? r : gd.nq - 1;
-        sq[j] = q[(int64_t)(gd.q_lo + rc) * ld_q + p + pq];
-      }
+    for (int h = 0; h < SQ / 2; ++h) {
+      const T2 w = *reinterpret_cast<const T2*>(src + 2 * h);
+      sq[2 * h] = w[0];
+      sq[2 * h + 1] = w[1];
     }
   };
-  // values of the chunk starting at p into buf; entries past the staged area go to the pad row
+  // values of the unit starting at p into buf; entries past the staged area go to the pad row
   auto stage_store = [&](T* buf, int64_t p, const TV (&sv)[SV], const T (&sq)[SQ]) {
 #pragma unroll
     for (int j = 0; j < SV; ++j) {
       const int e = tid + TPB * j;
-      const int pp = e / m16, c = e - pp * m16;
+      const int pp = (int)(((uint32_t)e * inv16) >> 20), c = e - pp * m16;
       const bool ok = p + pp < p_end && c < m;
-      const int at = e < sv_n ? c * VS + pp : (m16 + kMvtMaxNq) * VS + (tid & 31);
+      const int at = e < sv_n ? c * VS + pp : (m16 + kMvtMaxNq) * VS + (tid & 63);
       buf[at] = ok ? (T)sv[j] : (T)0;
     }
-    if constexpr (SQ == 2) {
-      typedef T T2 __attribute__((ext_vector_type(2)));
-      T2 w;
-      w[0] = sq[0];
-      w[1] = sq[1];
-      const int e = 2 * tid;
-      *reinterpret_cast<T2*>(buf + m16 * VS + (e >> 5) * VS + (e & 31)) = w;
-    } else {
+    const int e = SQ * tid;
+    T* dst = buf + m16 * VS + (e / SPAN) * VS + e % SPAN;
 #pragma unroll
-      for (int j = 0; j < SQ; ++j) {
-        const int e = tid + TPB * j;
-        buf[m16 * VS + (e >> 5) * VS + (e & 31)] = sq[j];
-      }
+    for (int h = 0; h < SQ / 2; ++h) {
+      T2 w;
+      w[0] = sq[2 * h];
+      w[1] = sq[2 * h + 1];
+      *reinterpret_cast<T2*>(dst + 2 * h) = w;
     }
   };
   auto lds8 = [&](const T* p, T (&v)[8]) {
@@ -1328,17 +1328,16 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
   for (int j = 0; j < NL; ++j)
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) acc[j][ct] = Acc{0, 0, 0, 0};
-  // slot j holds chunk c = j (mod PF): the tile in a[j], its staged values in sv[j], sq[j].  The
-  // chunk loop runs in whole groups of PF chunks; chunks past the split load clamped, in-bounds
-  // data and meet zero V values, so they add nothing.
+  // tile slot j holds chunk c = j (mod PF); staged slot u holds unit U = u (mod PS).  The chunk loop
+  // runs in whole groups of PF chunks; chunks past the split load clamped, in-bounds data and meet
+  // zero V values, so they add nothing.
   T a[PF][8];
 #pragma unroll
-  for (int j = 0; j < PF; ++j) {
-    load_tile(p_begin + j * CH, a[j]);
-    stage_load(p_begin + j * CH, sv[j], sq[j]);
-  }
+  for (int j = 0; j < PF; ++j) load_tile(p_begin + j * CH, a[j]);
+#pragma unroll
+  for (int u = 0; u < PS; ++u) stage_load(p_begin + u * SPAN, sv[u], sq[u]);
   stage_store(lds, p_begin, sv[0], sq[0]);
-  stage_load(p_begin + PF * CH, sv[0], sq[0]);     // slot 0 next holds chunk PF
+  stage_load(p_begin + PS * SPAN, sv[0], sq[0]);    // slot 0 next holds unit PS
   __syncthreads();
   const int64_t n_chunks = (p_end - p_begin + CH - 1) / CH;
   const int64_t n_rounds = (n_chunks + PF - 1) / PF;
@@ -1346,8 +1345,8 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int64_t pc = p_begin + (it * PF + j) * CH;
-      const int buf = j & 1;                        // PF is even: chunk parity = slot parity
-      const T* cur = lds + buf * half;
+      const int buf = (int)((it * PS + j / SP) & 1);  // the unit's LDS buffer: its parity
+      const T* cur = lds + buf * half + (j % SP) * CH;
       if (active) {                                 // uniform
         // radial function outermost: the A operands (tile values times the radial row) are formed
         // once and serve every column tile
@@ -1374,13 +1373,14 @@ k_mv_t_tile(const T* __restrict__ phi, int64_t ld_phi,
         }
       }
       load_tile(pc + PF * CH, a[j]);
-      // chunk pc + CH: its staged values (slot j + 1) go to the other buffer, and the slot is
-      // refilled with chunk pc + CH + PF CH
-      TV (&svn)[SV] = sv[(j + 1) % PF];
-      T (&sqn)[SQ] = sq[(j + 1) % PF];
-      stage_store(lds + (buf ^ 1) * half, pc + CH, svn, sqn);
-      stage_load(pc + CH + PF * CH, svn, sqn);
-      __syncthreads();
+      if (j % SP == SP - 1) {
+        // end of unit U: unit U + 1 (slot (U + 1) mod PS) goes to the other buffer, and the slot
+        // is refilled with unit U + 1 + PS
+        const int slot = (j / SP + 1) % PS;
+        stage_store(lds + (buf ^ 1) * half, pc + CH, sv[slot], sq[slot]);
+        stage_load(pc + CH + PS * SPAN, sv[slot], sq[slot]);
+        __syncthreads();
+      }
     }
   }
   if (!active) return;
