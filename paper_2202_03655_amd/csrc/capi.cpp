@@ -809,9 +809,20 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     if (f->cross) HIPCHK(upload_typed(f->q_coef2, qc2));
     HIPCHK(upload(f->q_len, ql.data(), ql.size() * 4));
     HIPCHK(upload(f->q_off, qo.data(), qo.size() * 4));
-    // contraction tables
-    HIPCHK(upload(f->degs_dev, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev)));
-    {
+    hdf::BuildTables tb{};
+    tb.col_of = (const int32_t*)f->col_of.p;
+    tb.chain = f->chain.p;
+    tb.q_len = (const int32_t*)f->q_len.p;
+    tb.q_off = (const int32_t*)f->q_off.p;
+    tb.q_coef = f->q_coef.p;
+    tb.K = Kh;
+    tb.S = (int)f->S;
+    f->tables = tb;
+    // tables of the products (not read by the factor evaluation): built and uploaded after its
+    // launch in the stored case, so the host work overlaps the evaluation on the device
+    auto product_tables = [&]() -> hdf_status {
+      // host tables first, then the uploads: an upload from pageable memory may wait for the
+      // stream (the evaluation just launched) before it returns
       std::vector<hdf::MvtWave> tw;
       std::vector<hdf::MvtGroup> tg;
       std::vector<hdf::MvtRankRow> rr;
@@ -830,31 +841,25 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       std::memcpy(tabs.data(), tw.data(), wb);
       std::memcpy(tabs.data() + f->tg_base, tg.data(), gb);
       std::memcpy(tabs.data() + f->rr_base, rr.data(), rr.size() * sizeof(hdf::MvtRankRow));
+      std::vector<double> lr;
+      lr.reserve(f->r);
+      for (size_t di = 0; di < f->degs.size(); ++di) {
+        const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
+        for (int h = 0; h < f->degs[di].nh; ++h)
+          for (int l = 0; l < df.s; ++l) lr.push_back(f->cross ? 1.0 : df.lam[l]);
+      }
+      std::vector<hdf::DegDev> dbk(K + 1);
+      for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
+      for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
+      HIPCHK(upload(f->degs_dev, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev)));
       HIPCHK(upload(f->tile_tabs, tabs.data(), tabs.size()));
-    }
-    std::vector<double> lr;
-    lr.reserve(f->r);
-    for (size_t di = 0; di < f->degs.size(); ++di) {
-      const hdf::DegreeFactor& df = f->deg[f->kept_k[di]];
-      for (int h = 0; h < f->degs[di].nh; ++h)
-        for (int l = 0; l < df.s; ++l) lr.push_back(f->cross ? 1.0 : df.lam[l]);
-    }
-    HIPCHK(upload(f->lam_row, lr.data(), lr.size() * 8));
-
-    hdf::BuildTables tb{};
-    tb.col_of = (const int32_t*)f->col_of.p;
-    tb.chain = f->chain.p;
-    tb.q_len = (const int32_t*)f->q_len.p;
-    tb.q_off = (const int32_t*)f->q_off.p;
-    tb.q_coef = f->q_coef.p;
-    tb.K = Kh;
-    tb.S = (int)f->S;
-    f->tables = tb;
-    std::vector<hdf::DegDev> dbk(K + 1);
-    for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
-    for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
-    HIPCHK(upload(f->degs_by_k, dbk.data(), dbk.size() * sizeof(hdf::DegDev)));
+      HIPCHK(upload(f->lam_row, lr.data(), lr.size() * 8));
+      HIPCHK(upload(f->degs_by_k, dbk.data(), dbk.size() * sizeof(hdf::DegDev)));
+      return HDF_OK;
+    };
     if (mfree) {                                // evaluated in every product
+      const hdf_status pst = product_tables();
+      if (pst != HDF_OK) return pst;
       if (f->mf_fused) {
         std::vector<char> tabs;
         if (!mf_tables(f, col_of, tabs)) return fail(HDF_E_ARG, "internal: inconsistent fused-pass tables");
@@ -880,6 +885,8 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       HIPCHK(clear_padding(f->q2.p, f->S, f->N2, f->ldN2, f->felem(), s));
     }
     HIPCHK(hipEventRecord(f->ev_b1, s));
+    const hdf_status pst = product_tables();
+    if (pst != HDF_OK) return pst;
   }
   return HDF_OK;
 }

@@ -389,6 +389,9 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
   typedef typename std::conditional<MODE == 0, double, float>::type T;
   typedef typename Mfma<T>::V V;
   __shared__ double sh[4][4 * 64];
+  // T_c(t) of a tile's 16 points, one row per point (padded stride), per wavefront
+  constexpr int TCS = 16 * NCT + 1;
+  __shared__ double tcs[4][16 * TCS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const double Reff = geo->Reff;
@@ -429,25 +432,32 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
         w[a][e] = pw;
       }
     }
-    // T_c(t) for c = b*16 + li, four points in flight
-    double tm1[4], t0[4];
+    // T_c(t) for c = b*16 + li: the recurrence of point g + 4 e runs once, in lane e of group g,
+    // and goes through LDS to the sixteen lanes that use it
+    double* trow = &tcs[wave][0];
+    if (li < 4) {
+      double tp = t[0];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { tm1[e] = 1.0; t0[e] = t[e]; }
+      for (int e = 1; e < 4; ++e) tp = li == e ? t[e] : tp;
+      double tm1 = 1.0, t0 = tp;
+      double* dst = trow + (g + 4 * li) * TCS;
+#pragma unroll
+      for (int c = 0; c < 16 * NCT; ++c) {
+        double cur;
+        if (c == 0) cur = 1.0;
+        else if (c == 1) cur = tp;
+        else { cur = 2.0 * tp * t0 - tm1; tm1 = t0; t0 = cur; }
+        dst[c] = cur;
+      }
+    }
+    // the rows are read by the other lanes of the wavefront (wavefront-synchronous exchange; the
+    // next tile's rows are written after this tile's MFMAs, which every lane reaches first)
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int b = 0; b < NCT; ++b) {
-      if (b >= nct) break;
+      const int c = b * 16 + li;
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) {
-        const int c = b * 16 + cc;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          double cur;
-          if (c == 0) cur = 1.0;
-          else if (c == 1) cur = t[e];
-          else { cur = 2.0 * t[e] * t0[e] - tm1[e]; tm1[e] = t0[e]; t0[e] = cur; }
-          if (cc == li) tc[b][e] = (c <= 2 * K) ? cur : 0.0;
-        }
-      }
+      for (int e = 0; e < 4; ++e) tc[b][e] = (b < nct && c <= 2 * K) ? trow[(g + 4 * e) * TCS + c] : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {

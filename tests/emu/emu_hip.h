@@ -117,6 +117,8 @@ void launch(const char* name, dim3 grid, dim3 block, size_t shm, hipStream_t s, 
 #define __syncthreads() emu::syncthreads()
 #define __syncthreads_count(p) emu::syncthreads_count(p)
 #define __shfl_xor(v, m) emu::shfl_xor(v, m)
+// wavefront-level synchronisation point: a wave-wide collective (a shuffle of nothing)
+#define __builtin_amdgcn_wave_barrier() ((void)emu::shfl_xor(0.0, 0))
 using std::max;
 using std::min;
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu::mfma_f32(a, b, c)
