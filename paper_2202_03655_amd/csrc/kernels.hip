@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
   typedef typename std::conditional<MODE == 0, double, float>::type T;
   typedef typename Mfma<T>::V V;
   __shared__ double sh[4][4 * 64];
-  // T_c(t) of a tile's 16 points, one row per point (padded stride), per wavefront
+  // T_c(t) (c < 16 NCT) and rho^2 of a tile's 16 points, one row per point, per wavefront
   constexpr int TCS = 16 * NCT + 1;
   __shared__ double tcs[4][16 * TCS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -410,13 +410,34 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
 #pragma unroll
     for (int b = 0; b < NCT; ++b) acc[a][b] = V{0, 0, 0, 0};
   for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
-    double t[4], w[NRT][4], tc[NCT][4];
+    double w[NRT][4], tc[NCT][4];
+    // the radial point and the T_c(t) recurrence of point g + 4 e run once, in lane e of group g,
+    // and go through LDS to the sixteen lanes that use them (T_c for c = b*16 + li, rho^2 for
+    // the powers rho^(2k), k = a*16 + li)
+    double* trow = &tcs[wave][0];
+    if (li < 4) {
+      const int64_t i = tile * 16 + g + 4 * li;
+      double rho2 = 0.0, tp = 0.0;
+      if (i < n) radial_point(x_soa, ldx, i, d, geo, Reff, u0, u1, rho2, tp);
+      double* dst = trow + (g + 4 * li) * TCS;
+      dst[16 * NCT] = rho2;
+      double tm1 = 1.0, t0 = tp;
+#pragma unroll
+      for (int c = 0; c < 16 * NCT; ++c) {
+        double cur;
+        if (c == 0) cur = 1.0;
+        else if (c == 1) cur = tp;
+        else { cur = 2.0 * tp * t0 - tm1; tm1 = t0; t0 = cur; }
+        dst[c] = cur;
+      }
+    }
+    // the rows are read by the other lanes of the wavefront (wavefront-synchronous exchange; the
+    // next tile's rows are written after this tile's MFMAs, which every lane reaches first)
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t i = tile * 16 + g + 4 * e;
-      double rho2 = 0.0, tt = 0.0;
-      if (i < n) radial_point(x_soa, ldx, i, d, geo, Reff, u0, u1, rho2, tt);
-      t[e] = tt;
+      const double rho2 = trow[(g + 4 * e) * TCS + 16 * NCT];
 #pragma unroll
       for (int a = 0; a < NRT; ++a) {
         const int k = a * 16 + li;
@@ -432,27 +453,6 @@ __global__ void __launch_bounds__(256) k_gram(const Tin* __restrict__ x_soa, int
         w[a][e] = pw;
       }
     }
-    // T_c(t) for c = b*16 + li: the recurrence of point g + 4 e runs once, in lane e of group g,
-    // and goes through LDS to the sixteen lanes that use it
-    double* trow = &tcs[wave][0];
-    if (li < 4) {
-      double tp = t[0];
-#pragma unroll
-      for (int e = 1; e < 4; ++e) tp = li == e ? t[e] : tp;
-      double tm1 = 1.0, t0 = tp;
-      double* dst = trow + (g + 4 * li) * TCS;
-#pragma unroll
-      for (int c = 0; c < 16 * NCT; ++c) {
-        double cur;
-        if (c == 0) cur = 1.0;
-        else if (c == 1) cur = tp;
-        else { cur = 2.0 * tp * t0 - tm1; tm1 = t0; t0 = cur; }
-        dst[c] = cur;
-      }
-    }
-    // the rows are read by the other lanes of the wavefront (wavefront-synchronous exchange; the
-    // next tile's rows are written after this tile's MFMAs, which every lane reaches first)
-    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int b = 0; b < NCT; ++b) {
       const int c = b * 16 + li;
