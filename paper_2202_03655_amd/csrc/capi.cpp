@@ -1067,7 +1067,10 @@ hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t
   std::vector<double> t1_all;
   std::vector<int32_t> t1_off(K + 1, 0);
   std::vector<int> refine;
-  for (int k = 0; k <= K; ++k) {
+  std::vector<char> needs_refine(K + 1, 0);
+  // the degrees are independent (host pool); the refinement list and the T1 table follow in
+  // degree order
+  hdf::parallel_for(K + 1, [&](int k) {
     const int L = K - k + 1;
     std::vector<double> G((size_t)L * L);
     for (int aa = 0; aa < L; ++aa)
@@ -1082,7 +1085,10 @@ hdf_status hdf_build_ex(const void* points, int dtype, int64_t n, int d, int64_t
     double lmax = 0.0;
     for (double v : f->deg[k].lam) lmax = std::max(lmax, std::fabs(v));
     const double est = eta1 * cond * (lmax > 0 ? f->tau / lmax : 1.0);
-    if (est > target) refine.push_back(k);
+    needs_refine[k] = est > target;
+  });
+  for (int k = 0; k <= K; ++k) {
+    if (needs_refine[k]) refine.push_back(k);
     t1_off[k] = (int32_t)t1_all.size();
     t1_all.insert(t1_all.end(), pcs[k].T1.begin(), pcs[k].T1.end());
   }

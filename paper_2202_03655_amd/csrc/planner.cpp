@@ -34,6 +34,9 @@
 #include <cstring>
 #include <stdexcept>
 #include <thread>
+#include <atomic>
+#include <condition_variable>
+#include <unistd.h>
 
 namespace hdf {
 
@@ -58,6 +61,83 @@ double kernel_dl(int kind, double r, double l) {
     case 3: { double z = std::sqrt(5.0) * r / l; return (z / 3.0) * (1.0 + z) * z * std::exp(-z) / l; }
   }
   return NAN;
+}
+
+// ---------------------------------------------------------------- host pool
+namespace {
+class Pool {
+ public:
+  explicit Pool(int n_workers) : pid_(getpid()) {
+    for (int i = 0; i < n_workers; ++i) workers_.emplace_back([this] { loop(); });
+  }
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : workers_) t.join();
+  }
+  void run(int n, const std::function<void(int)>& fn) {
+    if (workers_.empty() || getpid() != pid_) {
+      for (int i = 0; i < n; ++i) fn(i);
+      return;
+    }
+    std::lock_guard<std::mutex> serial(call_mu_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_.store(0);
+      finished_ = 0;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work(fn, n);
+    // every worker takes part in every generation, so none can be left behind on this one
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return finished_ == (int)workers_.size(); });
+    fn_ = nullptr;
+  }
+
+ private:
+  void work(const std::function<void(int)>& fn, int n) {
+    for (int i = next_.fetch_add(1); i < n; i = next_.fetch_add(1)) fn(i);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      const std::function<void(int)>* fn = fn_;
+      const int n = n_;
+      lk.unlock();
+      work(*fn, n);
+      lk.lock();
+      if (++finished_ == (int)workers_.size()) done_.notify_all();
+    }
+  }
+  const pid_t pid_;
+  std::vector<std::thread> workers_;
+  std::mutex mu_, call_mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)>* fn_ = nullptr;
+  std::atomic<int> next_{0};
+  int n_ = 0, finished_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+}  // namespace
+
+void parallel_for(int n, const std::function<void(int)>& fn) {
+  if (n <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  static Pool pool((int)std::min(8u, std::max(1u, std::thread::hardware_concurrency()) - 1));
+  pool.run(n, fn);
 }
 
 // ---------------------------------------------------------------- DCT-II
@@ -251,7 +331,8 @@ void radial_cores(const double* a, int p, int d, double u0, double u1,
   }
   const ld a0 = ((ld)u0 + (ld)u1) / 2, a1 = ((ld)u1 - (ld)u0) / 2;
   cores.assign(K + 1, std::vector<double>());
-  for (int k = 0; k <= K; ++k) {
+  // the degrees are independent: largest (k = 0) first
+  parallel_for(K + 1, [&](int k) {
     const int L = K - k + 1;
     // quadrature for int F^(k)(A - B t) (1 - t^2)^{k + alpha - 1/2} dt
     std::vector<ld> tq, wq;
@@ -315,7 +396,7 @@ void radial_cores(const double* a, int p, int d, double u0, double u1,
         double v = 0.5 * (M[(size_t)aa * L + bb] + M[(size_t)bb * L + aa]);
         M[(size_t)aa * L + bb] = M[(size_t)bb * L + aa] = v;
       }
-  }
+  });
 }
 
 // ------------------------------------------------------------ harmonics

@@ -3,6 +3,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace hdf {
@@ -100,6 +101,12 @@ void compress_degree_cross(int k, int L, const SqrtFactor& fx, const SqrtFactor&
 // of each group.  Returns false (outputs unspecified) if the inputs admit no placement.
 bool place_wave_items(const std::vector<int>& loads, int wg, int ns, std::vector<int>& order,
                       std::vector<int>& nw);
+// Runs fn(i) for every i in [0, n) on the calling thread and the workers of a process-wide
+// pool (at most 8, created on first use), each taking the next index from a shared counter;
+// returns when every call has returned.  The calls must be independent of each other and must
+// not call parallel_for.  Concurrent callers are served one after the other; in a process forked
+// after the pool started, everything runs on the calling thread.
+void parallel_for(int n, const std::function<void(int)>& fn);
 double tau_threshold(double tol, double nu, double N, int d, int p);
 
 // Tighter degree and rank selection (remark after Eq. bound).  The relative

@@ -1,6 +1,6 @@
-// Host-only driver of the planner under AddressSanitizer/UBSan: every table
-// size at the edges (K = 0, single-entry rows, d = 3..8), the core
-// quadrature, the Jacobi eigen/SVD routines and both compression routes.
+// Host-only driver of the planner under AddressSanitizer/UBSan (and ThreadSanitizer):
+// the host pool, every table size at the edges (K = 0, single-entry rows, d = 3..8), the
+// core quadrature, the Jacobi eigen/SVD routines and both compression routes.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -16,8 +16,29 @@ int main() {
       hdf::ChainCoeffs cc;
       hdf::chain_coeffs(d, K, cc);
     }
+  // the host pool: every index runs once, calls back to back, sizes around the worker count
+  for (int rep = 0; rep < 300; ++rep) {
+    const int n = rep % 41;
+    std::vector<int> hit(n, 0);
+    hdf::parallel_for(n, [&](int i) { hit[i] += 1; });
+    for (int i = 0; i < n; ++i)
+      if (hit[i] != 1) {
+        std::printf("pool: index %d of %d ran %d times\n", i, n, hit[i]);
+        return 1;
+      }
+  }
   std::vector<double> a(8192);
   hdf::chebyshev_coeffs(1, 2.0, 1.0, 8192, false, a.data());
+  {
+    // the cores of the degrees run on the pool: the same values on every call
+    std::vector<std::vector<double>> c1, c2;
+    hdf::radial_cores(a.data(), 20, 5, 0.1, 0.9, c1);
+    hdf::radial_cores(a.data(), 20, 5, 0.1, 0.9, c2);
+    if (c1 != c2) {
+      std::printf("radial cores differ between calls\n");
+      return 1;
+    }
+  }
   for (int d = 3; d <= 8; ++d)
     for (int p = 0; p <= 24; p += 2) {
       std::vector<std::vector<double>> cores;

@@ -1,4 +1,4 @@
-"""The host planner under AddressSanitizer and UBSan (g++, host code only):
+"""The host planner under AddressSanitizer and UBSan, and ThreadSanitizer (g++, host code only):
 table sizes at the edges, the core quadrature, the Jacobi eigen/SVD routines
 and both compression routes; the SVD reproduces a rectangular matrix."""
 import os
@@ -10,15 +10,16 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_planner_under_sanitizers(tmp_path):
+@pytest.mark.parametrize("sanitizers", ["address,undefined", "thread"])
+def test_planner_under_sanitizers(tmp_path, sanitizers):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
-    exe = tmp_path / "planner_asan"
+    exe = tmp_path / "planner_san"
     csrc = os.path.join(ROOT, "paper_2202_03655_amd", "csrc")
-    r = subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover",
+    r = subprocess.run([gxx, "-O1", "-g", "-std=c++17", f"-fsanitize={sanitizers}", "-fno-sanitize-recover",
                         "-I", csrc, os.path.join(ROOT, "tests", "native", "planner_asan_main.cpp"),
-                        os.path.join(csrc, "planner.cpp"), "-o", str(exe)],
+                        os.path.join(csrc, "planner.cpp"), "-o", str(exe), "-lpthread"],
                        stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     assert r.returncode == 0, r.stdout
     r = subprocess.run([str(exe)], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=300)
