@@ -88,12 +88,34 @@ struct OpAdd { __device__ double operator()(double a, double b) const { return a
 // Partial record per block: [0..7] min, [8..15] max, [16] nu2, [17] nonfinite.
 constexpr int kPrepRec = 18;
 
+// block_reduce of the 18 entries of a prep record at once (entries 0..7 min, 8..15 max, 16..17
+// sum): the same fixed tree per entry, with one barrier per level for all of them.
+__device__ __forceinline__ void block_reduce_rec(double (&v)[kPrepRec], double (*sh)[256]) {
+  const int t = threadIdx.x;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPrepRec; ++q) sh[q][t] = v[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int q = 0; q < kPrepRec; ++q) {
+        const double a = sh[q][t], b = sh[q][t + w];
+        sh[q][t] = q < 8 ? fmin(a, b) : (q < 16 ? fmax(a, b) : a + b);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kPrepRec; ++q) v[q] = sh[q][0];
+}
+
 template <typename Tin>
 __global__ void __launch_bounds__(256) k_prep_minmax(const Tin* __restrict__ pts, int64_t n, int d,
                                                       int64_t ld, Tin* __restrict__ x_soa,
                                                       int64_t ldx, int kind, double l,
                                                       double* __restrict__ part) {
-  __shared__ double sh[256];
+  __shared__ double shr[kPrepRec][256];
   double mn[8], mx[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) { mn[j] = INFINITY; mx[j] = -INFINITY; }
@@ -129,36 +151,39 @@ __global__ void __launch_bounds__(256) k_prep_minmax(const Tin* __restrict__ pts
     }
   }
   double* rec = part + (int64_t)blockIdx.x * kPrepRec;
-  for (int j = 0; j < 8; ++j) {
-    const double a = block_reduce(mn[j], sh, OpMin());
-    const double b = block_reduce(mx[j], sh, OpMax());
-    if (threadIdx.x == 0) { rec[j] = a; rec[8 + j] = b; }
+  double v[kPrepRec];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) { v[j] = mn[j]; v[8 + j] = mx[j]; }
+  v[16] = nu;
+  v[17] = nf;
+  block_reduce_rec(v, shr);
+  if (threadIdx.x < kPrepRec) {
+    double r = v[0];
+#pragma unroll
+    for (int q = 1; q < kPrepRec; ++q) r = threadIdx.x == q ? v[q] : r;
+    rec[threadIdx.x] = r;
   }
-  const double s1 = block_reduce(nu, sh, OpAdd());
-  const double s2 = block_reduce(nf, sh, OpAdd());
-  if (threadIdx.x == 0) { rec[16] = s1; rec[17] = s2; }
 }
 
 __global__ void __launch_bounds__(256) k_prep_fin1(const double* __restrict__ part, int nblk,
                                                     GeoDev* geo) {
-  __shared__ double sh[256];
-  for (int q = 0; q < kPrepRec; ++q) {
-    double v = (q < 8) ? INFINITY : (q < 16 ? -INFINITY : 0.0);
-    for (int b = threadIdx.x; b < nblk; b += 256) {
+  __shared__ double shr[kPrepRec][256];
+  double v[kPrepRec];
+#pragma unroll
+  for (int q = 0; q < kPrepRec; ++q) v[q] = (q < 8) ? INFINITY : (q < 16 ? -INFINITY : 0.0);
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+    for (int q = 0; q < kPrepRec; ++q) {
       const double x = part[(int64_t)b * kPrepRec + q];
-      v = (q < 8) ? fmin(v, x) : (q < 16 ? fmax(v, x) : v + x);
+      v[q] = (q < 8) ? fmin(v[q], x) : (q < 16 ? fmax(v[q], x) : v[q] + x);
     }
-    double r;
-    if (q < 8) r = block_reduce(v, sh, OpMin());
-    else if (q < 16) r = block_reduce(v, sh, OpMax());
-    else r = block_reduce(v, sh, OpAdd());
-    if (threadIdx.x == 0) {
-      if (q < 8) geo->c[q] = r;                   // min, combined below
-      else if (q < 16) geo->c[q - 8] = (geo->c[q - 8] + r) * 0.5;
-      else if (q == 16) geo->nu2_sum = r;
-      else geo->nonfinite = r;
-    }
-    __syncthreads();
+  }
+  block_reduce_rec(v, shr);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) geo->c[q] = (v[q] + v[8 + q]) * 0.5;   // centre of the bounding box
+    geo->nu2_sum = v[16];
+    geo->nonfinite = v[17];
   }
 }
 
