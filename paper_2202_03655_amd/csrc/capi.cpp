@@ -160,6 +160,11 @@ struct DevBuf {
   }
 };
 
+// A table inside a shared device buffer (the buffer owns the memory).
+struct DevView {
+  void* p = nullptr;
+};
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch())
@@ -208,7 +213,8 @@ struct hdf_factor {
   bool cross = false;
   int64_t N2 = 0, ldN2 = 0;
   std::vector<hdf::DegreeFactor> degy;            // deg[].E = Ey
-  DevBuf x_soa2, phi2, q2, q_coef2;
+  DevBuf x_soa2, phi2, q2;
+  DevView q_coef2;
   hdf::BuildTables tables2{};
   std::vector<hdf::DegDev> degs;                  // kept degrees
   std::vector<int> kept_k;
@@ -223,13 +229,15 @@ struct hdf_factor {
   bool mv_timed = false, adj_timed = false;
   bool time_products = true;                      // HIP events around the product's kernels
   // device storage
-  DevBuf x_soa, geo_dev, part, phi, q, col_of, chain, q_len, q_off, q_coef, degs_dev, tiles_dev,
-      lam_row, moments;
+  DevBuf x_soa, geo_dev, part, phi, q, tiles_dev, moments;
+  // tables of the factor evaluation (in build_tabs) and of the products (in prod_tabs), each
+  // set uploaded in one copy
+  DevBuf build_tabs, prod_tabs;
+  DevView col_of, chain, q_len, q_off, q_coef, degs_dev, lam_row, tile_tabs, degs_by_k;
   int n_tiles = 0, tiles_cpl = 0;                 // pass-1 work items for cpl = m16/16
   // tile-major pass 1 (m16 <= 64): wave items and their workgroup groups for each cpl = m16 / 16
   // in 1..4, built with the factor; tile_tabs holds all wave items, then all groups, then the
   // rank-row table
-  DevBuf tile_tabs;
   int tw_off[5] = {0, 0, 0, 0, 0}, tg_off[5] = {0, 0, 0, 0, 0}, n_tgroups[5] = {0, 0, 0, 0, 0};
   size_t tg_base = 0;                             // byte offset of the groups in tile_tabs
   size_t rr_base = 0;                             // byte offset of the rank-row table in tile_tabs
@@ -238,7 +246,7 @@ struct hdf_factor {
   // host copies of the pass-1 tables: they outlive their asynchronous uploads
   std::vector<hdf::TileDev> tiles_host;
   // matvec / adjoint workspace
-  DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW, degs_by_k;
+  DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW;
   DevBuf cphi, cq;                                // matrix-free chunk scratch
   // adjoint (dF/dX by contractions): the loop-order row table, q' = dq/d(rho^2) rows and their
   // coefficients, the shifted-factor degree table (harmonics of k - 1 with radial rows of k), the
@@ -776,7 +784,26 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       f->host_keep.emplace_back((const char*)src, (const char*)src + bytes);
       return hipMemcpyAsync(b.p, f->host_keep.back().data(), bytes, hipMemcpyHostToDevice, s);
     };
-    HIPCHK(upload(f->col_of, col_of.data(), col_of.size() * sizeof(int32_t)));
+    // several tables packed (256-byte aligned) into one device buffer with one copy
+    struct Batch {
+      std::vector<char> host;
+      std::vector<std::pair<DevView*, size_t>> parts;
+      void add(DevView& v, const void* src, size_t bytes) {
+        const size_t off = (host.size() + 255) / 256 * 256;
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, src, bytes);
+        parts.push_back({&v, off});
+      }
+    };
+    auto upload_batch = [&](DevBuf& b, Batch& batch) -> hipError_t {
+      hipError_t e = b.ensure(std::max<size_t>(batch.host.size(), 256));
+      if (e != hipSuccess) return e;
+      for (auto& pr : batch.parts) pr.first->p = (char*)b.p + pr.second;
+      f->host_keep.emplace_back(std::move(batch.host));
+      return hipMemcpyAsync(b.p, f->host_keep.back().data(), f->host_keep.back().size(), hipMemcpyHostToDevice, s);
+    };
+    Batch bt;
+    bt.add(f->col_of, col_of.data(), col_of.size() * sizeof(int32_t));
     // recurrence coefficients as (A, B) pairs in the storage type
     hdf::ChainCoeffs cc;
     hdf::chain_coeffs(d, Kh, cc);
@@ -797,18 +824,20 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
         }
       }
     }
-    auto upload_typed = [&](DevBuf& b, const std::vector<double>& v) -> hipError_t {
+    auto add_typed = [&](DevView& v, const std::vector<double>& x) {
       if (f->fprec == 1) {
-        std::vector<float> tmp(v.begin(), v.end());
-        return upload(b, tmp.data(), tmp.size() * 4);
+        std::vector<float> tmp(x.begin(), x.end());
+        bt.add(v, tmp.data(), tmp.size() * 4);
+      } else {
+        bt.add(v, x.data(), x.size() * 8);
       }
-      return upload(b, v.data(), v.size() * 8);
     };
-    HIPCHK(upload_typed(f->chain, pd));
-    HIPCHK(upload_typed(f->q_coef, qc));
-    if (f->cross) HIPCHK(upload_typed(f->q_coef2, qc2));
-    HIPCHK(upload(f->q_len, ql.data(), ql.size() * 4));
-    HIPCHK(upload(f->q_off, qo.data(), qo.size() * 4));
+    add_typed(f->chain, pd);
+    add_typed(f->q_coef, qc);
+    if (f->cross) add_typed(f->q_coef2, qc2);
+    bt.add(f->q_len, ql.data(), ql.size() * 4);
+    bt.add(f->q_off, qo.data(), qo.size() * 4);
+    HIPCHK(upload_batch(f->build_tabs, bt));
     hdf::BuildTables tb{};
     tb.col_of = (const int32_t*)f->col_of.p;
     tb.chain = f->chain.p;
@@ -851,10 +880,12 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
       std::vector<hdf::DegDev> dbk(K + 1);
       for (int k = 0; k <= K; ++k) { dbk[k] = hdf::DegDev{}; }
       for (size_t di = 0; di < f->degs.size(); ++di) dbk[f->kept_k[di]] = f->degs[di];
-      HIPCHK(upload(f->degs_dev, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev)));
-      HIPCHK(upload(f->tile_tabs, tabs.data(), tabs.size()));
-      HIPCHK(upload(f->lam_row, lr.data(), lr.size() * 8));
-      HIPCHK(upload(f->degs_by_k, dbk.data(), dbk.size() * sizeof(hdf::DegDev)));
+      Batch bp;
+      bp.add(f->degs_dev, f->degs.data(), f->degs.size() * sizeof(hdf::DegDev));
+      bp.add(f->tile_tabs, tabs.data(), tabs.size());
+      bp.add(f->lam_row, lr.data(), lr.size() * 8);
+      bp.add(f->degs_by_k, dbk.data(), dbk.size() * sizeof(hdf::DegDev));
+      HIPCHK(upload_batch(f->prod_tabs, bp));
       return HDF_OK;
     };
     if (mfree) {                                // evaluated in every product
