@@ -220,6 +220,7 @@ struct hdf_factor {
   std::vector<int> kept_k;
   std::vector<int32_t> index_table;               // H x (d-1)
   int64_t H = 0, S = 0, r = 0;
+  int64_t n_wblocks = 0;                          // blocks of pass 2's batch-major copy of D W
   int max_s = 0;
   int n_refined = 0;                              // degrees refined by the second Gram pass
   double t_prep = 0, t_plan = 0, t_gram = 0, t_compress = 0, t_finish = 0, t_build = -1;
@@ -246,7 +247,7 @@ struct hdf_factor {
   // host copies of the pass-1 tables: they outlive their asynchronous uploads
   std::vector<hdf::TileDev> tiles_host;
   // matvec / adjoint workspace
-  DevBuf ws_part, ws_W, ws_Wd, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW;
+  DevBuf ws_part, ws_W, ws_Wd, ws_Wb, ws_n, bw_GV, bw_GVd, bw_GW, bw_GWd, bw_VW;
   DevBuf cphi, cq;                                // matrix-free chunk scratch
   // adjoint (dF/dX by contractions): the loop-order row table, q' = dq/d(rho^2) rows and their
   // coefficients, the shifted-factor degree table (harmonics of k - 1 with radial rows of k), the
@@ -669,7 +670,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
   const int prec = f->fprec;
   const int64_t n = f->N;
   // kept degrees, offsets, tables
-  int64_t hoff = 0, qoff = 0, roff = 0;
+  int64_t hoff = 0, qoff = 0, roff = 0, boff = 0;
   std::unordered_map<uint64_t, int> canon;
   for (int k = 0; k <= K; ++k) {
     const hdf::DegreeFactor& df = f->deg[k];
@@ -677,6 +678,8 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     const int64_t nh = hdf::index_count(d, k);
     hdf::DegDev dd{};
     dd.hoff = (int32_t)hoff; dd.nh = (int32_t)nh; dd.qoff = (int32_t)qoff; dd.s = df.s; dd.roff = (int32_t)roff;
+    dd.boff = (int32_t)boff;
+    boff += (nh + 15) / 16 * df.s;
     f->degs.push_back(dd);
     f->kept_k.push_back(k);
     std::vector<int32_t> tab;
@@ -693,7 +696,7 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     roff += nh * df.s;
     f->max_s = std::max(f->max_s, df.s);
   }
-  f->H = hoff; f->S = qoff; f->r = roff;
+  f->H = hoff; f->S = qoff; f->r = roff; f->n_wblocks = boff;
   f->t_compress = now_ms() - t0;
   timer.t = now_ms();
 
@@ -1645,8 +1648,16 @@ static hdf_status pass2(hdf_handle h, const void* phi, const void* q, int64_t ld
     }
   }
   if (nz > 1) HIPCHK(h->ws_n.ensure((size_t)nz * n * m * el));
+  // one pass over the points: D W in batch-major order, four rows per lane in one load
+  const void* Wb = nullptr;
+  if (nz == 1) {
+    HIPCHK(h->ws_Wb.ensure((size_t)h->n_wblocks * 16 * m16 * el));
+    HIPCHK(hdf::launch_wd_batches((const hdf::DegDev*)h->degs_dev.p, (int)h->degs.size(), h->ws_Wd.p, m16,
+                                  h->n_wblocks, h->ws_Wb.p, h->fprec, s));
+    Wb = h->ws_Wb.p;
+  }
   HIPCHK(hdf::launch_matvec_n(phi, ld, q, ld, (const hdf::DegDev*)h->degs_dev.p, (int)h->degs.size(), h->max_s,
-                              h->ws_Wd.p, m16, KV, ldkv, n, (int)m, h->fprec, h->dtype, nz > 1 ? hchunk : 0, nz,
+                              h->ws_Wd.p, Wb, m16, KV, ldkv, n, (int)m, h->fprec, h->dtype, nz > 1 ? hchunk : 0, nz,
                               nz > 1 ? h->ws_n.p : nullptr, s));
   return HDF_OK;
 }
@@ -1758,8 +1769,8 @@ hdf_status hdf_matvec_noalloc(hdf_handle h, const void* V, int64_t m, int64_t ld
                                    h->fprec, h->dtype, s));
   HIPCHK(hdf::launch_matvec_reduce(part, n_splits, h->r, m16, (const double*)h->lam_row.p, W, Wd, h->fprec, s));
   HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
-                              (int)h->degs.size(), h->max_s, Wd, m16, KV, ldkv, h->N, (int)m, h->fprec, h->dtype, 0,
-                              1, nullptr, s));
+                              (int)h->degs.size(), h->max_s, Wd, nullptr, m16, KV, ldkv, h->N, (int)m, h->fprec,
+                              h->dtype, 0, 1, nullptr, s));
   return HDF_OK;
 }
 
@@ -1890,10 +1901,11 @@ static hdf_status adjoint_dx(hdf_handle h, const double* gv, const double* gw, i
   HIPCHK(hipEventRecord(h->ev_adj[0], s));
   // U' [Gv | Gw] and the shifted factor times [G^(j)T Gv | G^(j)T Gw] (pass-2 kernel, one chunk)
   HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->dq.p, h->ldN, (const hdf::DegDev*)h->degs_dev.p,
-                              (int)h->degs.size(), h->max_s, h->adj_c2.p, c2s, h->adj_kv2.p, m2, h->N, m2, h->fprec,
-                              io, 0, 1, nullptr, s));
+                              (int)h->degs.size(), h->max_s, h->adj_c2.p, nullptr, c2s, h->adj_kv2.p, m2, h->N, m2,
+                              h->fprec, io, 0, 1, nullptr, s));
   HIPCHK(hdf::launch_matvec_n(h->phi.p, h->ldN, h->q.p, h->ldN, (const hdf::DegDev*)h->adj_degs.p, Kh, h->max_s,
-                              h->adj_cs.p, css, h->adj_kvs.p, md2, h->N, md2, h->fprec, io, 0, 1, nullptr, s));
+                              h->adj_cs.p, nullptr, css, h->adj_kvs.p, md2, h->N, md2, h->fprec, io, 0, 1, nullptr,
+                              s));
   HIPCHK(hdf::launch_adj_combine(h->x_soa.p, h->dtype, h->ldN, h->N, d, (const hdf::GeoDev*)h->geo_dev.p,
                                  h->adj_kvs.p, md2, h->adj_kv2.p, m2, Wm, Vm, ld, m, dX, lddx, h->fprec, s));
   HIPCHK(hipEventRecord(h->ev_adj[1], s));

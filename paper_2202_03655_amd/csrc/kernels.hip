@@ -1522,11 +1522,13 @@ __global__ void k_mv_reduce(const double* __restrict__ part, int n_splits, int64
 // With hchunk > 0 (few points, many harmonics) blockIdx.z takes the harmonic
 // rows [z hchunk, (z+1) hchunk) only and writes its share of KV to
 // part[z][n][m]; k_mv_n_sum adds the shares in z order.
+// With Wb (and hchunk == 0) the rows of D W come from its batch-major copy (k_wd_batches): the four
+// values a lane needs for one radial function of a batch are one 16-byte (32-byte) load.
 template <typename T, typename TO>
 __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t ld_phi,
                                               const T* __restrict__ q, int64_t ld_q,
                                               const DegDev* __restrict__ degs, int n_deg,
-                                              const T* __restrict__ Wd, int m16,
+                                              const T* __restrict__ Wd, const T* __restrict__ Wb, int m16,
                                               TO* __restrict__ KV, int64_t ldkv, int64_t n, int m,
                                               int hchunk, T* __restrict__ part) {
   typedef typename Mfma<T>::V Acc;
@@ -1571,6 +1573,21 @@ __global__ void __launch_bounds__(64) k_mv_n(const T* __restrict__ phi, int64_t 
     // radial values of function l at this lane's points and the batch's rows of D W for l
     auto load_l = [&](int hb, int l, T (&ql)[4], T (&bw)[KB]) {
       load4(q + (int64_t)(dg.qoff + l) * ld_q, ql);
+      if (Wb) {                                     // uniform
+        // block (batch hb / 16, radial function l) of the degree, column tile blockIdx.y
+        const T* src = Wb + (((int64_t)dg.boff + (hb >> 4) * dg.s + l) * (m16 >> 4) + blockIdx.y) * 256 +
+                       (g * 16 + li) * KB;
+        if constexpr (sizeof(T) == 4) {
+          const floatx4 w = *reinterpret_cast<const floatx4*>(src);
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) bw[kb] = w[kb];
+        } else {
+          const doublex2 w0 = *reinterpret_cast<const doublex2*>(src);
+          const doublex2 w1 = *reinterpret_cast<const doublex2*>(src + 2);
+          bw[0] = w0[0]; bw[1] = w0[1]; bw[2] = w1[0]; bw[3] = w1[1];
+        }
+        return;
+      }
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         const int hh = hb + 4 * kb + g;
@@ -1682,12 +1699,47 @@ hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t ra
   return hipGetLastError();
 }
 
+// Batch-major copy of D W for pass 2: block B = boff_k + b s_k + l of degree k holds, for batch b
+// (harmonics 16 b .. 16 b + 15) and radial function l, every 16-column tile ct as 256 values in
+// the order (lane g 16 + c, K-step kb) with harmonic 16 b + 4 kb + g and column 16 ct + c; rows past
+// the degree's harmonics are zero.  boff_k is DegDev::boff.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wd_batches(const DegDev* __restrict__ degs, int n_deg,
+                                                     const T* __restrict__ Wd, int m16, int64_t n_blocks,
+                                                     T* __restrict__ Wb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int ncts = m16 >> 4;
+  if (e >= n_blocks * ncts * 256) return;
+  const int64_t blk = e / (ncts * 256);
+  const int rest = (int)(e - blk * ncts * 256);
+  const int ct = rest >> 8, lane = (rest >> 2) & 63, kb = rest & 3;
+  const int g = lane >> 4, c = lane & 15;
+  int di = 0;
+  while (di + 1 < n_deg && degs[di + 1].boff <= blk) ++di;
+  const DegDev dg = degs[di];
+  const int64_t rel = blk - dg.boff;
+  const int b = (int)(rel / dg.s), l = (int)(rel - (int64_t)b * dg.s);
+  const int hh = 16 * b + 4 * kb + g;
+  Wb[e] = hh < dg.nh ? Wd[(int64_t)(dg.roff + hh * dg.s + l) * m16 + 16 * ct + c] : (T)0;
+}
+
+hipError_t launch_wd_batches(const DegDev* degs, int n_deg, const void* Wd, int m16, int64_t n_blocks, void* Wb,
+                             int prec, hipStream_t s) {
+  if (m16 < 16 || m16 % 16 || n_blocks < 1 || n_deg < 1) return hipErrorInvalidValue;
+  const int64_t total = n_blocks * (m16 / 16) * 256;
+  const unsigned nb = (unsigned)((total + 255) / 256);
+  if (prec == 1) k_wd_batches<float><<<nb, 256, 0, s>>>(degs, n_deg, (const float*)Wd, m16, n_blocks, (float*)Wb);
+  else k_wd_batches<double><<<nb, 256, 0, s>>>(degs, n_deg, (const double*)Wd, m16, n_blocks, (double*)Wb);
+  return hipGetLastError();
+}
+
 hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
-                           const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
+                           const DegDev* degs, int n_deg, int max_s, const void* Wd, const void* Wb, int m16,
                            void* KV, int64_t ldkv, int64_t n, int m, int prec, int io, int hchunk, int nz,
                            void* part, hipStream_t s) {
   (void)max_s;
   if (nz < 1 || (nz > 1 && (hchunk <= 0 || !part))) return hipErrorInvalidValue;
+  if (Wb && nz > 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)(m16 / 16), (unsigned)nz);
   const int hc = nz > 1 ? hchunk : 0;
   const unsigned nb = (unsigned)((n * m + 255) / 256);
@@ -1695,7 +1747,7 @@ hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64
   do {                                                                                                       \
     T* dst = nz > 1 ? (T*)part : nullptr;                                                                    \
     k_mv_n<T, TO><<<grid, 64, 0, s>>>((const T*)phi, ld_phi, (const T*)q, ld_q, degs, n_deg, (const T*)Wd,  \
-                                      m16, (TO*)KV, ldkv, n, m, hc, dst);                                    \
+                                      (const T*)Wb, m16, (TO*)KV, ldkv, n, m, hc, dst);                      \
     if (nz > 1) k_mv_n_sum<T, TO><<<nb, 256, 0, s>>>((const T*)part, nz, n, m, (TO*)KV, ldkv);               \
   } while (0)
   if (prec == 1 && io == 0) HDF_MVN(float, float);

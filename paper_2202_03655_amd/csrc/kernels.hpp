@@ -79,7 +79,8 @@ struct DegDev {
   int32_t qoff;   // first radial row in q
   int32_t s;      // s_k
   int32_t roff;   // first rank row (k, h=0, l=0)
-  int32_t pad[3];
+  int32_t boff;   // first block of the degree in pass 2's batch-major copy of D W
+  int32_t pad[2];
 };
 struct TileDev {
   int32_t deg;    // index into DegDev
@@ -143,6 +144,10 @@ hipError_t launch_matvec_t_tile(const void* phi, int64_t ld_phi, const void* q, 
                                 int n_groups, int n_splits,
                                 int64_t split_len, const void* V, int64_t ldv, int64_t n, int m, int m16,
                                 int64_t rank, double* partials, int prec, int io, hipStream_t s);
+// Batch-major copy Wb of Wd for pass 2 (n_blocks = sum over degrees of ceil(nh / 16) s; the
+// degrees' block offsets in DegDev::boff): 16 m16 values per block.
+hipError_t launch_wd_batches(const DegDev* degs, int n_deg, const void* Wd, int m16, int64_t n_blocks, void* Wb,
+                             int prec, hipStream_t s);
 // Reduce over splits: W[row][c] = sum_split partial (binary64) and
 // Wd[row][c] = lambda_row * W (storage type) for pass 2.
 hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t rank, int m16,
@@ -151,8 +156,9 @@ hipError_t launch_matvec_reduce(const double* partials, int n_splits, int64_t ra
 // Pass 2: KV[i][c] = sum_rows U[i,row] Wd[row][c].
 // nz > 1: harmonic rows split into nz chunks of hchunk rows, each chunk's share
 // of KV in part (nz x n x m, storage type), summed in chunk order into KV
+// Wb: optional batch-major copy of Wd (launch_wd_batches; nz == 1 only), read instead of Wd.
 hipError_t launch_matvec_n(const void* phi, int64_t ld_phi, const void* q, int64_t ld_q,
-                           const DegDev* degs, int n_deg, int max_s, const void* Wd, int m16,
+                           const DegDev* degs, int n_deg, int max_s, const void* Wd, const void* Wb, int m16,
                            void* KV, int64_t ldkv, int64_t n, int m, int prec, int io, int hchunk, int nz,
                            void* part, hipStream_t s);
 

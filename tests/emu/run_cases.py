@@ -370,7 +370,18 @@ def case_noalloc():
         check(f"noalloc n={len(X)} m={m} {dt}", st == 0 and e <= bound, f"status {st}, {e:.2e}")
 
 
-CASES = {"noalloc": case_noalloc, "fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
+def case_passtwo():
+    """Pass 2 over enough points for one pass (no harmonic split): D W in batch-major order."""
+    n, m = 16500, 48
+    X = wl.uniform_cube(n, 3, 301)
+    st = ohdf.build(X, "gaussian", 0.8, 1e-6)
+    f = hdf.Factor(to_dev(X, torch.float64), "gaussian", 0.8, 1e-6, precision=hdf.HDF_FP64)
+    V = wl.rhs(n, m, 5)
+    e = rel(f.matvec(to_dev(V, torch.float64)).numpy(), ohdf.matvec(st, V))
+    check(f"pass 2 one pass n={n} m={m}", e <= 1e-12, f"{e:.2e}")
+
+
+CASES = {"noalloc": case_noalloc, "passtwo": case_passtwo, "fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
          "krr": case_krr, "mfree": case_mfree}
 
 if __name__ == "__main__":
