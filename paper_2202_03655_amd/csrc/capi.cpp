@@ -346,16 +346,17 @@ static hipError_t clear_padding(void* base, int64_t rows, int64_t n, int64_t ld,
 // Every item loads the same bytes (its 16 rows of the harmonics) while its MFMA work grows with its
 // radial functions, and the low degrees have the most of them.  The waves of a group synchronise
 // once per chunk and waves w and w + 4 share a SIMD, so the busiest SIMD of a group sets the pace
-// of its chunk loop.  When all radial rows fit one group's staging:
-//  - the harmonics of a degree that do not fill a 16-row tile (a degree's last rows, or all of a
+// of its chunk loop.
+//  - The harmonics of a degree that do not fill a 16-row tile (a degree's last rows, or all of a
 //    degree with fewer than 16) are not padded: their rank rows (harmonic, radial function) are
-//    pooled over the degrees and cut into rank-row items of 16 rows (MvtRankRow), one accumulator
-//    tile per column tile, instead of a partly empty tile per radial function;
-//  - items of one column tile are cut to at most kMvtSplitAcc radial functions;
-//  - hdf::place_wave_items places the items so that the waves of each SIMD and the groups carry
-//    about equal numbers of accumulator tiles.
-// Otherwise the groups are runs of consecutive items.  rr receives the rank-row table (the same for
-// every cpl).
+//    pooled over the degrees and cut into rank-row items of up to 16 rows (MvtRankRow) whose
+//    radial rows span at most kMvtMaxNq rows, one accumulator tile per column tile, instead of a
+//    partly empty tile per radial function.
+//  - When all radial rows fit one group's staging, items of one column tile are cut to at most
+//    kMvtSplitAcc radial functions and hdf::place_wave_items places the items so that the waves of
+//    each SIMD and the groups carry about equal numbers of accumulator tiles.  Otherwise the items,
+//    ordered by their first radial row, form runs of consecutive items.
+// rr receives the rank-row table (the same for every cpl).
 constexpr int kMvtSplitAcc = 3;
 static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl, std::vector<hdf::MvtWave>& tw,
                         std::vector<hdf::MvtGroup>& tg, std::vector<hdf::MvtRankRow>& rr) {
@@ -371,10 +372,11 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
   const int nl_cap = spread && nct_t == 1 ? std::min(nlmax, kMvtSplitAcc) : nlmax;
   const int w_base = (int)tw.size();
   std::vector<hdf::MvtRankRow> pool;
+  std::vector<std::pair<int, int>> qr;            // radial rows [lo, hi) of each item (host only)
   for (const hdf::DegDev& dg : degs)
     for (int h0 = 0; h0 < dg.nh; h0 += 16) {
       const int nr = std::min(16, dg.nh - h0);
-      if (spread && nr < 16) {
+      if (nr < 16) {
         for (int h = h0; h < dg.nh; ++h)
           for (int l = 0; l < dg.s; ++l) pool.push_back(hdf::MvtRankRow{dg.hoff + h, dg.qoff + l, dg.roff + h * dg.s + l, 0});
         continue;
@@ -390,19 +392,32 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
         w.out0 = dg.roff + h0 * dg.s + l0;
         w.s = dg.s;
         tw.push_back(w);
+        qr.push_back({w.qrow, w.qrow + w.nl});
       }
     }
   if (!pool.empty()) {
     if (rr.empty()) rr = pool;
-    for (size_t r0 = 0; r0 < pool.size(); r0 += 16) {
+    // items of up to 16 consecutive pooled rows whose radial rows span at most kMvtMaxNq
+    for (size_t r0 = 0; r0 < pool.size();) {
+      int lo = pool[r0].qrow, hi = pool[r0].qrow + 1;
+      size_t r1 = r0 + 1;
+      while (r1 < pool.size() && r1 - r0 < 16) {
+        const int lo2 = std::min(lo, pool[r1].qrow), hi2 = std::max(hi, pool[r1].qrow + 1);
+        if (hi2 - lo2 > hdf::kMvtMaxNq) break;
+        lo = lo2;
+        hi = hi2;
+        ++r1;
+      }
       hdf::MvtWave w{};
       w.row0 = (int32_t)r0;
-      w.nr = (int32_t)std::min<size_t>(16, pool.size() - r0);
+      w.nr = (int32_t)(r1 - r0);
       w.qrow = -1;
       w.nl = 1;
       w.ct0 = 0;
       w.nct = cpl;
       tw.push_back(w);
+      qr.push_back({lo, hi});
+      r0 = r1;
     }
   }
   const int n_items = (int)tw.size() - w_base;
@@ -431,19 +446,31 @@ static void tile_tables(const std::vector<hdf::DegDev>& degs, int fprec, int cpl
     }
     return;
   }
-  for (size_t i = (size_t)w_base; i < tw.size();) {
+  // items in order of their first radial row (the rank-row items join the tiles of their degrees),
+  // then runs of consecutive items whose radial rows span at most kMvtMaxNq rows
+  std::vector<int> by_q(n_items);
+  for (int i = 0; i < n_items; ++i) by_q[i] = i;
+  std::stable_sort(by_q.begin(), by_q.end(), [&](int a, int b) { return qr[a].first < qr[b].first; });
+  std::vector<hdf::MvtWave> sorted;
+  std::vector<std::pair<int, int>> sorted_qr;
+  for (int i : by_q) {
+    sorted.push_back(tw[w_base + i]);
+    sorted_qr.push_back(qr[i]);
+  }
+  std::copy(sorted.begin(), sorted.end(), tw.begin() + w_base);
+  for (int i = 0; i < n_items;) {
     hdf::MvtGroup gr{};
-    gr.w0 = (int32_t)(i - (size_t)w_base);
-    int lo = tw[i].qrow, hi = tw[i].qrow + tw[i].nl;
-    size_t j = i + 1;
-    while (j < tw.size() && j - i < (size_t)hdf::kMvtWavesPerGroup) {
-      const int lo2 = std::min(lo, tw[j].qrow), hi2 = std::max(hi, tw[j].qrow + tw[j].nl);
+    gr.w0 = i;
+    int lo = sorted_qr[i].first, hi = sorted_qr[i].second;
+    int j = i + 1;
+    while (j < n_items && j - i < hdf::kMvtWavesPerGroup) {
+      const int lo2 = std::min(lo, sorted_qr[j].first), hi2 = std::max(hi, sorted_qr[j].second);
       if (hi2 - lo2 > hdf::kMvtMaxNq) break;
       lo = lo2;
       hi = hi2;
       ++j;
     }
-    gr.nw = (int32_t)(j - i);
+    gr.nw = j - i;
     gr.q_lo = lo;
     gr.nq = hi - lo;
     tg.push_back(gr);

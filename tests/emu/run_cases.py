@@ -381,7 +381,18 @@ def case_passtwo():
     check(f"pass 2 one pass n={n} m={m}", e <= 1e-12, f"{e:.2e}")
 
 
-CASES = {"noalloc": case_noalloc, "passtwo": case_passtwo, "fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
+def case_grouped():
+    """More radial rows than one workgroup stages (S = 91): pooled rank-row items in runs of items."""
+    n, m = 3000, 5
+    X = wl.unit_ball(n, 3, 401)
+    st = ohdf.build(X, "gaussian", 0.5, 1e-10)
+    f = hdf.Factor(to_dev(X, torch.float64), "gaussian", 0.5, 1e-10, precision=hdf.HDF_FP64)
+    V = wl.rhs(n, m, 5)
+    e = rel(f.matvec(to_dev(V, torch.float64)).numpy(), ohdf.matvec(st, V))
+    check(f"grouped pass 1 S={f.info()['n_radial']} m={m}", e <= 1e-12, f"{e:.2e}")
+
+
+CASES = {"noalloc": case_noalloc, "passtwo": case_passtwo, "grouped": case_grouped, "fp64": case_fp64, "mixed": case_mixed, "cross": case_cross, "tiny": case_tiny, "sampled": case_sampled,
          "krr": case_krr, "mfree": case_mfree}
 
 if __name__ == "__main__":
