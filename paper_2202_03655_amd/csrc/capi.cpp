@@ -570,7 +570,16 @@ static bool mf_tables(hdf_factor* f, const std::vector<int32_t>& col_of, std::ve
   for (auto& j : jl) jc.push_back({cost(j), j});
   std::stable_sort(jc.begin(), jc.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
   std::vector<std::vector<hdf::MfJob>> per(hdf::kMfWaves);
+  // besides its jobs, evaluating wavefront w forms the radial tiles w, w + 8, ... (one MFMA chain of
+  // L_pad / 4 steps each) and the subtree prefixes of the entries 64 w + 512 i < 16 (K + 1) (one
+  // serial recurrence of about K + 1 steps each), all before the same barrier: their latencies
+  // enter its load, in the cost units above (measured on the headline workload: a radial tile
+  // about 6 units per step, a prefix entry about 3.5 units per recurrence step)
   std::vector<double> load(hdf::kMfWaves, 0.0);
+  for (int w = 0; w < hdf::kMfWaves; ++w) {
+    for (int tl = w; tl < f->mf_spad / 16; tl += hdf::kMfWaves) load[w] += 6.0 * (f->mf_lpad / 4) + 2.0;
+    for (int e = 64 * w; e < 16 * (K + 1); e += 64 * hdf::kMfWaves) load[w] += 3.5 * (K + 1);
+  }
   for (auto& e : jc) {
     const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     per[w].push_back(e.second);
@@ -838,7 +847,8 @@ static hdf_status finish_build(hdf_factor* f, double t0, hipStream_t s) {
     hdf::ChainCoeffs cc;
     hdf::chain_coeffs(d, Kh, cc);
     const size_t npair = cc.A.size();
-    std::vector<double> pd(2 * npair + 2, 0.0);     // one pad pair: the adjoint reads one ahead
+    // eight pad pairs: the adjoint reads one pair ahead, the fused passes whole blocks of pairs
+    std::vector<double> pd(2 * npair + 16, 0.0);
     for (size_t i = 0; i < npair; ++i) { pd[2 * i] = cc.A[i]; pd[2 * i + 1] = cc.B[i]; }
     std::vector<int32_t> ql, qo;
     std::vector<double> qc, qc2;

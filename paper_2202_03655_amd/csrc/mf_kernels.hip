@@ -83,18 +83,21 @@ struct MfChainS {
                                              const HDF_MF_CONST T* __restrict__ chain, T* __restrict__ phc,
                                              int (&out)[NB], const T (&pre)[NB]) {
     const HDF_MF_CONST T* cf = chain + 2 * ((LEVEL - 1) * (K + 1) + b) * (K + 1);   // (A, B) pairs
-    T pm1 = 0, p = cf[0];
+    // the pair of index nn + 1 is loaded before the levels below index nn run, so that its wait
+    // is the one those levels take for their own first block of pairs
+    T pm1 = 0, p = cf[0], ca = cf[2], cb = cf[3];
     MfChainS<T, D, LEVEL - 1, NB>::run(xt, r2, b, rem, s * p, K, chain, phc, out, pre);
-    if (rem >= 1) {
-      pm1 = p;
-      p = cf[2] * xt[LEVEL - 1];
-      MfChainS<T, D, LEVEL - 1, NB>::run(xt, r2, b + 1, rem - 1, s * p, K, chain, phc, out, pre);
-    }
-    for (int nn = 2; nn <= rem; ++nn) {
-      const T ca = cf[2 * nn], cb = cf[2 * nn + 1];
-      const T pn = ca * xt[LEVEL - 1] * p - cb * r2[LEVEL - 1] * pm1;
-      pm1 = p;
-      p = pn;
+    for (int nn = 1; nn <= rem; ++nn) {
+      if (nn == 1) {
+        pm1 = p;
+        p = ca * xt[LEVEL - 1];
+      } else {
+        const T pn = ca * xt[LEVEL - 1] * p - cb * r2[LEVEL - 1] * pm1;
+        pm1 = p;
+        p = pn;
+      }
+      ca = cf[2 * nn + 2];
+      cb = cf[2 * nn + 3];
       MfChainS<T, D, LEVEL - 1, NB>::run(xt, r2, b + nn, rem - nn, s * p, K, chain, phc, out, pre);
     }
   }
@@ -112,67 +115,81 @@ struct MfChainS<T, D, 1, NB> {
 #pragma unroll
     for (int k = 0; k < NB; ++k) out[k] += n * kMfP;
   }
+  // pairs of the chain read in blocks of kMfPairs (one scalar load and one wait per block; the
+  // table is padded so that a block may run past the last row)
+  static constexpr int kMfPairs = sizeof(T) == 4 ? 8 : 4;
+  static __device__ __forceinline__ void load(const HDF_MF_CONST T* __restrict__ cf, T (&c)[2 * kMfPairs]) {
+#pragma unroll
+    for (int i = 0; i < 2 * kMfPairs; ++i) c[i] = cf[i];
+  }
   static __device__ __forceinline__ void run(const T (&xt)[D], const T (&r2)[D], int b, int rem, T s, int K,
                                              const HDF_MF_CONST T* __restrict__ chain, T* __restrict__ phc,
                                              int (&out)[NB], const T (&pre)[NB]) {
     const HDF_MF_CONST T* cf = chain + 2 * b * (K + 1);
     const T x = xt[0], rr = r2[0];
-    T pm1 = 0, p = cf[0];
-    emit(phc, out, pre, s * p, 0);
-    step(out, 1);
-    if (rem >= 1) {
-      pm1 = p;
-      p = cf[2] * x;
-      emit(phc, out, pre, s * p, 0);
-      step(out, 1);
-    }
-    // four harmonics per round: one wait for four pairs, LDS stores at immediate offsets
-    int nn = 2;
-    for (; nn + 3 <= rem; nn += 4) {
-      T ca[4], cb[4];
+    T c[2 * kMfPairs];
+    load(cf, c);
+    // harmonics 0 and 1; p and pm1 are read below only when rem >= 2
+    T pm1 = c[0], p = c[2] * x;
+    emit(phc, out, pre, s * pm1, 0);
+    if (rem >= 1) emit(phc, out, pre, s * p, 1);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ca[u] = cf[2 * (nn + u)];
-        cb[u] = cf[2 * (nn + u) + 1];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const T pn = ca[u] * x * p - cb[u] * rr * pm1;
+    for (int u = 2; u < kMfPairs; ++u) {
+      if (u <= rem) {
+        const T pn = c[2 * u] * x * p - c[2 * u + 1] * rr * pm1;
         pm1 = p;
         p = pn;
         emit(phc, out, pre, s * p, u);
       }
-      step(out, 4);
     }
-    for (; nn <= rem; ++nn) {
-      const T ca = cf[2 * nn], cb = cf[2 * nn + 1];
-      const T pn = ca * x * p - cb * rr * pm1;
-      pm1 = p;
-      p = pn;
-      emit(phc, out, pre, s * p, 0);
-      step(out, 1);
+    step(out, rem + 1 < kMfPairs ? rem + 1 : kMfPairs);
+    for (int n0 = kMfPairs; n0 <= rem; n0 += kMfPairs) {
+      load(cf + 2 * n0, c);
+#pragma unroll
+      for (int u = 0; u < kMfPairs; ++u) {
+        if (n0 + u <= rem) {
+          const T pn = c[2 * u] * x * p - c[2 * u + 1] * rr * pm1;
+          pm1 = p;
+          p = pn;
+          emit(phc, out, pre, s * p, u);
+        }
+      }
+      step(out, rem + 1 - n0 < kMfPairs ? rem + 1 - n0 : kMfPairs);
     }
   }
 };
 
 // Scaled coordinates of the lane's point (points past n repeat point n - 1: finite values; their V
 // entries are zero and their KV rows unwritten), with the same operations as the factor-evaluation
-// kernel.  fetch issues the loads of a chunk's coordinates, finish turns them into xt, r2 and t, so
-// the loads of the next chunk can be in flight during a whole chunk's work.
+// kernel.  fetch issues the loads of a chunk's coordinates into raw, finish turns raw into xt, r2
+// and t, so the loads of the next chunk can be in flight during a chunk's work.  The specialised
+// kernels fetch into rawn instead, at the start of a chunk's evaluation, and advance moves rawn to
+// raw at its end: no branch separates the two, so the registers need no copies that would wait for
+// the loads before the barrier.
 template <typename Tin, typename T, int D>
 struct MfPoint {
   T xt[D], r2[D], tt;
-  Tin raw[D];
+  Tin raw[D], rawn[D];
   __device__ __forceinline__ void fetch(const MfArgs& a, int64_t c0, int pt) {
     const Tin* __restrict__ x_soa = (const Tin*)a.x_soa;
     const int64_t i = (c0 + pt < a.n) ? c0 + pt : a.n - 1;
 #pragma unroll
     for (int j = 0; j < D; ++j) raw[j] = x_soa[(int64_t)j * a.ldx + i];
   }
+  __device__ __forceinline__ void fetch_next(const MfArgs& a, int64_t c0, int pt) {
+    const Tin* __restrict__ x_soa = (const Tin*)a.x_soa;
+    const int64_t i = (c0 + pt < a.n) ? c0 + pt : a.n - 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) rawn[j] = x_soa[(int64_t)j * a.ldx + i];
+  }
+  __device__ __forceinline__ void advance() {
+#pragma unroll
+    for (int j = 0; j < D; ++j) raw[j] = rawn[j];
+  }
   __device__ __forceinline__ void finish(const MfArgs& a) {
     {
 #pragma clang fp contract(off)
-      const GeoDev* geo = a.geo;
+      const HDF_MF_CONST GeoDev* geo = (const HDF_MF_CONST GeoDev*)a.geo;   // scalar loads
       const double Reff = geo->Reff;
       double rho2 = 0.0;
 #pragma unroll
@@ -268,17 +285,21 @@ __device__ __forceinline__ void mf_job_pass(const MfJob& jb, int kb, const T (&x
   }
   if constexpr (D >= 5) {
     // level d-3 with base b, indices [n_lo, n_hi]; below each, the d - 4 shared levels
+    // the pair of index n + 1 is loaded before the levels below index n run (one wait for both)
     const HDF_MF_CONST T* cf = chain + 2 * ((D - 4) * (K + 1) + jb.b) * (K + 1);
-    T pm1 = 0, p = cf[0];
+    T pm1 = 0, p = cf[0], ca = cf[2], cb = cf[3];
     for (int n = 0; n <= jb.n_hi; ++n) {
       if (n == 1) {
         pm1 = p;
-        p = cf[2] * xt[D - 4];
+        p = ca * xt[D - 4];
       } else if (n >= 2) {
-        const T ca = cf[2 * n], cb = cf[2 * n + 1];
         const T pn = ca * xt[D - 4] * p - cb * r2[D - 4] * pm1;
         pm1 = p;
         p = pn;
+      }
+      if (n >= 1) {
+        ca = cf[2 * n + 2];
+        cb = cf[2 * n + 3];
       }
       if (n >= jb.n_lo) {
         T x[NB];
@@ -297,14 +318,19 @@ __device__ __forceinline__ void mf_job_pass(const MfJob& jb, int kb, const T (&x
 // subtrees per 16-lane group (a three-subtree pass repeats one).
 template <typename T, int D>
 __device__ __forceinline__ void mf_jobs(const MfArgs& a, const T (&xt)[D], const T (&r2)[D],
-                                        const MfJob* __restrict__ jobs, int j_lo, int j_hi,
+                                        const HDF_MF_CONST MfJob* __restrict__ jobs, int j_lo, int j_hi,
                                         const int32_t* __restrict__ btab, const T* __restrict__ ptab,
                                         T* __restrict__ phc, int tid) {
   const HDF_MF_CONST T* __restrict__ chain = (const HDF_MF_CONST T*)a.chain;
   const int pt = tid & 15, grp = (tid & 63) >> 4;
   const int K = a.K;
   for (int j = j_lo; j < j_hi; ++j) {
-    const MfJob jb = jobs[j];                                  // uniform
+    MfJob jb;                                                  // uniform: scalar loads
+    {
+      const HDF_MF_CONST MfJob* jp = jobs + j;
+      jb.b = jp->b; jb.n_lo = jp->n_lo; jb.n_hi = jp->n_hi;
+      jb.off = jp->off; jb.task0 = jp->task0; jb.ntask = jp->ntask;
+    }
     const int per_grp = (jb.ntask + 3) >> 2;
     for (int kb = 0; kb < per_grp; kb += 4) {
       const int nb = per_grp - kb;
@@ -355,19 +381,25 @@ __device__ __forceinline__ void mf_radial(const MfArgs& a, T tt, const T* __rest
 
 // The evaluation of one chunk, software-pipelined: on entry pnt holds the chunk's points, its raw
 // coordinates the next chunk's (if any), and ptab_cur the chunk's subtree prefixes (written before
-// the last barrier).  The harmonics and radial functions go to phc and qc; then pnt advances to
-// the next chunk, the loads of the chunk after it are issued, and the next chunk's prefixes go to
-// ptab_next (read after the next barrier).  Run by the kMfThreads threads of the evaluating
-// wavefronts.
-template <typename Tin, typename T, int D>
+// the last barrier).  The harmonics and radial functions go to phc and qc; pnt advances to the next
+// chunk, the loads of the chunk after it (at c_next2) are issued, and the next chunk's prefixes go
+// to ptab_next (read after the next barrier).  With PIPE (the specialised kernels) the loads are
+// issued first, for every chunk (past the points they read point n - 1).  Run by the kMfThreads
+// threads of the evaluating wavefronts.
+template <typename Tin, typename T, int D, bool PIPE>
 __device__ __forceinline__ void mf_eval(const MfArgs& a, MfPoint<Tin, T, D>& pnt, bool has_next, int64_t c_next2,
                                         bool has_next2, int j_lo, int j_hi, const T* __restrict__ ctop,
                                         const T* __restrict__ ptab_cur, T* __restrict__ ptab_next,
                                         T* __restrict__ phc, T* __restrict__ qc, const T* __restrict__ qcoef,
                                         const int32_t* __restrict__ btab, int tid) {
-  mf_jobs<T, D>(a, pnt.xt, pnt.r2, a.jobs, j_lo, j_hi, btab, ptab_cur, phc, tid);
+  if constexpr (PIPE) pnt.fetch_next(a, c_next2, tid & 15);
+  mf_jobs<T, D>(a, pnt.xt, pnt.r2, (const HDF_MF_CONST MfJob*)a.jobs, j_lo, j_hi, btab, ptab_cur, phc, tid);
   mf_radial<T>(a, pnt.tt, qcoef, qc, tid);
-  if (has_next) {
+  if constexpr (PIPE) {
+    pnt.finish(a);
+    pnt.advance();
+    if (has_next) mf_prefix<T, D>(pnt.xt, pnt.r2, a.K, ctop, ptab_next, tid);
+  } else if (has_next) {
     pnt.finish(a);
     if (has_next2) pnt.fetch(a, c_next2, tid & 15);
     mf_prefix<T, D>(pnt.xt, pnt.r2, a.K, ctop, ptab_next, tid);
@@ -438,18 +470,28 @@ __device__ __forceinline__ void mf_mma1(typename MfMma<T>::V (&acc)[NS], const T
   }
 }
 
-// V^T of the chunk at c0, columns of tile ct (threads tid < 256 of the evaluating wavefronts).
+// V^T of a chunk, columns of tile ct (threads tid < 256 of the evaluating wavefronts): fetch loads
+// the thread's value of the chunk at c0 into a register one chunk ahead of its use, put writes it
+// to LDS (zero past the range or past m), so the load's latency is hidden behind a chunk's evaluation.
 template <typename Tin, typename T>
-__device__ __forceinline__ void mf_stage_v(const Tin* __restrict__ V, int64_t ldv, int64_t n, int64_t p_end, int m,
-                                           int ct, int64_t c0, T* __restrict__ vc, int tid) {
-  if (tid < 16 * kMfP) {
-    const int pp = tid >> 4, c = tid & 15, col = ct * 16 + c;
-    const int64_t i = c0 + pp;
-    const int64_t ic = i < n ? i : n - 1;
-    const Tin v = V[ic * ldv + (col < m ? col : 0)];
-    vc[c * kMfP + pp] = (i < p_end && col < m) ? (T)v : (T)0;
+struct MfVStage {
+  Tin v;
+  __device__ __forceinline__ void fetch(const Tin* __restrict__ V, int64_t ldv, int64_t n, int m, int ct, int64_t c0,
+                                        int tid) {
+    if (tid < 16 * kMfP) {
+      const int pp = tid >> 4, c = tid & 15, col = ct * 16 + c;
+      const int64_t i = c0 + pp;
+      const int64_t ic = i < n ? i : n - 1;
+      v = V[ic * ldv + (col < m ? col : 0)];
+    }
   }
-}
+  __device__ __forceinline__ void put(int64_t p_end, int m, int ct, int64_t c0, T* __restrict__ vc, int tid) const {
+    if (tid < 16 * kMfP) {
+      const int pp = tid >> 4, c = tid & 15, col = ct * 16 + c;
+      vc[c * kMfP + pp] = (c0 + pp < p_end && col < m) ? (T)v : (T)0;
+    }
+  }
+};
 
 // Pass 1.  Block (split, y): slot group y / cpl, column tile y % cpl.  Each contracting wavefront
 // keeps its slots' accumulator tiles for the whole split.
@@ -484,10 +526,20 @@ k_mf_t(MfArgs a, MfLayout lay, const MfSlot1* __restrict__ slots, const int32_t*
   mf_stage_tables<T>(a, D, rows, n_rows, rtab, phc, MfMode<SPEC>::nbuf, lay.phc_len, qcoef, ctop, btab, tid,
                      MfMode<SPEC>::threads);
   MfPoint<Tin, T, D> pnt;
+  MfVStage<Tin, T> vs;
   if (evalw) {
-    pnt.fetch(a, p_begin, etid & 15);
-    pnt.finish(a);
-    if (nch > 1) pnt.fetch(a, p_begin + kMfP, etid & 15);
+    if constexpr (SPEC) {
+      pnt.fetch_next(a, p_begin, etid & 15);
+      pnt.advance();
+      pnt.finish(a);
+      pnt.fetch_next(a, p_begin + kMfP, etid & 15);
+      pnt.advance();
+    } else {
+      pnt.fetch(a, p_begin, etid & 15);
+      pnt.finish(a);
+      if (nch > 1) pnt.fetch(a, p_begin + kMfP, etid & 15);
+    }
+    if constexpr (SPEC) vs.fetch(V, ldv, a.n, m, ct, p_begin, etid);
   }
   __syncthreads();                                // tables staged
   const int s_lo = slot_off[gi * (kMfWaves + 1) + w8];
@@ -500,18 +552,19 @@ k_mf_t(MfArgs a, MfLayout lay, const MfSlot1* __restrict__ slots, const int32_t*
     // iteration it: the evaluating wavefronts fill buffer it & 1 with chunk it while the contracting
     // ones read chunk it - 1 from the other; nch + 1 barriers in either role
     if (evalw) {
+      // no branch inside the loop body, so the prefetched registers need no copies at its end
       mf_prefix<T, D>(pnt.xt, pnt.r2, a.K, ctop, ptab, etid);
-      for (int it = 0; it <= nch; ++it) {
+      for (int it = 0; it < nch; ++it) {
         HDF_MF_ROLE_BARRIER();
-        if (it < nch) {
-          const int b = it & 1;
-          const int64_t c0 = p_begin + (int64_t)it * kMfP;
-          mf_eval<Tin, T, D>(a, pnt, it + 1 < nch, c0 + 2 * kMfP, it + 2 < nch, j_lo, j_hi, ctop,
-                             ptab + b * lay.ptab_len, ptab + (b ^ 1) * lay.ptab_len, phc + b * lay.phc_len,
-                             qc + b * lay.qc_len, qcoef, btab, etid);
-          mf_stage_v<Tin, T>(V, ldv, a.n, p_end, m, ct, c0, vc + b * lay.aux_len, etid);
-        }
+        const int b = it & 1;
+        const int64_t c0 = p_begin + (int64_t)it * kMfP;
+        mf_eval<Tin, T, D, true>(a, pnt, it + 1 < nch, c0 + 2 * kMfP, it + 2 < nch, j_lo, j_hi, ctop,
+                                 ptab + b * lay.ptab_len, ptab + (b ^ 1) * lay.ptab_len, phc + b * lay.phc_len,
+                                 qc + b * lay.qc_len, qcoef, btab, etid);
+        vs.put(p_end, m, ct, c0, vc + b * lay.aux_len, etid);
+        vs.fetch(V, ldv, a.n, m, ct, c0 + kMfP, etid);        // past the points: row n - 1, unused
       }
+      HDF_MF_ROLE_BARRIER();
     } else {
       for (int it = 0; it <= nch; ++it) {
         HDF_MF_ROLE_BARRIER();
@@ -527,10 +580,11 @@ k_mf_t(MfArgs a, MfLayout lay, const MfSlot1* __restrict__ slots, const int32_t*
     for (int it = 0; it < nch; ++it) {
       const int64_t c0 = p_begin + (int64_t)it * kMfP;
       __syncthreads();                            // the previous chunk's reads are done
-      mf_eval<Tin, T, D>(a, pnt, it + 1 < nch, c0 + 2 * kMfP, it + 2 < nch, j_lo, j_hi, ctop,
-                         ptab + (it & 1) * lay.ptab_len, ptab + ((it & 1) ^ 1) * lay.ptab_len, phc, qc, qcoef,
-                         btab, tid);
-      mf_stage_v<Tin, T>(V, ldv, a.n, p_end, m, ct, c0, vc, tid);
+      mf_eval<Tin, T, D, false>(a, pnt, it + 1 < nch, c0 + 2 * kMfP, it + 2 < nch, j_lo, j_hi, ctop,
+                                ptab + (it & 1) * lay.ptab_len, ptab + ((it & 1) ^ 1) * lay.ptab_len, phc, qc,
+                                qcoef, btab, tid);
+      vs.fetch(V, ldv, a.n, m, ct, c0, tid);
+      vs.put(p_end, m, ct, c0, vc, tid);
       __syncthreads();
       mf_mma1<T, NS>(acc, phc, qc, vc, rtab, s_lo, ns, r, q);
     }
@@ -628,9 +682,17 @@ k_mf_n(MfArgs a, MfLayout lay, const MfSlot2* __restrict__ slots, const int32_t*
                      MfMode<SPEC>::threads);
   MfPoint<Tin, T, D> pnt;
   if (evalw) {
-    pnt.fetch(a, p_begin, etid & 15);
-    pnt.finish(a);
-    if (nch > 1) pnt.fetch(a, p_begin + kMfP, etid & 15);
+    if constexpr (SPEC) {
+      pnt.fetch_next(a, p_begin, etid & 15);
+      pnt.advance();
+      pnt.finish(a);
+      pnt.fetch_next(a, p_begin + kMfP, etid & 15);
+      pnt.advance();
+    } else {
+      pnt.fetch(a, p_begin, etid & 15);
+      pnt.finish(a);
+      if (nch > 1) pnt.fetch(a, p_begin + kMfP, etid & 15);
+    }
   }
   __syncthreads();                                // tables staged
   const int s_lo = slot_off[gi * (kMfWaves + 1) + w8];
@@ -651,15 +713,15 @@ k_mf_n(MfArgs a, MfLayout lay, const MfSlot2* __restrict__ slots, const int32_t*
     // in either role
     if (evalw) {
       mf_prefix<T, D>(pnt.xt, pnt.r2, a.K, ctop, ptab, etid);
-      for (int it = 0; it <= nch + 1; ++it) {
+      for (int it = 0; it < nch; ++it) {
         HDF_MF_ROLE_BARRIER();
-        if (it < nch) {
-          const int b = it & 1;
-          mf_eval<Tin, T, D>(a, pnt, it + 1 < nch, p_begin + (int64_t)(it + 2) * kMfP, it + 2 < nch, j_lo, j_hi,
-                             ctop, ptab + b * lay.ptab_len, ptab + (b ^ 1) * lay.ptab_len, phc + b * lay.phc_len,
-                             qc + b * lay.qc_len, qcoef, btab, etid);
-        }
+        const int b = it & 1;
+        mf_eval<Tin, T, D, true>(a, pnt, it + 1 < nch, p_begin + (int64_t)(it + 2) * kMfP, it + 2 < nch, j_lo,
+                                 j_hi, ctop, ptab + b * lay.ptab_len, ptab + (b ^ 1) * lay.ptab_len,
+                                 phc + b * lay.phc_len, qc + b * lay.qc_len, qcoef, btab, etid);
       }
+      HDF_MF_ROLE_BARRIER();
+      HDF_MF_ROLE_BARRIER();
     } else {
       for (int it = 0; it <= nch + 1; ++it) {
         HDF_MF_ROLE_BARRIER();
@@ -678,7 +740,7 @@ k_mf_n(MfArgs a, MfLayout lay, const MfSlot2* __restrict__ slots, const int32_t*
     for (int it = 0; it < nch; ++it) {
       const int64_t c0 = p_begin + (int64_t)it * kMfP;
       __syncthreads();                            // the previous chunk's reads are done
-      mf_eval<Tin, T, D>(a, pnt, it + 1 < nch, c0 + 2 * kMfP, it + 2 < nch, j_lo, j_hi, ctop,
+      mf_eval<Tin, T, D, false>(a, pnt, it + 1 < nch, c0 + 2 * kMfP, it + 2 < nch, j_lo, j_hi, ctop,
                          ptab + (it & 1) * lay.ptab_len, ptab + ((it & 1) ^ 1) * lay.ptab_len, phc, qc, qcoef,
                          btab, tid);
       __syncthreads();
