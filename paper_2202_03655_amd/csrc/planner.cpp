@@ -452,21 +452,26 @@ void chain_coeffs(int d, int K, ChainCoeffs& out) {
   const size_t sz = (size_t)(d - 2) * (K + 1) * (K + 1);
   out.A.assign(sz, 0.0);
   out.B.assign(sz, 0.0);
+  std::vector<ld> logh((size_t)std::max(2, K + 1));
+  // lgamma at the integers the terms below take (n + 2 lam and n + 1 are whole numbers)
+  std::vector<ld> lg_int((size_t)(3 * K + d + 4));
+  for (size_t m = 1; m < lg_int.size(); ++m) lg_int[m] = lgammal((ld)m);
   for (int level = 1; level <= d - 2; ++level) {
     for (int b = 0; b <= K; ++b) {
+      const int two_lam = 2 * b + d - level - 1;
       const ld lam = b + (ld)(d - level - 1) / 2;
       // log h_n^lam = log(pi) + (1 - 2 lam) log 2 + lgamma(n + 2 lam) - lgamma(n + 1)
-      //               - log(n + lam) - 2 lgamma(lam)
-      auto logh = [&](int n) {
-        return logl(kPiL) + (1 - 2 * lam) * logl(2.0L) + lgammal(n + 2 * lam) - lgammal(n + 1.0L) -
-               logl(n + lam) - 2 * lgammal(lam);
-      };
+      //               - log(n + lam) - 2 lgamma(lam), summed in this order; each log h_n once
+      // (the steps below read three consecutive ones)
+      const ld head = logl(kPiL) + (1 - 2 * lam) * logl(2.0L), tail = 2 * lgammal(lam);
+      const int nh = std::max(2, K - b + 1);
+      for (int n = 0; n < nh; ++n) logh[n] = head + lg_int[n + two_lam] - lg_int[n + 1] - logl(n + lam) - tail;
       const size_t base = out.idx(level, b, 0);
-      out.A[base + 0] = (double)expl(-0.5L * logh(0));                 // c0
-      if (b < K) out.A[base + 1] = (double)(2 * lam * expl(-0.5L * logh(1)));   // c1 (rows of length >= 2)
+      out.A[base + 0] = (double)expl(-0.5L * logh[0]);                 // c0
+      if (b < K) out.A[base + 1] = (double)(2 * lam * expl(-0.5L * logh[1]));   // c1 (rows of length >= 2)
       for (int n = 1; n + 1 <= K - b; ++n) {
-        const ld an = 2 * (n + lam) / (n + 1) * expl(0.5L * (logh(n) - logh(n + 1)));
-        const ld bn = (n + 2 * lam - 1) / (n + 1) * expl(0.5L * (logh(n - 1) - logh(n + 1)));
+        const ld an = 2 * (n + lam) / (n + 1) * expl(0.5L * (logh[n] - logh[n + 1]));
+        const ld bn = (n + 2 * lam - 1) / (n + 1) * expl(0.5L * (logh[n - 1] - logh[n + 1]));
         out.A[base + n + 1] = (double)an;   // step producing P_{n+1}
         out.B[base + n + 1] = (double)bn;
       }
